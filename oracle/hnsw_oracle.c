@@ -1,0 +1,685 @@
+/*
+ * CPU oracle of Hierarchical NSW (Malkov & Yashunin, "Efficient and robust
+ * approximate nearest neighbor search using Hierarchical Navigable Small World
+ * graphs", arXiv:1603.09320).
+ *
+ * TEST INFRASTRUCTURE ONLY.  This file is the plain, slow reference that the
+ * GPU path is checked against.  Only the test suite, the smoke check and the
+ * CPU-baseline leg of the benchmark may load it; the product path never does.
+ * It shares no code, header or table with the GPU library.
+ *
+ * What it implements, each in the paper's order and notation:
+ *   - level draw of Alg. 1 (its line computing l = floor(-ln(unif(0..1)) * mL)),
+ *   - SEARCH-LAYER (Alg. 2) with an exact visited set and two binary heaps
+ *     (C: nearest first, W: furthest first),
+ *   - SELECT-NEIGHBORS-SIMPLE (Alg. 3) and SELECT-NEIGHBORS-HEURISTIC (Alg. 4),
+ *     both flags of Alg. 4 included,
+ *   - INSERT (Alg. 1), including the connection shrink,
+ *   - K-NN-SEARCH (Alg. 5),
+ *   - brute-force K-NN, the plain definition of the problem (Sec. 1).
+ *
+ * Readings taken where the paper is silent (each is listed with its reason in
+ * the design notes of the repository):
+ *   - Distances: squared L2, or 1 - <q,x> for the inner-product metric (Sec. 5.2
+ *     treats cosine as L2 after normalisation).  The sum is accumulated in
+ *     double precision; the value that takes part in every comparison is that
+ *     sum rounded once to float (the precision of the paper's implementation
+ *     and of the GPU kernel), so both sides take each decision in fp32.
+ *   - Ties: every "nearest"/"furthest" compares the key (distance, id) in
+ *     lexicographic order, a strict total order.
+ *   - unif(0..1): U = (r + 1) * 2^-53 with r the top 53 bits of
+ *     splitmix64(seed XOR i), so U lies in (0, 1] and ln U is finite.
+ *   - Alg. 4's keep-test: candidate e is kept iff dist(e, q) < dist(e, r) for
+ *     every r already kept (the rule stated in Sec. 3; the printed line is
+ *     garbled).
+ *   - Alg. 1: the first element becomes the entry point with no links; a new
+ *     element takes M links on every layer it belongs to, layer 0 included;
+ *     all of W is the entry set of the next layer; elements are inserted in
+ *     id order.
+ *   - Alg. 5: ef below K is raised to K; fewer than K results are padded with
+ *     id -1 and distance +inf; results are sorted by (distance, id).
+ */
+#include <math.h>
+#include <pthread.h>
+#include <stdint.h>
+#include <stdio.h>
+#include <stdlib.h>
+#include <string.h>
+
+#define OR_EXPORT __attribute__((visibility("default")))
+#define OR_NONE 0xFFFFFFFFu
+
+enum { OR_L2 = 0, OR_IP = 1 };
+
+typedef struct {
+    float d;
+    uint32_t id;
+} item;
+
+/* key(a) < key(b) in the (distance, id) order. */
+static int key_less(item a, item b) { return a.d < b.d || (a.d == b.d && a.id < b.id); }
+
+/* ---------------------------------------------------------------- distance */
+
+static double dist64(int metric, const float *a, const float *b, uint32_t dim) {
+    double s = 0.0;
+    if (metric == OR_L2) {
+        for (uint32_t j = 0; j < dim; ++j) {
+            double t = (double)a[j] - (double)b[j];
+            s += t * t;
+        }
+        return s;
+    }
+    for (uint32_t j = 0; j < dim; ++j) s += (double)a[j] * (double)b[j];
+    return 1.0 - s;
+}
+
+/* --------------------------------------------------------------- the graph */
+
+typedef struct {
+    uint32_t n, dim, metric;
+    uint32_t M, Mmax, Mmax0, efC;
+    double mL;
+    uint64_t seed;
+    int heuristic, extend, keep_pruned;
+    const float *X;    /* [n][dim], borrowed from the caller                */
+    uint8_t *level;    /* [n]                                               */
+    uint32_t *cnt0;    /* [n]          layer-0 list lengths                 */
+    uint32_t *adj0;    /* [n][Mmax0+1] layer-0 lists                        */
+    int64_t *uoff;     /* [n]          row of layer 1 in the upper store, -1 */
+    uint32_t *ucnt;    /* [rows]                                            */
+    uint32_t *uadj;    /* [rows][Mmax+1]                                    */
+    uint64_t rows;
+    uint32_t n_inserted;
+    int64_t entry;     /* entry point, -1 while empty                       */
+    int max_level;     /* L, the level of the entry point                   */
+    struct searcher *ws; /* workspace used by INSERT                         */
+} graph;
+
+static uint32_t *nbr(const graph *g, uint32_t e, int lc, uint32_t **cnt) {
+    if (lc == 0) {
+        *cnt = &g->cnt0[e];
+        return g->adj0 + (uint64_t)e * (g->Mmax0 + 1);
+    }
+    uint64_t row = (uint64_t)g->uoff[e] + (uint64_t)(lc - 1);
+    *cnt = &g->ucnt[row];
+    return g->uadj + row * (g->Mmax + 1);
+}
+
+static float dkey(const graph *g, const float *q, uint32_t e) {
+    return (float)dist64((int)g->metric, q, g->X + (uint64_t)e * g->dim, g->dim);
+}
+
+/* ----------------------------------------------------------- binary heaps */
+
+typedef struct {
+    item *a;
+    size_t n, cap;
+    int is_max; /* 1: furthest on top (W), 0: nearest on top (C) */
+} heap;
+
+static int h_above(const heap *h, item x, item y) { return h->is_max ? key_less(y, x) : key_less(x, y); }
+
+static void h_reserve(heap *h, size_t cap) {
+    if (cap <= h->cap) return;
+    size_t c = h->cap ? h->cap : 64;
+    while (c < cap) c *= 2;
+    h->a = (item *)realloc(h->a, c * sizeof(item));
+    if (!h->a) { fprintf(stderr, "oracle: out of memory\n"); abort(); }
+    h->cap = c;
+}
+
+static void h_push(heap *h, item x) {
+    h_reserve(h, h->n + 1);
+    size_t i = h->n++;
+    while (i > 0) {
+        size_t p = (i - 1) / 2;
+        if (!h_above(h, x, h->a[p])) break;
+        h->a[i] = h->a[p];
+        i = p;
+    }
+    h->a[i] = x;
+}
+
+static item h_pop(heap *h) {
+    item top = h->a[0];
+    item x = h->a[--h->n];
+    size_t i = 0;
+    for (;;) {
+        size_t l = 2 * i + 1, r = l + 1, b = i;
+        item bx = x;
+        if (l < h->n && h_above(h, h->a[l], bx)) { b = l; bx = h->a[l]; }
+        if (r < h->n && h_above(h, h->a[r], bx)) { b = r; bx = h->a[r]; }
+        if (b == i) break;
+        h->a[i] = h->a[b];
+        i = b;
+    }
+    if (h->n) h->a[i] = x;
+    return top;
+}
+
+/* ------------------------------------------------------ search workspace */
+
+typedef struct searcher {
+    uint32_t *vis; /* visited stamps, one per element                   */
+    uint32_t gen;
+    uint32_t n;
+    heap C, W;
+    uint64_t n_dist[64], n_exp[64]; /* per-layer counters of the last search */
+} searcher;
+
+static searcher *ws_new(uint32_t n) {
+    searcher *s = (searcher *)calloc(1, sizeof(searcher));
+    s->vis = (uint32_t *)calloc(n ? n : 1, sizeof(uint32_t));
+    s->n = n;
+    s->W.is_max = 1;
+    return s;
+}
+
+static void ws_free(searcher *s) {
+    if (!s) return;
+    free(s->vis);
+    free(s->C.a);
+    free(s->W.a);
+    free(s);
+}
+
+static uint32_t next_gen(searcher *s) {
+    if (++s->gen == 0) {
+        memset(s->vis, 0, (size_t)s->n * sizeof(uint32_t));
+        s->gen = 1;
+    }
+    return s->gen;
+}
+
+/*
+ * SEARCH-LAYER (Alg. 2).  On return s->W holds the result (heap order).
+ * ep: enter points (ids), q: query vector.
+ */
+static void search_layer(const graph *g, searcher *s, const float *q, const uint32_t *ep, size_t n_ep,
+                         uint32_t ef, int lc) {
+    uint32_t gen = next_gen(s);
+    s->C.n = 0;
+    s->W.n = 0;
+    for (size_t i = 0; i < n_ep; ++i) {
+        if (s->vis[ep[i]] == gen) continue;
+        s->vis[ep[i]] = gen;
+        item it = {dkey(g, q, ep[i]), ep[i]};
+        s->n_dist[lc]++;
+        h_push(&s->C, it);
+        h_push(&s->W, it);
+    }
+    while (s->C.n > 0) {
+        item c = h_pop(&s->C);        /* nearest element of C            */
+        item f = s->W.a[0];           /* furthest element of W           */
+        if (key_less(f, c)) break;    /* all elements of W are evaluated */
+        s->n_exp[lc]++;
+        uint32_t *cnt;
+        const uint32_t *nb = nbr(g, c.id, lc, &cnt);
+        uint32_t m = *cnt;
+        for (uint32_t k = 0; k < m; ++k) {
+            uint32_t e = nb[k];
+            if (s->vis[e] == gen) continue;
+            s->vis[e] = gen;
+            f = s->W.a[0];
+            item it = {dkey(g, q, e), e};
+            s->n_dist[lc]++;
+            if (key_less(it, f) || s->W.n < ef) {
+                h_push(&s->C, it);
+                h_push(&s->W, it);
+                if (s->W.n > ef) h_pop(&s->W);
+            }
+        }
+    }
+}
+
+static int cmp_item(const void *pa, const void *pb) {
+    item a = *(const item *)pa, b = *(const item *)pb;
+    return key_less(a, b) ? -1 : (key_less(b, a) ? 1 : 0);
+}
+
+/* ------------------------------------------------------ neighbor selection */
+
+/* SELECT-NEIGHBORS-SIMPLE (Alg. 3): the M nearest of cand (distances to the base). */
+static size_t select_simple(item *cand, size_t n, uint32_t M, uint32_t *out) {
+    qsort(cand, n, sizeof(item), cmp_item);
+    size_t m = n < M ? n : M;
+    for (size_t i = 0; i < m; ++i) out[i] = cand[i].id;
+    return m;
+}
+
+/*
+ * SELECT-NEIGHBORS-HEURISTIC (Alg. 4).  base: vector of the base element,
+ * base_id: its id (excluded when extending), cand: candidates with distances
+ * to the base.
+ */
+static size_t select_heuristic(const graph *g, searcher *s, const float *base, uint32_t base_id, const item *cand,
+                               size_t n, uint32_t M, int lc, int extend, int keep_pruned, uint32_t *out) {
+    heap Wq = {0}, Wd = {0};
+    for (size_t i = 0; i < n; ++i) h_push(&Wq, cand[i]);
+    if (extend) {
+        uint32_t gen = next_gen(s);
+        for (size_t i = 0; i < n; ++i) s->vis[cand[i].id] = gen;
+        s->vis[base_id] = gen;
+        for (size_t i = 0; i < n; ++i) {
+            uint32_t *cnt;
+            const uint32_t *nb = nbr(g, cand[i].id, lc, &cnt);
+            for (uint32_t k = 0; k < *cnt; ++k) {
+                uint32_t e = nb[k];
+                if (s->vis[e] == gen) continue;
+                s->vis[e] = gen;
+                item it = {dkey(g, base, e), e};
+                h_push(&Wq, it);
+            }
+        }
+    }
+    size_t r = 0;
+    while (Wq.n > 0 && r < M) {
+        item e = h_pop(&Wq);
+        const float *xe = g->X + (uint64_t)e.id * g->dim;
+        int keep = 1;
+        for (size_t j = 0; j < r; ++j) {
+            float der = (float)dist64((int)g->metric, xe, g->X + (uint64_t)out[j] * g->dim, g->dim);
+            if (!(e.d < der)) { keep = 0; break; }
+        }
+        if (keep) out[r++] = e.id;
+        else h_push(&Wd, e);
+    }
+    if (keep_pruned)
+        while (Wd.n > 0 && r < M) out[r++] = h_pop(&Wd).id;
+    free(Wq.a);
+    free(Wd.a);
+    return r;
+}
+
+static size_t select_neighbors(const graph *g, searcher *s, const float *base, uint32_t base_id, item *cand,
+                               size_t n, uint32_t M, int lc, uint32_t *out) {
+    if (g->heuristic) return select_heuristic(g, s, base, base_id, cand, n, M, lc, g->extend, g->keep_pruned, out);
+    return select_simple(cand, n, M, out);
+}
+
+/* ---------------------------------------------------------------- levels */
+
+static uint64_t splitmix64(uint64_t x) {
+    x += 0x9E3779B97F4A7C15ull;
+    x = (x ^ (x >> 30)) * 0xBF58476D1CE4E5B9ull;
+    x = (x ^ (x >> 27)) * 0x94D049BB133111EBull;
+    return x ^ (x >> 31);
+}
+
+/* The level line of Alg. 1: l = floor(-ln(unif(0..1)) * mL). */
+OR_EXPORT void or_levels(uint64_t seed, uint32_t n, double mL, uint8_t *out) {
+    for (uint32_t i = 0; i < n; ++i) {
+        uint64_t r = splitmix64(seed ^ (uint64_t)i) >> 11;
+        double U = (double)(r + 1) * 0x1.0p-53;
+        double l = floor(-log(U) * mL);
+        if (l > 255.0) l = 255.0;
+        out[i] = (uint8_t)l;
+    }
+}
+
+/* ---------------------------------------------------------------- INSERT */
+
+static void alloc_lists(graph *g) {
+    g->cnt0 = (uint32_t *)calloc(g->n ? g->n : 1, sizeof(uint32_t));
+    g->adj0 = (uint32_t *)malloc(((size_t)g->n * (g->Mmax0 + 1) + 1) * sizeof(uint32_t));
+    g->uoff = (int64_t *)malloc(((size_t)g->n + 1) * sizeof(int64_t));
+    uint64_t rows = 0;
+    for (uint32_t i = 0; i < g->n; ++i) {
+        g->uoff[i] = g->level[i] ? (int64_t)rows : -1;
+        rows += g->level[i];
+    }
+    g->rows = rows;
+    g->ucnt = (uint32_t *)calloc(rows ? rows : 1, sizeof(uint32_t));
+    g->uadj = (uint32_t *)malloc(((size_t)rows * (g->Mmax + 1) + 1) * sizeof(uint32_t));
+    if (!g->cnt0 || !g->adj0 || !g->uoff || !g->ucnt || !g->uadj) {
+        fprintf(stderr, "oracle: out of memory\n");
+        abort();
+    }
+}
+
+OR_EXPORT graph *or_create(const float *X, uint32_t n, uint32_t dim, uint32_t metric, uint32_t M, uint32_t Mmax,
+                           uint32_t Mmax0, uint32_t efC, double mL, uint64_t seed, int heuristic, int extend,
+                           int keep_pruned) {
+    graph *g = (graph *)calloc(1, sizeof(graph));
+    g->n = n; g->dim = dim; g->metric = metric;
+    g->M = M; g->Mmax = Mmax; g->Mmax0 = Mmax0; g->efC = efC;
+    g->mL = mL; g->seed = seed;
+    g->heuristic = heuristic; g->extend = extend; g->keep_pruned = keep_pruned;
+    g->X = X;
+    g->level = (uint8_t *)malloc(n ? n : 1);
+    or_levels(seed, n, mL, g->level);
+    alloc_lists(g);
+    g->entry = -1;
+    g->max_level = -1;
+    g->ws = ws_new(n);
+    return g;
+}
+
+/* INSERT (Alg. 1) of element q (its id); elements must be inserted in id order. */
+static void insert(graph *g, uint32_t qid) {
+    searcher *s = g->ws;
+    const float *q = g->X + (uint64_t)qid * g->dim;
+    int l = g->level[qid];
+    if (g->entry < 0) {               /* first element: entry point, no links */
+        g->entry = qid;
+        g->max_level = l;
+        g->n_inserted++;
+        return;
+    }
+    int L = g->max_level;
+    uint32_t *ep = (uint32_t *)malloc(sizeof(uint32_t) * ((size_t)g->efC + 1));
+    size_t n_ep = 1;
+    ep[0] = (uint32_t)g->entry;
+    for (int lc = L; lc > l; --lc) {  /* greedy phase, ef = 1 */
+        search_layer(g, s, q, ep, n_ep, 1, lc);
+        item best = s->W.a[0];
+        for (size_t i = 1; i < s->W.n; ++i)
+            if (key_less(s->W.a[i], best)) best = s->W.a[i];
+        ep[0] = best.id;
+        n_ep = 1;
+    }
+    uint32_t Mcap = g->Mmax0 > g->Mmax ? g->Mmax0 : g->Mmax;
+    item *cand = (item *)malloc(sizeof(item) * ((size_t)g->efC + Mcap + 2));
+    uint32_t *sel = (uint32_t *)malloc(sizeof(uint32_t) * ((size_t)g->efC + Mcap + 2));
+    uint32_t *sel2 = (uint32_t *)malloc(sizeof(uint32_t) * ((size_t)Mcap + 2));
+    for (int lc = (L < l ? L : l); lc >= 0; --lc) {
+        search_layer(g, s, q, ep, n_ep, g->efC, lc);
+        size_t nW = s->W.n;
+        for (size_t i = 0; i < nW; ++i) cand[i] = s->W.a[i];
+        /* W is also the next layer's entry set */
+        for (size_t i = 0; i < nW; ++i) ep[i] = cand[i].id;
+        n_ep = nW;
+        size_t m = select_neighbors(g, s, q, qid, cand, nW, g->M, lc, sel);
+        uint32_t *cq;
+        uint32_t *lq = nbr(g, qid, lc, &cq);
+        for (size_t i = 0; i < m; ++i) lq[i] = sel[i];
+        *cq = (uint32_t)m;
+        uint32_t cap = lc == 0 ? g->Mmax0 : g->Mmax;
+        for (size_t i = 0; i < m; ++i) {     /* the reverse links */
+            uint32_t *ce;
+            uint32_t *le = nbr(g, sel[i], lc, &ce);
+            le[(*ce)++] = qid;
+        }
+        for (size_t i = 0; i < m; ++i) {     /* shrink overflowing lists */
+            uint32_t e = sel[i];
+            uint32_t *ce;
+            uint32_t *le = nbr(g, e, lc, &ce);
+            if (*ce <= cap) continue;
+            const float *xe = g->X + (uint64_t)e * g->dim;
+            for (uint32_t k = 0; k < *ce; ++k) {
+                cand[k].id = le[k];
+                cand[k].d = dkey(g, xe, le[k]);
+            }
+            size_t mm = select_neighbors(g, s, xe, e, cand, *ce, cap, lc, sel2);
+            for (size_t k = 0; k < mm; ++k) le[k] = sel2[k];
+            *ce = (uint32_t)mm;
+        }
+        /* select_neighbors may have reordered cand; ep was saved before. */
+    }
+    if (l > L) {
+        g->entry = qid;
+        g->max_level = l;
+    }
+    g->n_inserted++;
+    free(ep);
+    free(cand);
+    free(sel);
+    free(sel2);
+}
+
+/* Insert elements [start, end) in id order; returns the number inserted so far. */
+OR_EXPORT uint32_t or_insert_range(graph *g, uint32_t start, uint32_t end) {
+    if (start != g->n_inserted || end > g->n || start > end) return (uint32_t)-1;
+    for (uint32_t i = start; i < end; ++i) insert(g, i);
+    return g->n_inserted;
+}
+
+OR_EXPORT void or_free(graph *g) {
+    if (!g) return;
+    free(g->level); free(g->cnt0); free(g->adj0); free(g->uoff); free(g->ucnt); free(g->uadj);
+    ws_free(g->ws);
+    free(g);
+}
+
+/* -------------------------------------------------------- K-NN-SEARCH */
+
+/* K-NN-SEARCH (Alg. 5) of one query using workspace s. */
+static void knn_search(const graph *g, searcher *s, const float *q, uint32_t K, uint32_t ef, int32_t *ids,
+                       float *dists, uint64_t *counters) {
+    memset(s->n_dist, 0, sizeof(s->n_dist));
+    memset(s->n_exp, 0, sizeof(s->n_exp));
+    uint32_t efe = ef < K ? K : ef;
+    size_t nres = 0;
+    if (g->entry >= 0) {
+        uint32_t ep = (uint32_t)g->entry;
+        for (int lc = g->max_level; lc >= 1; --lc) {
+            search_layer(g, s, q, &ep, 1, 1, lc);
+            item best = s->W.a[0];
+            for (size_t i = 1; i < s->W.n; ++i)
+                if (key_less(s->W.a[i], best)) best = s->W.a[i];
+            ep = best.id;
+        }
+        search_layer(g, s, q, &ep, 1, efe, 0);
+        nres = s->W.n;
+        qsort(s->W.a, nres, sizeof(item), cmp_item);
+    }
+    for (uint32_t k = 0; k < K; ++k) {
+        if (k < nres) { ids[k] = (int32_t)s->W.a[k].id; dists[k] = s->W.a[k].d; }
+        else { ids[k] = -1; dists[k] = INFINITY; }
+    }
+    if (counters) {
+        uint64_t dt = 0, et = 0;
+        for (int l = 0; l < 64; ++l) { dt += s->n_dist[l]; et += s->n_exp[l]; }
+        counters[0] = dt;             /* distance evaluations, all layers */
+        counters[1] = et;             /* expansions, all layers            */
+        counters[2] = s->n_dist[0];   /* distance evaluations, layer 0     */
+        counters[3] = s->n_exp[0];    /* expansions, layer 0               */
+    }
+}
+
+typedef struct {
+    const graph *g;
+    const float *Q;
+    uint32_t K, ef, lo, hi;
+    int32_t *ids;
+    float *dists;
+    uint64_t *counters;
+} search_job;
+
+static void *search_worker(void *p) {
+    search_job *j = (search_job *)p;
+    searcher *s = ws_new(j->g->n);
+    for (uint32_t i = j->lo; i < j->hi; ++i)
+        knn_search(j->g, s, j->Q + (uint64_t)i * j->g->dim, j->K, j->ef, j->ids + (uint64_t)i * j->K,
+                   j->dists + (uint64_t)i * j->K, j->counters ? j->counters + 4ull * i : NULL);
+    ws_free(s);
+    return NULL;
+}
+
+/* Batched K-NN-SEARCH: queries are independent, split over nthreads threads. */
+OR_EXPORT void or_search(const graph *g, const float *Q, uint32_t nq, uint32_t K, uint32_t ef, int32_t *ids,
+                         float *dists, uint64_t *counters, int nthreads) {
+    if (nthreads < 1) nthreads = 1;
+    if ((uint32_t)nthreads > nq) nthreads = nq ? (int)nq : 1;
+    pthread_t th[256];
+    search_job jobs[256];
+    if (nthreads > 256) nthreads = 256;
+    for (int t = 0; t < nthreads; ++t) {
+        jobs[t] = (search_job){g, Q, K, ef, (uint32_t)((uint64_t)nq * t / nthreads),
+                               (uint32_t)((uint64_t)nq * (t + 1) / nthreads), ids, dists, counters};
+        if (nthreads == 1) search_worker(&jobs[t]);
+        else pthread_create(&th[t], NULL, search_worker, &jobs[t]);
+    }
+    if (nthreads > 1)
+        for (int t = 0; t < nthreads; ++t) pthread_join(th[t], NULL);
+}
+
+/* One SEARCH-LAYER call from explicit enter points; W is returned sorted. */
+OR_EXPORT uint32_t or_search_layer(const graph *g, const float *q, const uint32_t *ep, uint32_t n_ep, uint32_t ef,
+                                   int lc, int32_t *ids, float *dists, uint64_t *n_dist) {
+    searcher *s = ws_new(g->n);
+    memset(s->n_dist, 0, sizeof(s->n_dist));
+    search_layer(g, s, q, ep, n_ep, ef, lc);
+    qsort(s->W.a, s->W.n, sizeof(item), cmp_item);
+    uint32_t m = (uint32_t)s->W.n;
+    for (uint32_t i = 0; i < m; ++i) { ids[i] = (int32_t)s->W.a[i].id; dists[i] = s->W.a[i].d; }
+    if (n_dist) *n_dist = s->n_dist[lc];
+    ws_free(s);
+    return m;
+}
+
+/* Alg. 4 on an explicit candidate list, against the graph's vectors and layer lc. */
+OR_EXPORT uint32_t or_select_heuristic(const graph *g, uint32_t base_id, const uint32_t *cand_ids, uint32_t n,
+                                       uint32_t M, int lc, int extend, int keep_pruned, uint32_t *out) {
+    searcher *s = ws_new(g->n);
+    const float *base = g->X + (uint64_t)base_id * g->dim;
+    item *c = (item *)malloc(sizeof(item) * (n + 1));
+    for (uint32_t i = 0; i < n; ++i) c[i] = (item){dkey(g, base, cand_ids[i]), cand_ids[i]};
+    size_t m = select_heuristic(g, s, base, base_id, c, n, M, lc, extend, keep_pruned, out);
+    free(c);
+    ws_free(s);
+    return (uint32_t)m;
+}
+
+/* ---------------------------------------------------------- brute force */
+
+typedef struct {
+    const float *X, *Q;
+    uint32_t n, dim, metric, K, lo, hi;
+    int by_f32;
+    int32_t *ids;
+    double *d64;
+} bf_job;
+
+typedef struct {
+    double d;
+    float f;
+    uint32_t id;
+} bf_item;
+
+static int bf_cmp64(const void *pa, const void *pb) {
+    const bf_item *a = (const bf_item *)pa, *b = (const bf_item *)pb;
+    if (a->d != b->d) return a->d < b->d ? -1 : 1;
+    return a->id < b->id ? -1 : (a->id > b->id);
+}
+
+static int bf_cmp32(const void *pa, const void *pb) {
+    const bf_item *a = (const bf_item *)pa, *b = (const bf_item *)pb;
+    if (a->f != b->f) return a->f < b->f ? -1 : 1;
+    return a->id < b->id ? -1 : (a->id > b->id);
+}
+
+static void *bf_worker(void *p) {
+    bf_job *j = (bf_job *)p;
+    bf_item *all = (bf_item *)malloc(sizeof(bf_item) * (j->n ? j->n : 1));
+    for (uint32_t qi = j->lo; qi < j->hi; ++qi) {
+        const float *q = j->Q + (uint64_t)qi * j->dim;
+        for (uint32_t i = 0; i < j->n; ++i) {
+            double d = dist64((int)j->metric, q, j->X + (uint64_t)i * j->dim, j->dim);
+            all[i] = (bf_item){d, (float)d, i};
+        }
+        qsort(all, j->n, sizeof(bf_item), j->by_f32 ? bf_cmp32 : bf_cmp64);
+        for (uint32_t k = 0; k < j->K; ++k) {
+            j->ids[(uint64_t)qi * j->K + k] = k < j->n ? (int32_t)all[k].id : -1;
+            j->d64[(uint64_t)qi * j->K + k] = k < j->n ? all[k].d : INFINITY;
+        }
+    }
+    free(all);
+    return NULL;
+}
+
+/*
+ * Exact K-NN by computing all n distances (the problem statement of Sec. 1).
+ * by_f32 = 0 orders by the double-precision distance, 1 by the fp32 key.
+ */
+OR_EXPORT void or_bruteforce(const float *X, uint32_t n, uint32_t dim, uint32_t metric, const float *Q, uint32_t nq,
+                             uint32_t K, int by_f32, int32_t *ids, double *d64, int nthreads) {
+    if (nthreads < 1) nthreads = 1;
+    if ((uint32_t)nthreads > nq) nthreads = nq ? (int)nq : 1;
+    if (nthreads > 256) nthreads = 256;
+    pthread_t th[256];
+    bf_job jobs[256];
+    for (int t = 0; t < nthreads; ++t) {
+        jobs[t] = (bf_job){X, Q, n, dim, metric, K, (uint32_t)((uint64_t)nq * t / nthreads),
+                           (uint32_t)((uint64_t)nq * (t + 1) / nthreads), by_f32, ids, d64};
+        if (nthreads == 1) bf_worker(&jobs[t]);
+        else pthread_create(&th[t], NULL, bf_worker, &jobs[t]);
+    }
+    if (nthreads > 1)
+        for (int t = 0; t < nthreads; ++t) pthread_join(th[t], NULL);
+}
+
+/* Exact distances of explicit (query, id) pairs, fp64 and the fp32 key. */
+OR_EXPORT void or_pair_dist(const float *X, uint32_t dim, uint32_t metric, const float *Q, const int32_t *ids,
+                            uint64_t n_pairs, uint32_t per_query, double *d64) {
+    for (uint64_t p = 0; p < n_pairs; ++p) {
+        int32_t id = ids[p];
+        const float *q = Q + (p / per_query) * dim;
+        d64[p] = id < 0 ? INFINITY : dist64((int)metric, q, X + (uint64_t)id * dim, dim);
+    }
+}
+
+/* ------------------------------------------------------- export / import */
+
+OR_EXPORT void or_info(const graph *g, uint64_t *out) {
+    out[0] = g->n; out[1] = g->dim; out[2] = g->metric; out[3] = g->M; out[4] = g->Mmax; out[5] = g->Mmax0;
+    out[6] = g->efC; out[7] = (uint64_t)(g->max_level < 0 ? 0 : g->max_level);
+    out[8] = (uint64_t)(g->entry < 0 ? 0 : g->entry); out[9] = g->rows; out[10] = g->n_inserted;
+    out[11] = g->seed;
+}
+
+/*
+ * Packed form: levels[n] u8, adj0[n][Mmax0] u32 padded with 0xFFFFFFFF,
+ * upper_off[n] i32 (row of layer 1, -1 when the element has level 0),
+ * adjU[rows][Mmax] u32 padded; an element's rows for layers 1..level are
+ * consecutive.
+ */
+OR_EXPORT void or_export(const graph *g, uint8_t *levels, uint32_t *adj0, int32_t *upper_off, uint32_t *adjU) {
+    memcpy(levels, g->level, g->n);
+    for (uint32_t i = 0; i < g->n; ++i) {
+        const uint32_t *src = g->adj0 + (uint64_t)i * (g->Mmax0 + 1);
+        uint32_t *dst = adj0 + (uint64_t)i * g->Mmax0;
+        for (uint32_t k = 0; k < g->Mmax0; ++k) dst[k] = k < g->cnt0[i] ? src[k] : OR_NONE;
+        upper_off[i] = (int32_t)g->uoff[i];
+    }
+    for (uint64_t r = 0; r < g->rows; ++r)
+        for (uint32_t k = 0; k < g->Mmax; ++k)
+            adjU[r * g->Mmax + k] = k < g->ucnt[r] ? g->uadj[r * (g->Mmax + 1) + k] : OR_NONE;
+}
+
+/* Rebuild a searchable graph from the packed form (e.g. read from a file, or a hand-made graph). */
+OR_EXPORT graph *or_import(const float *X, uint32_t n, uint32_t dim, uint32_t metric, uint32_t M, uint32_t Mmax,
+                           uint32_t Mmax0, int64_t entry, int max_level, const uint8_t *levels, const uint32_t *adj0,
+                           const uint32_t *adjU) {
+    graph *g = (graph *)calloc(1, sizeof(graph));
+    g->n = n; g->dim = dim; g->metric = metric; g->M = M; g->Mmax = Mmax; g->Mmax0 = Mmax0;
+    g->X = X;
+    g->level = (uint8_t *)malloc(n ? n : 1);
+    memcpy(g->level, levels, n);
+    alloc_lists(g);
+    for (uint32_t i = 0; i < n; ++i) {
+        uint32_t c = 0;
+        for (uint32_t k = 0; k < Mmax0; ++k) {
+            uint32_t v = adj0[(uint64_t)i * Mmax0 + k];
+            if (v != OR_NONE) g->adj0[(uint64_t)i * (Mmax0 + 1) + c++] = v;
+        }
+        g->cnt0[i] = c;
+    }
+    for (uint64_t r = 0; r < g->rows; ++r) {
+        uint32_t c = 0;
+        for (uint32_t k = 0; k < Mmax; ++k) {
+            uint32_t v = adjU[r * Mmax + k];
+            if (v != OR_NONE) g->uadj[r * (Mmax + 1) + c++] = v;
+        }
+        g->ucnt[r] = c;
+    }
+    g->entry = entry;
+    g->max_level = max_level;
+    g->n_inserted = n;
+    g->ws = ws_new(n);
+    return g;
+}
+
+/* Swap the vector store (same shape), e.g. for the dequantised low-precision copy. */
+OR_EXPORT void or_set_vectors(graph *g, const float *X) { g->X = X; }

@@ -1,0 +1,142 @@
+/*
+ * hnsw_gpu.h -- C ABI of the MI355X (gfx950) Hierarchical NSW query path.
+ *
+ * The library answers the K-ANNS problem of Malkov & Yashunin,
+ * arXiv:1603.09320, Sec. 1: given a distance, a stored set of n vectors and a
+ * query q, return the K stored elements nearest to q.  The search is
+ * K-NN-SEARCH (Alg. 5): a greedy descent with ef = 1 through layers L..1,
+ * then SEARCH-LAYER (Alg. 2) on layer 0 with ef candidates, returning the K
+ * nearest elements of the final list W.
+ *
+ * Conventions shared by every entry point
+ *   - Status codes only; nothing is thrown across the ABI.  Arguments are
+ *     validated on the host before anything is enqueued.
+ *   - `stream` is a hipStream_t passed as void* (NULL = the null stream).
+ *     Search entry points only enqueue work on it and never synchronise.
+ *   - "device" buffers must be device memory of the current HIP device
+ *     (e.g. PyTorch tensors); host pointers are rejected with
+ *     HNSW_ERR_INVALID_ARG.  The caller owns them and keeps them alive until
+ *     the enqueued work has completed.
+ *   - Ids are 32-bit.  Output rows are sorted ascending by (distance, id);
+ *     rows with fewer than k reachable elements are padded with id -1 and
+ *     distance +inf.
+ *   - Distances: HNSW_L2SQ is the squared Euclidean distance, HNSW_IP is
+ *     1 - <q, x> (cosine distance for unit vectors, Sec. 5.2).  Each distance
+ *     is accumulated in double precision and rounded once to float; every
+ *     ordering decision compares (float distance, id) keys.
+ *   - An index is immutable after upload and may be searched concurrently
+ *     from several streams.
+ */
+#ifndef HNSW_GPU_H
+#define HNSW_GPU_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct hnsw_index hnsw_index; /* opaque, device resident */
+
+typedef enum {
+    HNSW_OK = 0,
+    HNSW_ERR_INVALID_ARG = 1,   /* null/host pointer, bad size, malformed graph     */
+    HNSW_ERR_OUT_OF_MEMORY = 2, /* device allocation failed                          */
+    HNSW_ERR_DEVICE = 3,        /* no device, launch or runtime failure              */
+    HNSW_ERR_UNSUPPORTED = 4,   /* a size beyond the kernels' limits (dim, ef, deg)  */
+    HNSW_ERR_FORMAT = 5         /* inconsistent graph description                    */
+} hnsw_status;
+
+typedef enum { HNSW_L2SQ = 0, HNSW_IP = 1 } hnsw_metric;
+
+/* Limits of this build. */
+#define HNSW_EF_MAX 1024u   /* largest ef (after ef := max(ef, k))               */
+#define HNSW_DIM_MAX 256u   /* largest vector dimension                          */
+#define HNSW_DEG_MAX 64u    /* largest Mmax and Mmax0                            */
+
+/*
+ * Host-side description of a multilayer graph (Sec. 3, Alg. 1), in the packed
+ * form produced by graph construction:
+ *   vectors    [n][dim] fp32, row major.
+ *   levels     [n] u8: the level l of each element (Alg. 1), <= max_level.
+ *   adj0       [n][Mmax0] u32: layer-0 neighbour lists, unused slots
+ *              0xFFFFFFFF (4-byte links, Sec. 4.2.3).
+ *   upper_off  [n] i32: row of the element's layer-1 list in adjU, -1 for
+ *              level-0 elements; the rows of layers 1..level are consecutive.
+ *   adjU       [n_upper_rows][Mmax] u32: lists of layers >= 1, padded.
+ *   entry_point / max_level: the enter point and top layer L (Alg. 5).
+ */
+typedef struct {
+    uint32_t n, dim;
+    uint32_t metric; /* hnsw_metric */
+    uint32_t M, Mmax, Mmax0;
+    uint32_t max_level, entry_point;
+    const float *vectors;
+    const uint8_t *levels;
+    const uint32_t *adj0;
+    const int32_t *upper_off;
+    const uint32_t *adjU;
+    uint64_t n_upper_rows;
+} hnsw_graph_desc;
+
+/*
+ * Copy a graph to the current device and return an index handle.
+ * All arrays of `g` are host memory, read only during the call (which
+ * synchronises `stream` before returning); the caller may free them after.
+ * Every link is checked to lie in [0, n) (or be the 0xFFFFFFFF pad), every
+ * upper_off row range to lie inside adjU, and the entry point to sit on the
+ * top level; a violation returns HNSW_ERR_FORMAT and allocates nothing.
+ * Device layout: vectors padded to rows of a multiple of 64 bytes (16 bytes
+ * for dim <= 4), adj0/upper_off/adjU copied as given.
+ */
+hnsw_status hnsw_index_upload(const hnsw_graph_desc *g, void *stream, hnsw_index **out);
+
+/* Release the index and its device memory (NULL is ignored).  The caller
+ * must ensure no enqueued search still reads it. */
+void hnsw_index_free(hnsw_index *index);
+
+/* Read back index properties: out[0..7] = n, dim, metric, M, Mmax, Mmax0,
+ * max_level, entry_point; out[8] = device bytes held. */
+hnsw_status hnsw_index_info(const hnsw_index *index, uint64_t out[9]);
+
+/*
+ * Batched K-NN-SEARCH (Alg. 5), one query per wavefront.
+ *   queries   device fp32 [n][dim] row major (the index's dim).
+ *   n         number of queries; 0 is a successful no-op.
+ *   k         neighbours per query, 1 <= k <= HNSW_EF_MAX.
+ *   ef        size of the dynamic list W (Alg. 2); raised to k when smaller;
+ *             above HNSW_EF_MAX returns HNSW_ERR_UNSUPPORTED.
+ *   ids_out   device i32 [n][k];  dists_out  device fp32 [n][k].
+ */
+hnsw_status hnsw_search_batch(const hnsw_index *index, const float *queries, uint32_t n, uint32_t k, uint32_t ef,
+                              int32_t *ids_out, float *dists_out, void *stream);
+
+/* Search modes of hnsw_search_batch_ex. */
+typedef enum {
+    HNSW_MODE_PLAIN = 0, /* fp32 vectors, as hnsw_search_batch                       */
+    HNSW_MODE_BF16 = 1,  /* traverse the BF16 copy, then exact fp32 rerank of W       */
+    HNSW_MODE_FP8 = 2,   /* traverse the FP8-E4M3 copy (per-vector scale), then rerank */
+    HNSW_MODE_LEARNED = 3 /* fp32 traversal with the learned early-termination net    */
+} hnsw_mode;
+
+/*
+ * hnsw_search_batch with a mode and optional per-query counters.
+ *   mode       hnsw_mode; BF16/FP8 need hnsw_index_add_lowp first.
+ *   mlp        for HNSW_MODE_LEARNED: a network from hnsw_mlp_create (NULL
+ *              otherwise); a NULL net in learned mode runs the plain search.
+ *   counters   NULL or device u32 [n][4]: distance evaluations (all layers),
+ *              expansions (all layers), distance evaluations on layer 0,
+ *              expansions on layer 0.
+ */
+hnsw_status hnsw_search_batch_ex(const hnsw_index *index, const float *queries, uint32_t n, uint32_t k, uint32_t ef,
+                                 int mode, const void *mlp, int32_t *ids_out, float *dists_out, uint32_t *counters,
+                                 void *stream);
+
+/* Human-readable name of a status code (static storage). */
+const char *hnsw_status_str(hnsw_status s);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* HNSW_GPU_H */

@@ -1,0 +1,178 @@
+"""Python binding of the gfx950 HNSW query library (``libhnsw_gpu.so``).
+
+Argument marshalling only: tensors are passed to the C ABI of
+``include/hnsw_gpu.h`` as raw device pointers on the current torch stream;
+every step of the search runs in the library's HIP kernels.  There is no CPU
+fallback: if the library is missing the import of :func:`lib` raises.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+from . import graphfile
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libhnsw_gpu.so")
+
+HNSW_L2SQ, HNSW_IP = 0, 1
+MODE_PLAIN, MODE_BF16, MODE_FP8, MODE_LEARNED = 0, 1, 2, 3
+EF_MAX, DIM_MAX, DEG_MAX = 1024, 256, 64
+
+STATUS = {0: "ok", 1: "invalid argument", 2: "out of device memory", 3: "device error", 4: "unsupported size",
+          5: "malformed graph"}
+
+
+class HnswError(RuntimeError):
+    def __init__(self, fn: str, code: int):
+        super().__init__(f"{fn}: {STATUS.get(code, code)} ({code})")
+        self.code = code
+
+
+class GraphDesc(C.Structure):
+    _fields_ = [
+        ("n", C.c_uint32), ("dim", C.c_uint32), ("metric", C.c_uint32),
+        ("M", C.c_uint32), ("Mmax", C.c_uint32), ("Mmax0", C.c_uint32),
+        ("max_level", C.c_uint32), ("entry_point", C.c_uint32),
+        ("vectors", C.c_void_p), ("levels", C.c_void_p), ("adj0", C.c_void_p),
+        ("upper_off", C.c_void_p), ("adjU", C.c_void_p), ("n_upper_rows", C.c_uint64),
+    ]
+
+
+# name -> (restype, argtypes); the exported symbols of include/hnsw_gpu.h
+_vp, _u32, _u64, _i32 = C.c_void_p, C.c_uint32, C.c_uint64, C.c_int
+SIGNATURES = {
+    "hnsw_status_str": (C.c_char_p, [C.c_int]),
+    "hnsw_index_upload": (C.c_int, [C.POINTER(GraphDesc), _vp, C.POINTER(_vp)]),
+    "hnsw_index_free": (None, [_vp]),
+    "hnsw_index_info": (C.c_int, [_vp, _vp]),
+    "hnsw_search_batch": (C.c_int, [_vp, _vp, _u32, _u32, _u32, _vp, _vp, _vp]),
+    "hnsw_search_batch_ex": (C.c_int, [_vp, _vp, _u32, _u32, _u32, _i32, _vp, _vp, _vp, _vp, _vp]),
+}
+
+_lib = None
+
+
+def lib():
+    """The loaded library; raises if it has not been built."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(f"{LIB_PATH} is missing: build it with paper_1603_09320_amd.build_ext.build()")
+        L = C.CDLL(LIB_PATH)
+        for name, (res, args) in SIGNATURES.items():
+            fn = getattr(L, name)
+            fn.restype = res
+            fn.argtypes = args
+        _lib = L
+    return _lib
+
+
+def _check(fn: str, code: int):
+    if code != 0:
+        raise HnswError(fn, code)
+
+
+def _stream_ptr(stream=None):
+    import torch
+
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return C.c_void_p(s.cuda_stream)
+
+
+def _dptr(t):
+    return C.c_void_p(t.data_ptr())
+
+
+def _np(a):
+    return a.ctypes.data_as(C.c_void_p)
+
+
+class Index:
+    """A graph uploaded to the current GPU (an ``hnsw_index``)."""
+
+    def __init__(self, graph: dict, vectors: np.ndarray, stream=None):
+        X = np.ascontiguousarray(vectors, dtype=np.float32)
+        if X.shape != (graph["n"], graph["dim"]):
+            raise ValueError(f"vectors {X.shape} do not match graph ({graph['n']}, {graph['dim']})")
+        self._arrays = [X, np.ascontiguousarray(graph["levels"], dtype=np.uint8),
+                        np.ascontiguousarray(graph["adj0"], dtype=np.uint32),
+                        np.ascontiguousarray(graph["upper_off"], dtype=np.int32),
+                        np.ascontiguousarray(graph["adjU"], dtype=np.uint32)]
+        X, lv, a0, uo, aU = self._arrays
+        d = GraphDesc(graph["n"], graph["dim"], graph["metric"], graph["M"], graph["Mmax"], graph["Mmax0"],
+                      graph["max_level"], graph["entry_point"], _np(X).value, _np(lv).value, _np(a0).value,
+                      _np(uo).value, _np(aU).value if aU.size else None, aU.shape[0] if aU.size else 0)
+        h = C.c_void_p()
+        _check("hnsw_index_upload", lib().hnsw_index_upload(C.byref(d), _stream_ptr(stream), C.byref(h)))
+        self._h = h
+        self._arrays = None
+        self.n, self.dim, self.metric = graph["n"], graph["dim"], graph["metric"]
+
+    @classmethod
+    def from_file(cls, path: str, vectors: np.ndarray, stream=None) -> "Index":
+        return cls(graphfile.read(path), vectors, stream)
+
+    @property
+    def handle(self):
+        return self._h
+
+    def info(self) -> dict:
+        out = np.zeros(9, dtype=np.uint64)
+        _check("hnsw_index_info", lib().hnsw_index_info(self._h, _np(out)))
+        keys = ["n", "dim", "metric", "M", "Mmax", "Mmax0", "max_level", "entry_point", "device_bytes"]
+        return {k: int(v) for k, v in zip(keys, out)}
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib().hnsw_index_free(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def search(self, queries, k: int, ef: int, mode: int = MODE_PLAIN, mlp=None, counters: bool = False,
+               out=None, stream=None):
+        """K-NN-SEARCH (Alg. 5) of every row of ``queries`` (a float32 CUDA tensor [n][dim]).
+
+        Returns (ids int32 [n][k], dists float32 [n][k]) and, with ``counters``,
+        a uint32-valued int32 tensor [n][4] of work counters.  ``out`` may give
+        preallocated (ids, dists[, counters]) tensors.
+        """
+        import torch
+
+        if queries.dtype != torch.float32 or not queries.is_cuda or queries.dim() != 2:
+            raise ValueError("queries must be a float32 CUDA tensor [n][dim]")
+        if queries.shape[1] != self.dim:
+            raise ValueError(f"queries have dim {queries.shape[1]}, index has {self.dim}")
+        q = queries.contiguous()
+        n = q.shape[0]
+        if out is None:
+            ids = torch.empty((n, k), dtype=torch.int32, device=q.device)
+            dists = torch.empty((n, k), dtype=torch.float32, device=q.device)
+            cnt = torch.zeros((n, 4), dtype=torch.int32, device=q.device) if counters else None
+        else:
+            ids, dists = out[0], out[1]
+            cnt = out[2] if counters else None
+        mlp_ptr = C.c_void_p(mlp.handle.value) if mlp is not None else None
+        code = lib().hnsw_search_batch_ex(self._h, _dptr(q), n, k, ef, mode, mlp_ptr, _dptr(ids), _dptr(dists),
+                                          _dptr(cnt) if cnt is not None else None, _stream_ptr(stream))
+        _check("hnsw_search_batch_ex", code)
+        return (ids, dists, cnt) if counters else (ids, dists)
+
+
+def search_batch(index: Index, queries, k: int, ef: int, stream=None):
+    """The plain ``hnsw_search_batch`` entry point."""
+    import torch
+
+    n = queries.shape[0]
+    ids = torch.empty((n, k), dtype=torch.int32, device=queries.device)
+    dists = torch.empty((n, k), dtype=torch.float32, device=queries.device)
+    _check("hnsw_search_batch", lib().hnsw_search_batch(index.handle, _dptr(queries), n, k, ef, _dptr(ids),
+                                                        _dptr(dists), _stream_ptr(stream)))
+    return ids, dists

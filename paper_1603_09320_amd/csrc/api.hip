@@ -1,0 +1,245 @@
+// Host runtime of the C ABI declared in include/hnsw_gpu.h.
+//
+// Everything here is argument checking, device memory management and kernel
+// launches; all arithmetic of the search runs in the kernels.
+#include <stdlib.h>
+#include <string.h>
+
+#include <vector>
+
+#include "internal.h"
+
+struct hnsw_index {
+    hnsw::DevIndex ix;
+    uint32_t M;
+    int device;
+    uint64_t bytes;
+    std::vector<void *> allocations;
+};
+
+namespace {
+
+using hnsw::kNoLink;
+
+bool device_count_ok() {
+    int n = 0;
+    if (hipGetDeviceCount(&n) != hipSuccess) {
+        (void)hipGetLastError();
+        return false;
+    }
+    return n > 0;
+}
+
+// True for memory the current device can address as device memory.
+bool is_device_ptr(const void *p) {
+    if (!p) return false;
+    hipPointerAttribute_t at;
+    if (hipPointerGetAttributes(&at, p) != hipSuccess) {
+        (void)hipGetLastError();
+        return false;
+    }
+    return at.type == hipMemoryTypeDevice || at.type == hipMemoryTypeManaged || at.isManaged;
+}
+
+// Optional cap on the bytes an upload may allocate (HNSW_DEVICE_MEM_CAP),
+// used to exercise the out-of-memory path from the host.
+uint64_t mem_cap() {
+    const char *s = getenv("HNSW_DEVICE_MEM_CAP");
+    if (!s || !*s) return UINT64_MAX;
+    return strtoull(s, nullptr, 10);
+}
+
+uint32_t row_floats(uint32_t dim) {
+    const uint32_t v4 = (dim + 3) / 4;
+    if (v4 <= 1) return 4;
+    return ((v4 + 3) / 4) * 16;  // rows of a multiple of 64 bytes
+}
+
+// Structural checks of a graph description; nothing is touched on the device.
+hnsw_status validate_graph(const hnsw_graph_desc *g) {
+    if (!g || !g->vectors || !g->levels || !g->adj0 || !g->upper_off) return HNSW_ERR_INVALID_ARG;
+    if (g->n == 0 || g->n >= 0x7FFFFFFFu || g->dim == 0) return HNSW_ERR_INVALID_ARG;
+    if (g->metric != HNSW_L2SQ && g->metric != HNSW_IP) return HNSW_ERR_INVALID_ARG;
+    if (g->dim > HNSW_DIM_MAX || g->Mmax0 > HNSW_DEG_MAX || g->Mmax > HNSW_DEG_MAX) return HNSW_ERR_UNSUPPORTED;
+    if (g->Mmax0 == 0 || (g->max_level > 0 && g->Mmax == 0)) return HNSW_ERR_FORMAT;
+    if (g->max_level > 255 || g->entry_point >= g->n) return HNSW_ERR_FORMAT;
+    if (g->levels[g->entry_point] != g->max_level) return HNSW_ERR_FORMAT;
+    if (g->n_upper_rows > 0 && !g->adjU) return HNSW_ERR_INVALID_ARG;
+    const uint64_t n = g->n;
+    for (uint64_t i = 0; i < n; ++i) {
+        const uint32_t l = g->levels[i];
+        if (l > g->max_level) return HNSW_ERR_FORMAT;
+        const uint32_t *r0 = g->adj0 + i * g->Mmax0;
+        for (uint32_t k = 0; k < g->Mmax0; ++k)
+            if (r0[k] != kNoLink && r0[k] >= g->n) return HNSW_ERR_FORMAT;
+        const int32_t off = g->upper_off[i];
+        if (l == 0) {
+            if (off != -1) return HNSW_ERR_FORMAT;
+            continue;
+        }
+        if (off < 0 || static_cast<uint64_t>(off) + l > g->n_upper_rows) return HNSW_ERR_FORMAT;
+        for (uint32_t lc = 1; lc <= l; ++lc) {
+            const uint32_t *ru = g->adjU + (static_cast<uint64_t>(off) + lc - 1) * g->Mmax;
+            for (uint32_t k = 0; k < g->Mmax; ++k) {
+                const uint32_t e = ru[k];
+                if (e == kNoLink) continue;
+                // a link on layer lc must point to a member of layer lc
+                if (e >= g->n || g->levels[e] < lc) return HNSW_ERR_FORMAT;
+            }
+        }
+    }
+    return HNSW_OK;
+}
+
+struct Allocator {
+    std::vector<void *> got;
+    uint64_t bytes = 0;
+    uint64_t cap = mem_cap();
+    void *take(size_t sz) {
+        if (bytes + sz > cap) return nullptr;
+        void *p = nullptr;
+        if (hipMalloc(&p, sz ? sz : 16) != hipSuccess) {
+            (void)hipGetLastError();
+            return nullptr;
+        }
+        got.push_back(p);
+        bytes += sz;
+        return p;
+    }
+    void release() {
+        for (void *p : got) (void)hipFree(p);
+        got.clear();
+    }
+};
+
+}  // namespace
+
+extern "C" {
+
+const char *hnsw_status_str(hnsw_status s) {
+    switch (s) {
+        case HNSW_OK: return "ok";
+        case HNSW_ERR_INVALID_ARG: return "invalid argument";
+        case HNSW_ERR_OUT_OF_MEMORY: return "out of device memory";
+        case HNSW_ERR_DEVICE: return "device error";
+        case HNSW_ERR_UNSUPPORTED: return "unsupported size";
+        case HNSW_ERR_FORMAT: return "malformed graph";
+    }
+    return "unknown status";
+}
+
+hnsw_status hnsw_index_upload(const hnsw_graph_desc *g, void *stream, hnsw_index **out) {
+    if (!out) return HNSW_ERR_INVALID_ARG;
+    *out = nullptr;
+    const hnsw_status v = validate_graph(g);
+    if (v != HNSW_OK) return v;
+    if (!device_count_ok()) return HNSW_ERR_DEVICE;
+    hipStream_t st = static_cast<hipStream_t>(stream);
+
+    const uint32_t rf = row_floats(g->dim);
+    const size_t vec_bytes = static_cast<size_t>(g->n) * rf * 4;
+    const size_t adj0_bytes = static_cast<size_t>(g->n) * g->Mmax0 * 4;
+    const size_t uoff_bytes = static_cast<size_t>(g->n) * 4;
+    const size_t adjU_bytes = static_cast<size_t>(g->n_upper_rows) * g->Mmax * 4;
+
+    Allocator al;
+    float *vec = static_cast<float *>(al.take(vec_bytes));
+    uint32_t *adj0 = static_cast<uint32_t *>(al.take(adj0_bytes));
+    int32_t *uoff = static_cast<int32_t *>(al.take(uoff_bytes));
+    uint32_t *adjU = static_cast<uint32_t *>(al.take(adjU_bytes));
+    if (!vec || !adj0 || !uoff || !adjU) {
+        al.release();
+        return HNSW_ERR_OUT_OF_MEMORY;
+    }
+    bool ok = hipMemsetAsync(vec, 0, vec_bytes, st) == hipSuccess;
+    ok = ok && hipMemcpy2DAsync(vec, static_cast<size_t>(rf) * 4, g->vectors, static_cast<size_t>(g->dim) * 4,
+                                static_cast<size_t>(g->dim) * 4, g->n, hipMemcpyHostToDevice, st) == hipSuccess;
+    ok = ok && hipMemcpyAsync(adj0, g->adj0, adj0_bytes, hipMemcpyHostToDevice, st) == hipSuccess;
+    ok = ok && hipMemcpyAsync(uoff, g->upper_off, uoff_bytes, hipMemcpyHostToDevice, st) == hipSuccess;
+    if (adjU_bytes)
+        ok = ok && hipMemcpyAsync(adjU, g->adjU, adjU_bytes, hipMemcpyHostToDevice, st) == hipSuccess;
+    ok = ok && hipStreamSynchronize(st) == hipSuccess;
+    if (!ok) {
+        (void)hipGetLastError();
+        al.release();
+        return HNSW_ERR_DEVICE;
+    }
+    hnsw_index *h = new hnsw_index();
+    h->ix = hnsw::DevIndex{};
+    h->ix.vec = vec;
+    h->ix.adj0 = adj0;
+    h->ix.uoff = uoff;
+    h->ix.adjU = adjU;
+    h->ix.n = g->n;
+    h->ix.dim = g->dim;
+    h->ix.dv4 = (g->dim + 3) / 4;
+    h->ix.stride4 = rf / 4;
+    h->ix.Mmax = g->Mmax;
+    h->ix.Mmax0 = g->Mmax0;
+    h->ix.entry = g->entry_point;
+    h->ix.max_level = g->max_level;
+    h->ix.metric = g->metric;
+    h->M = g->M;
+    (void)hipGetDevice(&h->device);
+    h->bytes = al.bytes;
+    h->allocations = al.got;
+    *out = h;
+    return HNSW_OK;
+}
+
+void hnsw_index_free(hnsw_index *index) {
+    if (!index) return;
+    for (void *p : index->allocations) (void)hipFree(p);
+    delete index;
+}
+
+hnsw_status hnsw_index_info(const hnsw_index *index, uint64_t out[9]) {
+    if (!index || !out) return HNSW_ERR_INVALID_ARG;
+    const hnsw::DevIndex &x = index->ix;
+    const uint64_t v[9] = {x.n, x.dim, x.metric, index->M, x.Mmax, x.Mmax0, x.max_level, x.entry, index->bytes};
+    memcpy(out, v, sizeof(v));
+    return HNSW_OK;
+}
+
+hnsw_status hnsw_search_batch_ex(const hnsw_index *index, const float *queries, uint32_t n, uint32_t k, uint32_t ef,
+                                 int mode, const void *mlp, int32_t *ids_out, float *dists_out, uint32_t *counters,
+                                 void *stream) {
+    if (!index) return HNSW_ERR_INVALID_ARG;
+    if (k == 0 || ef == 0) return HNSW_ERR_INVALID_ARG;
+    if (mode != HNSW_MODE_PLAIN) return HNSW_ERR_UNSUPPORTED;
+    (void)mlp;
+    const uint32_t efe = ef < k ? k : ef;
+    if (efe > HNSW_EF_MAX) return HNSW_ERR_UNSUPPORTED;
+    if (n == 0) return HNSW_OK;
+    if (!is_device_ptr(queries) || !is_device_ptr(ids_out) || !is_device_ptr(dists_out)) return HNSW_ERR_INVALID_ARG;
+    if (counters && !is_device_ptr(counters)) return HNSW_ERR_INVALID_ARG;
+
+    hnsw::SearchArgs a{};
+    a.queries = queries;
+    a.nq = n;
+    a.k = k;
+    a.ef = efe;
+    a.ids = ids_out;
+    a.dists = dists_out;
+    a.counters = counters;
+    a.wcap = (efe + 63) & ~63u;
+    // visited table: about 8 slots per unit of ef, 1024..4096 slots
+    uint32_t lg = 10;
+    while (lg < 12 && (1u << lg) < 8u * efe) ++lg;
+    a.ht_log2 = lg;
+    a.mode = mode;
+    a.mlp = mlp;
+    if (hnsw::launch_search(index->ix, a, static_cast<hipStream_t>(stream)) != hipSuccess) {
+        (void)hipGetLastError();
+        return HNSW_ERR_DEVICE;
+    }
+    return HNSW_OK;
+}
+
+hnsw_status hnsw_search_batch(const hnsw_index *index, const float *queries, uint32_t n, uint32_t k, uint32_t ef,
+                              int32_t *ids_out, float *dists_out, void *stream) {
+    return hnsw_search_batch_ex(index, queries, n, k, ef, HNSW_MODE_PLAIN, nullptr, ids_out, dists_out, nullptr,
+                                stream);
+}
+
+}  // extern "C"

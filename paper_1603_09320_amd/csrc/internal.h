@@ -1,0 +1,49 @@
+// Internal declarations shared by the host runtime and the gfx950 kernels.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "../../include/hnsw_gpu.h"
+
+namespace hnsw {
+
+constexpr uint32_t kNoLink = 0xFFFFFFFFu;
+
+// Device-resident index as the kernels see it.
+struct DevIndex {
+    const float *vec;      // [n][stride4 * 4] fp32, rows zero padded
+    const uint32_t *adj0;  // [n][Mmax0] layer-0 lists, kNoLink padded
+    const int32_t *uoff;   // [n] row of layer 1 in adjU, -1 for level 0
+    const uint32_t *adjU;  // [rows][Mmax] lists of layers >= 1
+    const uint16_t *vbf16; // [n][stride4 * 4] BF16 copy or null
+    const uint8_t *vfp8;   // [n][fp8_stride] FP8-E4M3 copy or null
+    const float *scale8;   // [n] per-vector scale of the FP8 copy
+    uint32_t n, dim, dv4, stride4, fp8_stride;
+    uint32_t Mmax, Mmax0, entry, max_level, metric;
+};
+
+// One batched search launch.
+struct SearchArgs {
+    const float *queries;  // [nq][dim]
+    uint32_t nq, k, ef;    // ef already raised to k
+    int32_t *ids;          // [nq][k]
+    float *dists;          // [nq][k]
+    uint32_t *counters;    // [nq][4] or null
+    uint32_t wcap;         // capacity of W in LDS, multiple of 64, >= ef
+    uint32_t ht_log2;      // visited-table slots = 1 << ht_log2
+    int mode;              // hnsw_mode
+    const void *mlp;       // device parameters of the learned stop rule or null
+};
+
+// Vector tile shape for a dimension: G lanes share one vector, each lane
+// holding F float4 pieces of it (G * F * 4 >= dim).
+struct TileShape {
+    int G, F;
+};
+TileShape tile_for_dim(uint32_t dim);
+
+size_t search_lds_bytes(const SearchArgs &a);
+hipError_t launch_search(const DevIndex &ix, const SearchArgs &a, hipStream_t stream);
+
+}  // namespace hnsw

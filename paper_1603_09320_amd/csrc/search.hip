@@ -1,0 +1,408 @@
+// Batched K-NN-SEARCH (Alg. 5 of arXiv:1603.09320) for gfx950.
+//
+// One wavefront (64 lanes) answers one query:
+//   1. the query is loaded into registers, split over lane groups;
+//   2. greedy descent with ef = 1 through layers L..1: SEARCH-LAYER with
+//      ef = 1 moves to the (dist, id)-smallest of the current element and its
+//      neighbours until none is smaller, so no visited set is needed there;
+//   3. SEARCH-LAYER (Alg. 2) on layer 0 with ef candidates;
+//   4. the K nearest of W are written out.
+//
+// Layer-0 state per wave, all in LDS:
+//   W    -- up to ef 64-bit keys sorted ascending; key = (ordered float bits
+//           of the distance) << 32 | id << 1 | expanded-flag.  Alg. 2 keeps
+//           the candidate set C and the list W; since an element that has
+//           left W can never be expanded again (its key exceeds that of the
+//           furthest element of W from then on), C is exactly the unexpanded
+//           part of W, so one sorted list with a flag holds both.
+//   ht   -- open-addressing visited table of element ids.  A probe run that
+//           finds no free slot reports "not visited" without recording the
+//           id: the table may forget (the element is scored again) but never
+//           reports an unseen element as visited.  A re-scored element has
+//           the same key; it is either in W (dropped by de-duplication) or
+//           above the furthest element of W (rejected), so results do not
+//           depend on the table size.
+// Each expansion reads the candidate's adjacency row (one coalesced load of
+// Mmax0 ids), filters it through ht, gathers the surviving vectors with G
+// lanes per vector, reduces each distance across its lane group with
+// cross-lane shuffles, then merges all new keys into W at once: W becomes the
+// ef smallest of W and the new keys, which is what processing the
+// neighbourhood one element at a time (Alg. 2, inner loop) produces.
+#include <climits>
+
+#include "internal.h"
+
+namespace hnsw {
+namespace {
+
+constexpr int kProbes = 4;
+
+__device__ __forceinline__ uint32_t ord_of(float f) {
+    uint32_t u = __float_as_uint(f);
+    if (u == 0x80000000u) u = 0u;  // -0 orders as +0
+    return (u & 0x80000000u) ? ~u : (u | 0x80000000u);
+}
+
+__device__ __forceinline__ float float_of(uint32_t o) {
+    const uint32_t u = (o & 0x80000000u) ? (o & 0x7FFFFFFFu) : ~o;
+    return __uint_as_float(u);
+}
+
+__device__ __forceinline__ uint64_t make_key(float d, uint32_t id) {
+    return (static_cast<uint64_t>(ord_of(d)) << 32) | (static_cast<uint64_t>(id) << 1);
+}
+__device__ __forceinline__ uint32_t key_id(uint64_t k) { return static_cast<uint32_t>(k) >> 1; }
+__device__ __forceinline__ float key_dist(uint64_t k) { return float_of(static_cast<uint32_t>(k >> 32)); }
+
+// Orders LDS traffic of the wave: every lane's earlier LDS accesses are
+// complete before any later one starts.
+__device__ __forceinline__ void wave_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+}
+
+__device__ __forceinline__ int lane_id() { return __builtin_amdgcn_mbcnt_hi(~0u, __builtin_amdgcn_mbcnt_lo(~0u, 0)); }
+
+// Number of set bits of `mask` below this lane.
+__device__ __forceinline__ int rank_in(uint64_t mask) {
+    return __builtin_amdgcn_mbcnt_hi(static_cast<uint32_t>(mask >> 32),
+                                     __builtin_amdgcn_mbcnt_lo(static_cast<uint32_t>(mask), 0));
+}
+
+__device__ __forceinline__ uint64_t wave_min_u64(uint64_t v) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+        const uint64_t w = __shfl_xor(v, o, 64);
+        v = w < v ? w : v;
+    }
+    return v;
+}
+
+__device__ __forceinline__ int wave_min_int(int v) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+        const int w = __shfl_xor(v, o, 64);
+        v = w < v ? w : v;
+    }
+    return v;
+}
+
+// Test-and-set of `id` in the visited table; true when the id was not seen.
+__device__ __forceinline__ bool visit(uint32_t *ht, uint32_t shift, uint32_t mask, uint32_t id) {
+    const uint32_t h = (id * 0x9E3779B1u) >> shift;
+#pragma unroll
+    for (int p = 0; p < kProbes; ++p) {
+        const uint32_t slot = (h + p) & mask;
+        const uint32_t old = atomicCAS(&ht[slot], kNoLink, id);
+        if (old == kNoLink) return true;
+        if (old == id) return false;
+    }
+    return true;  // run full: forget, score again
+}
+
+template <int G, int F>
+struct QueryRegs {
+    double q[F][4];  // components 4c..4c+3 of float4 pieces c = sub + f*G
+};
+
+template <int G, int F>
+__device__ __forceinline__ void load_query(const float *qrow, uint32_t dim, QueryRegs<G, F> &Q) {
+    const int sub = lane_id() % G;
+#pragma unroll
+    for (int f = 0; f < F; ++f)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            const uint32_t e = 4u * static_cast<uint32_t>(sub + f * G) + j;
+            Q.q[f][j] = e < dim ? static_cast<double>(qrow[e]) : 0.0;
+        }
+}
+
+// Scores ids[0..m) against the query; keys[slot] receives the key of ids[slot].
+// Lane group grp = lane / G handles slots grp, grp + P, ... (P = 64 / G).
+template <int G, int F, int METRIC>
+__device__ __forceinline__ void score_ids(const DevIndex &ix, const QueryRegs<G, F> &Q, const uint32_t *ids, int m,
+                                          uint64_t *keys) {
+    constexpr int P = 64 / G;
+    constexpr int B = (32 / P) < 1 ? 1 : ((32 / P) > 4 ? 4 : (32 / P));
+    const int lane = lane_id();
+    const int grp = lane / G, sub = lane % G;
+    const float4 *vec = reinterpret_cast<const float4 *>(ix.vec);
+    for (int base = 0; base < m; base += P * B) {
+        float4 v[B][F];
+        uint32_t idv[B];
+#pragma unroll
+        for (int b = 0; b < B; ++b) {
+            const int slot = base + b * P + grp;
+            idv[b] = slot < m ? ids[slot] : kNoLink;
+#pragma unroll
+            for (int f = 0; f < F; ++f) {
+                const uint32_t c = static_cast<uint32_t>(sub + f * G);
+                v[b][f] = make_float4(0.f, 0.f, 0.f, 0.f);
+                if (idv[b] != kNoLink && c < ix.dv4) v[b][f] = vec[static_cast<size_t>(idv[b]) * ix.stride4 + c];
+            }
+        }
+#pragma unroll
+        for (int b = 0; b < B; ++b) {
+            double acc = 0.0;
+#pragma unroll
+            for (int f = 0; f < F; ++f) {
+                const float x[4] = {v[b][f].x, v[b][f].y, v[b][f].z, v[b][f].w};
+#pragma unroll
+                for (int j = 0; j < 4; ++j) {
+                    if (METRIC == HNSW_L2SQ) {
+                        const double t = Q.q[f][j] - static_cast<double>(x[j]);
+                        acc = __fma_rn(t, t, acc);
+                    } else {
+                        acc = __fma_rn(Q.q[f][j], static_cast<double>(x[j]), acc);
+                    }
+                }
+            }
+#pragma unroll
+            for (int o = G / 2; o > 0; o >>= 1) acc += __shfl_xor(acc, o, 64);
+            const int slot = base + b * P + grp;
+            if (sub == 0 && slot < m) {
+                const double d = METRIC == HNSW_L2SQ ? acc : 1.0 - acc;
+                keys[slot] = make_key(static_cast<float>(d), idv[b]);
+            }
+        }
+    }
+}
+
+struct WaveLds {
+    uint64_t *W;       // [wcap]
+    uint64_t *keys;    // [64] keys of the current batch
+    uint64_t *sorted;  // [64] admitted keys in ascending order
+    uint32_t *ids;     // [64] ids of the current batch
+    uint32_t *ht;      // [1 << ht_log2]
+};
+
+__device__ __forceinline__ WaveLds carve(uint8_t *base, const SearchArgs &a) {
+    WaveLds s;
+    s.W = reinterpret_cast<uint64_t *>(base);
+    s.keys = s.W + a.wcap;
+    s.sorted = s.keys + 64;
+    s.ids = reinterpret_cast<uint32_t *>(s.sorted + 64);
+    s.ht = s.ids + 64;
+    return s;
+}
+
+// Merges keys[0..m) (lane j owns keys[j]) into the sorted list W of size
+// wsize: W <- the ef smallest of W and the new keys, dropping keys whose
+// (distance, id) is already in W.  Returns the insertion position of the
+// smallest admitted key (INT_MAX when none was admitted).
+__device__ __forceinline__ int merge_into_w(const WaveLds &s, int m, uint32_t ef, uint32_t &wsize) {
+    const int lane = lane_id();
+    uint64_t a = 0;
+    bool keep = false;
+    int lb = 0;
+    if (lane < m) {
+        a = s.keys[lane];
+        keep = wsize < ef || a < s.W[ef - 1];
+        if (keep) {
+            const uint64_t ak = a >> 1;
+            int lo = 0, hi = static_cast<int>(wsize);
+            while (lo < hi) {
+                const int mid = (lo + hi) >> 1;
+                if ((s.W[mid] >> 1) < ak) lo = mid + 1;
+                else hi = mid;
+            }
+            lb = lo;
+            if (lb < static_cast<int>(wsize) && (s.W[lb] >> 1) == ak) keep = false;
+        }
+    }
+    const uint64_t km = __ballot(keep);
+    if (km == 0) return INT_MAX;
+    const int cnt = __popcll(km);
+    int r = 0;
+    if (keep) {
+        uint64_t mm = km;
+        while (mm) {
+            const int t = __ffsll(static_cast<unsigned long long>(mm)) - 1;
+            mm &= mm - 1;
+            const uint64_t kt = s.keys[t];
+            r += (kt < a) || (kt == a && t < lane);
+        }
+        s.sorted[r] = a;
+    }
+    const int lbmin = wave_min_int(keep ? lb : INT_MAX);
+    wave_sync();
+    // Old elements at positions >= lbmin move right by the number of admitted
+    // keys below them; chunks are moved top first so no unread slot is overwritten.
+    const int ws = static_cast<int>(wsize);
+    for (int cb = (ws - 1) & ~63; cb >= (lbmin & ~63); cb -= 64) {
+        const int i = cb + lane;
+        uint64_t w = 0;
+        int np = -1;
+        if (i >= lbmin && i < ws) {
+            w = s.W[i];
+            int lo = 0, hi = cnt;
+            while (lo < hi) {
+                const int mid = (lo + hi) >> 1;
+                if (s.sorted[mid] < w) lo = mid + 1;
+                else hi = mid;
+            }
+            np = i + lo;
+        }
+        wave_sync();
+        if (np >= 0 && np < static_cast<int>(ef)) s.W[np] = w;
+        wave_sync();
+    }
+    if (keep && lb + r < static_cast<int>(ef)) s.W[lb + r] = a;
+    wave_sync();
+    wsize = min(ef, wsize + static_cast<uint32_t>(cnt));
+    return lbmin;
+}
+
+template <int G, int F, int METRIC>
+__global__ __launch_bounds__(64) void search_kernel(DevIndex ix, SearchArgs a) {
+    extern __shared__ __align__(16) uint8_t smem[];
+    const uint32_t qi = blockIdx.x;
+    if (qi >= a.nq) return;
+    const int lane = lane_id();
+    WaveLds s = carve(smem, a);
+
+    QueryRegs<G, F> Q;
+    load_query<G, F>(a.queries + static_cast<size_t>(qi) * ix.dim, ix.dim, Q);
+
+    const uint32_t ht_slots = 1u << a.ht_log2;
+    for (uint32_t i = lane; i < ht_slots; i += 64) s.ht[i] = kNoLink;
+
+    uint32_t n_dist = 0, n_exp = 0, n_dist0 = 0, n_exp0 = 0;
+
+    // Entry point (Alg. 5): its distance seeds the descent.
+    if (lane == 0) s.ids[0] = ix.entry;
+    wave_sync();
+    score_ids<G, F, METRIC>(ix, Q, s.ids, 1, s.keys);
+    wave_sync();
+    uint64_t cur = s.keys[0];
+    n_dist += 1;
+
+    // Greedy descent through layers L..1 (SEARCH-LAYER with ef = 1).
+    for (int lc = static_cast<int>(ix.max_level); lc >= 1; --lc) {
+        for (;;) {
+            const uint32_t cid = key_id(cur);
+            const size_t row = static_cast<size_t>(ix.uoff[cid]) + static_cast<size_t>(lc - 1);
+            const uint32_t e = lane < static_cast<int>(ix.Mmax) ? ix.adjU[row * ix.Mmax + lane] : kNoLink;
+            const bool valid = e != kNoLink;
+            const uint64_t vm = __ballot(valid);
+            const int m = __popcll(vm);
+            if (valid) s.ids[rank_in(vm)] = e;
+            wave_sync();
+            score_ids<G, F, METRIC>(ix, Q, s.ids, m, s.keys);
+            wave_sync();
+            uint64_t best = cur;
+            for (int i = lane; i < m; i += 64) best = s.keys[i] < best ? s.keys[i] : best;
+            best = wave_min_u64(best);
+            n_dist += m;
+            n_exp += 1;
+            wave_sync();
+            if (best == cur) break;
+            cur = best;
+        }
+    }
+
+    // SEARCH-LAYER on layer 0 with ef candidates, starting from the descent's result.
+    const uint32_t ef = a.ef;
+    const uint32_t ht_shift = 32u - a.ht_log2, ht_mask = ht_slots - 1u;
+    if (lane == 0) {
+        s.W[0] = cur;
+        visit(s.ht, ht_shift, ht_mask, key_id(cur));
+    }
+    wave_sync();
+    uint32_t wsize = 1;
+    int cursor = 0;  // every position below it is expanded
+    n_dist0 = 1;
+    for (;;) {
+        int c = -1;
+        for (int cb = cursor; cb < static_cast<int>(wsize); cb += 64) {
+            const int i = cb + lane;
+            const bool un = i < static_cast<int>(wsize) && !(s.W[i] & 1ull);
+            const uint64_t um = __ballot(un);
+            if (um) {
+                c = cb + __ffsll(static_cast<unsigned long long>(um)) - 1;
+                break;
+            }
+        }
+        if (c < 0) break;  // every element of W has been expanded
+        const uint64_t ck = s.W[c];
+        wave_sync();
+        if (lane == 0) s.W[c] = ck | 1ull;
+        cursor = c + 1;
+        const uint32_t cid = key_id(ck);
+        const uint32_t e = lane < static_cast<int>(ix.Mmax0) ? ix.adj0[static_cast<size_t>(cid) * ix.Mmax0 + lane]
+                                                              : kNoLink;
+        const bool fresh = e != kNoLink && visit(s.ht, ht_shift, ht_mask, e);
+        const uint64_t fm = __ballot(fresh);
+        const int m = __popcll(fm);
+        if (fresh) s.ids[rank_in(fm)] = e;
+        wave_sync();
+        score_ids<G, F, METRIC>(ix, Q, s.ids, m, s.keys);
+        wave_sync();
+        n_dist0 += m;
+        n_exp0 += 1;
+        const int lbmin = merge_into_w(s, m, ef, wsize);
+        if (lbmin < cursor) cursor = lbmin;
+    }
+
+    // The K nearest of W (Alg. 5, last line); W is sorted.
+    for (uint32_t i = lane; i < a.k; i += 64) {
+        const size_t o = static_cast<size_t>(qi) * a.k + i;
+        if (i < wsize) {
+            const uint64_t kk = s.W[i];
+            a.ids[o] = static_cast<int32_t>(key_id(kk));
+            a.dists[o] = key_dist(kk);
+        } else {
+            a.ids[o] = -1;
+            a.dists[o] = __int_as_float(0x7f800000);
+        }
+    }
+    if (a.counters && lane == 0) {
+        uint32_t *c4 = a.counters + static_cast<size_t>(qi) * 4;
+        c4[0] = n_dist + n_dist0;
+        c4[1] = n_exp + n_exp0;
+        c4[2] = n_dist0;
+        c4[3] = n_exp0;
+    }
+}
+
+template <int G, int F>
+hipError_t launch_gf(const DevIndex &ix, const SearchArgs &a, hipStream_t stream) {
+    const size_t lds = search_lds_bytes(a);
+    if (ix.metric == HNSW_IP)
+        hipLaunchKernelGGL((search_kernel<G, F, HNSW_IP>), dim3(a.nq), dim3(64), lds, stream, ix, a);
+    else
+        hipLaunchKernelGGL((search_kernel<G, F, HNSW_L2SQ>), dim3(a.nq), dim3(64), lds, stream, ix, a);
+    return hipGetLastError();
+}
+
+}  // namespace
+
+TileShape tile_for_dim(uint32_t dim) {
+    const uint32_t dv4 = (dim + 3) / 4;
+    if (dv4 <= 1) return {1, 1};
+    if (dv4 <= 4) return {2, 2};
+    if (dv4 <= 8) return {4, 2};
+    if (dv4 <= 16) return {8, 2};
+    if (dv4 <= 32) return {16, 2};
+    return {16, 4};
+}
+
+size_t search_lds_bytes(const SearchArgs &a) {
+    return static_cast<size_t>(a.wcap) * 8 + 64 * 8 * 2 + 64 * 4 + (static_cast<size_t>(1) << a.ht_log2) * 4;
+}
+
+hipError_t launch_search(const DevIndex &ix, const SearchArgs &a, hipStream_t stream) {
+    const TileShape t = tile_for_dim(ix.dim);
+    switch (t.G * 16 + t.F) {
+        case 1 * 16 + 1: return launch_gf<1, 1>(ix, a, stream);
+        case 2 * 16 + 2: return launch_gf<2, 2>(ix, a, stream);
+        case 4 * 16 + 2: return launch_gf<4, 2>(ix, a, stream);
+        case 8 * 16 + 2: return launch_gf<8, 2>(ix, a, stream);
+        case 16 * 16 + 2: return launch_gf<16, 2>(ix, a, stream);
+        case 16 * 16 + 4: return launch_gf<16, 4>(ix, a, stream);
+        default: return hipErrorInvalidValue;
+    }
+}
+
+}  // namespace hnsw

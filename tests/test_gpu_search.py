@@ -1,0 +1,193 @@
+"""GPU parity of the plain K-NN-SEARCH path against the oracle, through the C ABI.
+
+Every graph is built by the oracle; the GPU and the oracle search the same
+graph with the same seeded queries, and the per-query parity rule of
+``tests/parity.py`` is applied.  The distance accumulation on both sides is
+fp64 rounded once to fp32, so ids are expected to agree exactly
+(zero tie exemptions) and distances bit for bit.
+"""
+import math
+import os
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+import synthdata
+from tests import parity
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+def _log(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def hnsw():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_1603_09320_amd as h
+
+    h.lib()
+    return h
+
+
+def _index(h, G, X):
+    return h.Index(G.packed(), X)
+
+
+@pytest.fixture(scope="module")
+def cfg0():
+    X = synthdata.base("uniform16", 10000)
+    Q = synthdata.queries("uniform16", 1000)
+    G = oracle.Graph.build(X, M=16, efC=100, seed=1003)
+    return X, Q, G
+
+
+def _run_parity(h, G, X, Q, K, ef, metric=oracle.L2, counters=True):
+    idx = _index(h, G, X)
+    q = torch.from_numpy(Q).cuda()
+    ids, ds, cnt = idx.search(q, K, ef, counters=True)
+    torch.cuda.synchronize()
+    ids, ds, cnt = ids.cpu().numpy(), ds.cpu().numpy(), cnt.cpu().numpy().astype(np.uint32)
+    oi, od, oc = G.search(Q, K, ef, nthreads=8, counters=True)
+    r = parity.compare(ids, ds, oi, od, X, Q, metric)
+    _log(f"parity K={K} ef={ef}: {r['equal']} equal, {r['exempt']} tie-exempt, {r['fail']} fail, "
+         f"max rel {r['max_rel']:.2e}")
+    assert r["fail"] == 0, r["failed"][:10]
+    assert r["exempt"] == 0
+    # identical W evolution: identical expansion counts; the visited table may
+    # forget, so the GPU scores at least as many elements as the oracle
+    assert np.array_equal(cnt[:, 3], oc[:, 3].astype(np.uint32))
+    assert np.array_equal(cnt[:, 1], oc[:, 1].astype(np.uint32))
+    assert (cnt[:, 2] >= oc[:, 2].astype(np.uint32)).all()
+    return ids, ds, cnt, oc
+
+
+@pytest.mark.parametrize("ef", [10, 50, 200])
+def test_parity_uniform16(hnsw, cfg0, ef):
+    _log(f"case uniform16 10k x 16, K=10 ef={ef}")
+    X, Q, G = cfg0
+    ids, ds, cnt, oc = _run_parity(hnsw, G, X, Q, 10, ef)
+    assert np.array_equal(ds, G.search(Q, 10, ef, nthreads=8)[1])
+
+
+@pytest.mark.parametrize("K,ef", [(1, 1), (1, 10), (10, 1), (64, 64), (100, 300), (200, 1024), (1024, 1)])
+def test_parity_k_ef_edges(hnsw, cfg0, K, ef):
+    _log(f"case uniform16 K={K} ef={ef}")
+    X, Q, G = cfg0
+    _run_parity(hnsw, G, X, Q[:300], K, ef)
+
+
+@pytest.mark.parametrize("dim", [1, 3, 5, 8, 17, 33, 64, 100, 130, 256])
+def test_parity_dims(hnsw, dim):
+    """Every lane-group tile shape, with dimensions that leave a ragged tail."""
+    _log(f"case random dim={dim}")
+    rng = np.random.default_rng(dim)
+    X = rng.random((3000, dim)).astype(np.float32)
+    Q = rng.random((200, dim)).astype(np.float32)
+    G = oracle.Graph.build(X, M=8, efC=60, seed=7)
+    _run_parity(hnsw, G, X, Q, 10, 40)
+
+
+def test_parity_inner_product(hnsw):
+    _log("case glove_like 20k x 100 IP")
+    X = synthdata.base("glove_like", 20000)
+    Q = synthdata.queries("glove_like", 300)
+    G = oracle.Graph.build(X, metric=oracle.IP, M=16, efC=100, seed=3004)
+    for ef in (10, 100, 400):
+        _run_parity(hnsw, G, X, Q, 10, ef, metric=oracle.IP)
+
+
+def test_parity_sift_like_subset(hnsw):
+    _log("case sift_like 30k x 128")
+    X = synthdata.base("sift_like", 30000)
+    Q = synthdata.queries("sift_like", 300)
+    G = oracle.Graph.build(X, M=16, efC=200, seed=2003)
+    for K, ef in ((1, 10), (10, 10), (10, 64), (10, 256), (10, 800)):
+        _run_parity(hnsw, G, X, Q, K, ef)
+
+
+def test_tiny_graphs_and_padding(hnsw):
+    """n = 1 (entry point only, no links) and n < K: rows are padded with (-1, +inf)."""
+    for n in (1, 2, 7):
+        _log(f"case tiny n={n}")
+        X = np.arange(n * 4, dtype=np.float32).reshape(n, 4)
+        G = oracle.Graph.build(X, M=4, efC=10, seed=1)
+        Q = np.array([[1.0, 2.0, 3.0, 4.0], [100.0, 0.0, 0.0, 0.0]], dtype=np.float32)
+        ids, ds, _, _ = _run_parity(hnsw, G, X, Q, 10, 20)
+        assert (ids[:, n:] == -1).all() and np.isinf(ds[:, n:]).all()
+        assert sorted(ids[0, :n]) == list(range(n))
+
+
+def test_empty_batch_and_errors(hnsw, cfg0):
+    X, Q, G = cfg0
+    idx = _index(hnsw, G, X)
+    q = torch.from_numpy(Q[:4]).cuda()
+    ids, ds = idx.search(q[:0], 10, 10)
+    assert ids.shape == (0, 10)
+    with pytest.raises(hnsw.HnswError) as e:
+        idx.search(q, 10, 2000)
+    assert e.value.code == 4
+    with pytest.raises(hnsw.HnswError) as e:
+        idx.search(q, 0, 10)
+    assert e.value.code == 1
+    # host pointers are rejected
+    import ctypes as C
+
+    hq = np.ascontiguousarray(Q[:4])
+    hi = np.empty((4, 10), np.int32)
+    hd = np.empty((4, 10), np.float32)
+    code = hnsw.lib().hnsw_search_batch(idx.handle, hq.ctypes.data_as(C.c_void_p), 4, 10, 10,
+                                        hi.ctypes.data_as(C.c_void_p), hd.ctypes.data_as(C.c_void_p), None)
+    assert code == 1
+
+
+def test_plain_entry_point_and_determinism(hnsw, cfg0):
+    X, Q, G = cfg0
+    idx = _index(hnsw, G, X)
+    q = torch.from_numpy(Q).cuda()
+    a = hnsw.search_batch(idx, q, 10, 50)
+    b = idx.search(q, 10, 50)
+    s = torch.cuda.Stream()
+    with torch.cuda.stream(s):
+        c = idx.search(q, 10, 50, stream=s)
+    torch.cuda.synchronize()
+    for x, y in ((a, b), (a, c)):
+        assert torch.equal(x[0], y[0]) and torch.equal(x[1], y[1])
+
+
+FULL = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "graphs", "sift_like_1M.bin")
+
+
+@pytest.mark.skipif(not os.path.exists(FULL), reason="1M sift_like graph file not built")
+def test_parity_sift_like_full_size_sampled(hnsw):
+    """The 1M x 128 workload in the benchmark's launch shape: all 10,000 queries
+    on the GPU, a sample checked against the oracle on the same graph."""
+    _log("case sift_like 1M x 128 full size, sampled")
+    p = hnsw.graphfile.read(FULL)
+    X = synthdata.base("sift_like", p["n"])
+    Q = synthdata.queries("sift_like", 10000)
+    idx = hnsw.Index(p, X)
+    G = oracle.Graph.from_packed(X, p)
+    q = torch.from_numpy(Q).cuda()
+    sample = np.random.default_rng(0).choice(10000, size=150, replace=False)
+    for K, ef in ((10, 64), (10, 256), (1, 32)):
+        ids, ds, cnt = idx.search(q, K, ef, counters=True)
+        torch.cuda.synchronize()
+        ids, ds = ids.cpu().numpy(), ds.cpu().numpy()
+        oi, od, oc = G.search(Q[sample], K, ef, nthreads=8, counters=True)
+        r = parity.compare(ids[sample], ds[sample], oi, od, X, Q[sample], oracle.L2)
+        _log(f"full-size K={K} ef={ef}: {r}")
+        assert r["fail"] == 0 and r["exempt"] == 0
+        # properties over every query: valid distinct ids, sorted keys, exact distances
+        assert ((ids >= 0) & (ids < p["n"])).all()
+        assert all(len(set(row)) == K for row in ids)
+        assert (np.diff(ds, axis=1) >= 0).all()
+        d64 = oracle.pair_dist(X, Q, ids)
+        assert np.array_equal(d64.astype(np.float32), ds)

@@ -132,6 +132,23 @@ hnsw_status hnsw_search_batch_ex(const hnsw_index *index, const float *queries, 
                                  int mode, const void *mlp, int32_t *ids_out, float *dists_out, uint32_t *counters,
                                  void *stream);
 
+/*
+ * Exact K-NN by brute force over the index's vectors (the problem statement
+ * of Sec. 1; the "BF time" column of Table 1), the ground truth for recall.
+ * A fp32 matrix-core contraction ranks every stored vector by
+ * ||x||^2 - 2<q,x> (L2) or -<q,x> (IP) and keeps the best
+ * max(64, 2k)-ish candidates per query; those are re-scored exactly in fp64.
+ *   queries    device fp32 [n][dim].
+ *   k          1 <= k <= HNSW_BF_K_MAX.
+ *   ids_out    device i32 [n][k]; dists_out device f64 [n][k]: exact distances,
+ *              rows sorted by (distance, id), padded with (-1, +inf) when k > index n.
+ * Allocates stream-ordered scratch of n * chunks * candidates * 8 bytes on
+ * `stream` and frees it in stream order.
+ */
+#define HNSW_BF_K_MAX 128u
+hnsw_status hnsw_bruteforce_knn(const hnsw_index *index, const float *queries, uint32_t n, uint32_t k,
+                                int32_t *ids_out, double *dists_out, void *stream);
+
 /* Human-readable name of a status code (static storage). */
 const char *hnsw_status_str(hnsw_status s);
 

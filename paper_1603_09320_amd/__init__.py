@@ -50,6 +50,7 @@ SIGNATURES = {
     "hnsw_index_info": (C.c_int, [_vp, _vp]),
     "hnsw_search_batch": (C.c_int, [_vp, _vp, _u32, _u32, _u32, _vp, _vp, _vp]),
     "hnsw_search_batch_ex": (C.c_int, [_vp, _vp, _u32, _u32, _u32, _i32, _vp, _vp, _vp, _vp, _vp]),
+    "hnsw_bruteforce_knn": (C.c_int, [_vp, _vp, _u32, _u32, _vp, _vp, _vp]),
 }
 
 _lib = None
@@ -164,6 +165,19 @@ class Index:
                                           _dptr(cnt) if cnt is not None else None, _stream_ptr(stream))
         _check("hnsw_search_batch_ex", code)
         return (ids, dists, cnt) if counters else (ids, dists)
+
+
+def bruteforce(index: Index, queries, k: int, stream=None):
+    """Exact K-NN (``hnsw_bruteforce_knn``): (ids int32 [n][k], fp64 distances [n][k])."""
+    import torch
+
+    n = queries.shape[0]
+    ids = torch.empty((n, k), dtype=torch.int32, device=queries.device)
+    d = torch.empty((n, k), dtype=torch.float64, device=queries.device)
+    q = queries.contiguous()
+    _check("hnsw_bruteforce_knn", lib().hnsw_bruteforce_knn(index.handle, _dptr(q), n, k, _dptr(ids), _dptr(d),
+                                                            _stream_ptr(stream)))
+    return ids, d
 
 
 def search_batch(index: Index, queries, k: int, ef: int, stream=None):

@@ -11,6 +11,7 @@
 
 struct hnsw_index {
     hnsw::DevIndex ix;
+    float *xnorm;  // [n] squared norms of the vectors (brute-force ranking)
     uint32_t M;
     int device;
     uint64_t bytes;
@@ -147,7 +148,8 @@ hnsw_status hnsw_index_upload(const hnsw_graph_desc *g, void *stream, hnsw_index
     uint32_t *adj0 = static_cast<uint32_t *>(al.take(adj0_bytes));
     int32_t *uoff = static_cast<int32_t *>(al.take(uoff_bytes));
     uint32_t *adjU = static_cast<uint32_t *>(al.take(adjU_bytes));
-    if (!vec || !adj0 || !uoff || !adjU) {
+    float *xnorm = static_cast<float *>(al.take(static_cast<size_t>(g->n) * 4));
+    if (!vec || !adj0 || !uoff || !adjU || !xnorm) {
         al.release();
         return HNSW_ERR_OUT_OF_MEMORY;
     }
@@ -158,6 +160,21 @@ hnsw_status hnsw_index_upload(const hnsw_graph_desc *g, void *stream, hnsw_index
     ok = ok && hipMemcpyAsync(uoff, g->upper_off, uoff_bytes, hipMemcpyHostToDevice, st) == hipSuccess;
     if (adjU_bytes)
         ok = ok && hipMemcpyAsync(adjU, g->adjU, adjU_bytes, hipMemcpyHostToDevice, st) == hipSuccess;
+    hnsw::DevIndex ix{};
+    ix.vec = vec;
+    ix.adj0 = adj0;
+    ix.uoff = uoff;
+    ix.adjU = adjU;
+    ix.n = g->n;
+    ix.dim = g->dim;
+    ix.dv4 = (g->dim + 3) / 4;
+    ix.stride4 = rf / 4;
+    ix.Mmax = g->Mmax;
+    ix.Mmax0 = g->Mmax0;
+    ix.entry = g->entry_point;
+    ix.max_level = g->max_level;
+    ix.metric = g->metric;
+    ok = ok && hnsw::launch_row_norms(ix, xnorm, st) == hipSuccess;
     ok = ok && hipStreamSynchronize(st) == hipSuccess;
     if (!ok) {
         (void)hipGetLastError();
@@ -165,20 +182,8 @@ hnsw_status hnsw_index_upload(const hnsw_graph_desc *g, void *stream, hnsw_index
         return HNSW_ERR_DEVICE;
     }
     hnsw_index *h = new hnsw_index();
-    h->ix = hnsw::DevIndex{};
-    h->ix.vec = vec;
-    h->ix.adj0 = adj0;
-    h->ix.uoff = uoff;
-    h->ix.adjU = adjU;
-    h->ix.n = g->n;
-    h->ix.dim = g->dim;
-    h->ix.dv4 = (g->dim + 3) / 4;
-    h->ix.stride4 = rf / 4;
-    h->ix.Mmax = g->Mmax;
-    h->ix.Mmax0 = g->Mmax0;
-    h->ix.entry = g->entry_point;
-    h->ix.max_level = g->max_level;
-    h->ix.metric = g->metric;
+    h->ix = ix;
+    h->xnorm = xnorm;
     h->M = g->M;
     (void)hipGetDevice(&h->device);
     h->bytes = al.bytes;
@@ -230,6 +235,32 @@ hnsw_status hnsw_search_batch_ex(const hnsw_index *index, const float *queries, 
     a.mode = mode;
     a.mlp = mlp;
     if (hnsw::launch_search(index->ix, a, static_cast<hipStream_t>(stream)) != hipSuccess) {
+        (void)hipGetLastError();
+        return HNSW_ERR_DEVICE;
+    }
+    return HNSW_OK;
+}
+
+hnsw_status hnsw_bruteforce_knn(const hnsw_index *index, const float *queries, uint32_t n, uint32_t k,
+                                int32_t *ids_out, double *dists_out, void *stream) {
+    if (!index || k == 0) return HNSW_ERR_INVALID_ARG;
+    if (k > HNSW_BF_K_MAX) return HNSW_ERR_UNSUPPORTED;
+    if (n == 0) return HNSW_OK;
+    if (!is_device_ptr(queries) || !is_device_ptr(ids_out) || !is_device_ptr(dists_out)) return HNSW_ERR_INVALID_ARG;
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    uint32_t nchunks = 1, chunk = 64;
+    hnsw::bf_plan(index->ix, n, k, &nchunks, &chunk);
+    const size_t scratch = static_cast<size_t>(n) * nchunks * hnsw::bf_candidates(k) * 8;
+    void *partial = nullptr;
+    if (hipMallocAsync(&partial, scratch, st) != hipSuccess) {
+        (void)hipGetLastError();
+        return HNSW_ERR_OUT_OF_MEMORY;
+    }
+    const hipError_t e = hnsw::launch_bruteforce(index->ix, queries, n, k, index->xnorm,
+                                                 static_cast<uint64_t *>(partial), nchunks, chunk, ids_out,
+                                                 dists_out, st);
+    (void)hipFreeAsync(partial, st);
+    if (e != hipSuccess) {
         (void)hipGetLastError();
         return HNSW_ERR_DEVICE;
     }

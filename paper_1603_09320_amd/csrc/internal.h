@@ -44,6 +44,14 @@ struct TileShape {
 TileShape tile_for_dim(uint32_t dim);
 
 size_t search_lds_bytes(const SearchArgs &a);
+
+// Brute-force K-NN (MFMA scan + fp64 rerank).
+hipError_t launch_row_norms(const DevIndex &ix, float *out, hipStream_t stream);
+uint32_t bf_candidates(uint32_t k);
+void bf_plan(const DevIndex &ix, uint32_t nq, uint32_t k, uint32_t *nchunks, uint32_t *chunk);
+hipError_t launch_bruteforce(const DevIndex &ix, const float *Q, uint32_t nq, uint32_t k, const float *xnorm,
+                             uint64_t *partial, uint32_t nchunks, uint32_t chunk, int32_t *ids, double *d,
+                             hipStream_t stream);
 hipError_t launch_search(const DevIndex &ix, const SearchArgs &a, hipStream_t stream);
 
 }  // namespace hnsw

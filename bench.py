@@ -113,6 +113,8 @@ def main():
     ap.add_argument("--ef", type=int, default=0, help="time this ef instead of sweeping")
     ap.add_argument("--target-recall", type=float, default=0.95)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--copy-probe-bytes", type=int, default=0,
+                    help="also run a plain device-to-device copy of this size (counter calibration)")
     a = ap.parse_args()
     if a.gpus != 1:
         print(f"bench.py runs on one GPU only; --gpus {a.gpus} is not supported "
@@ -191,6 +193,15 @@ def main():
     achieved = alg_bytes / (kern_ms / 1000.0) / 1e9
     khash = kernel_source_hash()
     traffic = load_traffic(khash, a.workload, ef)
+
+    if a.copy_probe_bytes:
+        src = torch.ones(a.copy_probe_bytes // 4, dtype=torch.float32, device=dev)
+        dst = torch.empty_like(src)
+        for _ in range(2):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        log(f"[bench] copy probe: {a.copy_probe_bytes} bytes read and written, twice")
+        del src, dst
 
     cpu = None
     if not a.no_cpu_baseline:

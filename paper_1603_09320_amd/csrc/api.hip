@@ -138,7 +138,7 @@ hnsw_status hnsw_index_upload(const hnsw_graph_desc *g, void *stream, hnsw_index
     hipStream_t st = static_cast<hipStream_t>(stream);
 
     const uint32_t rf = row_floats(g->dim);
-    const size_t vec_bytes = static_cast<size_t>(g->n) * rf * 4;
+    const size_t vec_bytes = (static_cast<size_t>(g->n) + 1) * rf * 4;  // + one zero row
     const size_t adj0_bytes = static_cast<size_t>(g->n) * g->Mmax0 * 4;
     const size_t uoff_bytes = static_cast<size_t>(g->n) * 4;
     const size_t adjU_bytes = static_cast<size_t>(g->n_upper_rows) * g->Mmax * 4;

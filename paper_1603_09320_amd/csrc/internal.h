@@ -12,7 +12,7 @@ constexpr uint32_t kNoLink = 0xFFFFFFFFu;
 
 // Device-resident index as the kernels see it.
 struct DevIndex {
-    const float *vec;      // [n][stride4 * 4] fp32, rows zero padded
+    const float *vec;      // [n + 1][stride4 * 4] fp32, rows zero padded; row n is all zero
     const uint32_t *adj0;  // [n][Mmax0] layer-0 lists, kNoLink padded
     const int32_t *uoff;   // [n] row of layer 1 in adjU, -1 for level 0
     const uint32_t *adjU;  // [rows][Mmax] lists of layers >= 1

@@ -101,6 +101,28 @@ __device__ __forceinline__ bool visit(uint32_t *ht, uint32_t shift, uint32_t mas
     return true;  // run full: forget, score again
 }
 
+// One DPP move of both halves of a double (gfx9 DPP controls, full rows/banks).
+template <int CTRL>
+__device__ __forceinline__ double dpp_f64(double v) {
+    const uint64_t u = static_cast<uint64_t>(__double_as_longlong(v));
+    const uint32_t lo = static_cast<uint32_t>(__builtin_amdgcn_update_dpp(0, static_cast<int>(u), CTRL, 0xF, 0xF, false));
+    const uint32_t hi =
+        static_cast<uint32_t>(__builtin_amdgcn_update_dpp(0, static_cast<int>(u >> 32), CTRL, 0xF, 0xF, false));
+    return __longlong_as_double(static_cast<long long>((static_cast<uint64_t>(hi) << 32) | lo));
+}
+
+// Sum over aligned groups of G lanes (G in {1,2,4,8,16}); every lane of a
+// group ends with the same bits: each step adds two equal-shaped partial sums
+// (xor-1 and xor-2 swaps inside a quad, then the mirrored half-row and row).
+template <int G>
+__device__ __forceinline__ double group_sum(double v) {
+    if (G >= 2) v += dpp_f64<0xB1>(v);   // quad_perm [1,0,3,2]
+    if (G >= 4) v += dpp_f64<0x4E>(v);   // quad_perm [2,3,0,1]
+    if (G >= 8) v += dpp_f64<0x141>(v);  // row_half_mirror
+    if (G >= 16) v += dpp_f64<0x140>(v); // row_mirror
+    return v;
+}
+
 template <int G, int F>
 struct QueryRegs {
     double q[F][4];  // components 4c..4c+3 of float4 pieces c = sub + f*G
@@ -114,12 +136,17 @@ __device__ __forceinline__ void load_query(const float *qrow, uint32_t dim, Quer
 #pragma unroll
         for (int j = 0; j < 4; ++j) {
             const uint32_t e = 4u * static_cast<uint32_t>(sub + f * G) + j;
-            Q.q[f][j] = e < dim ? static_cast<double>(qrow[e]) : 0.0;
+            const float x = qrow[e < dim ? e : dim - 1];
+            Q.q[f][j] = e < dim ? static_cast<double>(x) : 0.0;
         }
 }
 
 // Scores ids[0..m) against the query; keys[slot] receives the key of ids[slot].
 // Lane group grp = lane / G handles slots grp, grp + P, ... (P = 64 / G).
+// Every load is unconditional so that all of a chunk's loads are in flight
+// together: an unused slot, and a piece beyond the end of a row, read from the
+// all-zero row n of the vector store instead (the address is chosen, not the
+// value, so no load is split or predicated).
 template <int G, int F, int METRIC>
 __device__ __forceinline__ void score_ids(const DevIndex &ix, const QueryRegs<G, F> &Q, const uint32_t *ids, int m,
                                           uint64_t *keys) {
@@ -128,18 +155,21 @@ __device__ __forceinline__ void score_ids(const DevIndex &ix, const QueryRegs<G,
     const int lane = lane_id();
     const int grp = lane / G, sub = lane % G;
     const float4 *vec = reinterpret_cast<const float4 *>(ix.vec);
+    const size_t zero_row = static_cast<size_t>(ix.n) * ix.stride4;
     for (int base = 0; base < m; base += P * B) {
-        float4 v[B][F];
         uint32_t idv[B];
 #pragma unroll
+        for (int b = 0; b < B; ++b) idv[b] = ids[(base + b * P + grp) & 63];
+#pragma unroll
+        for (int b = 0; b < B; ++b) idv[b] = base + b * P + grp < m ? idv[b] : ix.n;
+        float4 v[B][F];
+#pragma unroll
         for (int b = 0; b < B; ++b) {
-            const int slot = base + b * P + grp;
-            idv[b] = slot < m ? ids[slot] : kNoLink;
+            const size_t row = static_cast<size_t>(idv[b]) * ix.stride4;
 #pragma unroll
             for (int f = 0; f < F; ++f) {
                 const uint32_t c = static_cast<uint32_t>(sub + f * G);
-                v[b][f] = make_float4(0.f, 0.f, 0.f, 0.f);
-                if (idv[b] != kNoLink && c < ix.dv4) v[b][f] = vec[static_cast<size_t>(idv[b]) * ix.stride4 + c];
+                v[b][f] = vec[c < ix.stride4 ? row + c : zero_row];
             }
         }
 #pragma unroll
@@ -158,8 +188,7 @@ __device__ __forceinline__ void score_ids(const DevIndex &ix, const QueryRegs<G,
                     }
                 }
             }
-#pragma unroll
-            for (int o = G / 2; o > 0; o >>= 1) acc += __shfl_xor(acc, o, 64);
+            acc = group_sum<G>(acc);
             const int slot = base + b * P + grp;
             if (sub == 0 && slot < m) {
                 const double d = METRIC == HNSW_L2SQ ? acc : 1.0 - acc;
@@ -283,7 +312,8 @@ __global__ __launch_bounds__(64) void search_kernel(DevIndex ix, SearchArgs a) {
         for (;;) {
             const uint32_t cid = key_id(cur);
             const size_t row = static_cast<size_t>(ix.uoff[cid]) + static_cast<size_t>(lc - 1);
-            const uint32_t e = lane < static_cast<int>(ix.Mmax) ? ix.adjU[row * ix.Mmax + lane] : kNoLink;
+            const uint32_t ld = ix.adjU[row * ix.Mmax + min(lane, static_cast<int>(ix.Mmax) - 1)];
+            const uint32_t e = lane < static_cast<int>(ix.Mmax) ? ld : kNoLink;
             const bool valid = e != kNoLink;
             const uint64_t vm = __ballot(valid);
             const int m = __popcll(vm);
@@ -330,8 +360,8 @@ __global__ __launch_bounds__(64) void search_kernel(DevIndex ix, SearchArgs a) {
         if (lane == 0) s.W[c] = ck | 1ull;
         cursor = c + 1;
         const uint32_t cid = key_id(ck);
-        const uint32_t e = lane < static_cast<int>(ix.Mmax0) ? ix.adj0[static_cast<size_t>(cid) * ix.Mmax0 + lane]
-                                                              : kNoLink;
+        const uint32_t ld = ix.adj0[static_cast<size_t>(cid) * ix.Mmax0 + min(lane, static_cast<int>(ix.Mmax0) - 1)];
+        const uint32_t e = lane < static_cast<int>(ix.Mmax0) ? ld : kNoLink;
         const bool fresh = e != kNoLink && visit(s.ht, ht_shift, ht_mask, e);
         const uint64_t fm = __ballot(fresh);
         const int m = __popcll(fm);

@@ -121,7 +121,11 @@ typedef enum {
 
 /*
  * hnsw_search_batch with a mode and optional per-query counters.
- *   mode       hnsw_mode; BF16/FP8 need hnsw_index_add_lowp first.
+ *   mode       hnsw_mode; BF16/FP8 need hnsw_index_add_lowp first.  In
+ *              those modes the descent and the layer-0 search score the
+ *              low-precision copy (s * x in double, fp64 accumulation), and
+ *              every element of the final W is then re-scored from the fp32
+ *              vectors; the output is the K nearest by that exact distance.
  *   mlp        for HNSW_MODE_LEARNED: a network from hnsw_mlp_create (NULL
  *              otherwise); a NULL net in learned mode runs the plain search.
  *   counters   NULL or device u32 [n][4]: distance evaluations (all layers),
@@ -148,6 +152,24 @@ hnsw_status hnsw_search_batch_ex(const hnsw_index *index, const float *queries, 
 #define HNSW_BF_K_MAX 128u
 hnsw_status hnsw_bruteforce_knn(const hnsw_index *index, const float *queries, uint32_t n, uint32_t k,
                                 int32_t *ids_out, double *dists_out, void *stream);
+
+/*
+ * Add a low-precision copy of the vector store for HNSW_MODE_BF16 /
+ * HNSW_MODE_FP8 searches (quantised on the device from the fp32 rows; the
+ * call synchronises `stream`).  BF16: round to nearest even.  FP8: OCP E4M3
+ * with a per-vector fp32 scale s = max_j |x_j| / 448 (1 for an all-zero
+ * row); code = nearest E4M3 value of x_j / s, ties to even, saturating at 448.
+ * A second call for a kind already present is a no-op.
+ */
+hnsw_status hnsw_index_add_lowp(hnsw_index *index, int kind, void *stream);
+
+/*
+ * Layout and contents of a low-precision copy: layout[0] = bytes per row,
+ * layout[1] = 16-byte pieces holding values, layout[2] = byte offset of the
+ * FP8 row scale (0 for BF16).  host_out (optional) receives the n rows,
+ * [n][layout[0]] bytes (synchronous copy).
+ */
+hnsw_status hnsw_index_read_lowp(const hnsw_index *index, int kind, void *host_out, uint64_t layout[3]);
 
 /* Human-readable name of a status code (static storage). */
 const char *hnsw_status_str(hnsw_status s);

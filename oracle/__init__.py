@@ -74,6 +74,15 @@ def lib():
         L.or_import.restype = vp
         L.or_import.argtypes = [vp, u32, u32, u32, u32, u32, u32, C.c_int64, i32, vp, vp, vp]
         L.or_set_vectors.argtypes = [vp, vp]
+        L.or_set_lowp.argtypes = [vp, vp, vp]
+        L.or_quantize_bf16.argtypes = [vp, u64, u32, vp, vp]
+        L.or_quantize_fp8.argtypes = [vp, u64, u32, vp, vp, vp]
+        L.or_e4m3_value.restype = C.c_float
+        L.or_e4m3_value.argtypes = [C.c_uint8]
+        L.or_e4m3_rne.restype = C.c_uint8
+        L.or_e4m3_rne.argtypes = [C.c_float]
+        L.or_bf16_rne.restype = C.c_uint16
+        L.or_bf16_rne.argtypes = [C.c_float]
         _lib = L
     return _lib
 
@@ -196,12 +205,56 @@ class Graph:
         m = lib().or_search_layer(self._h, _p(q), _p(ep), len(ep), ef, lc, _p(ids), _p(ds), _p(nd))
         return ids[:m], ds[:m], int(nd[0])
 
+    def set_lowp(self, decoded, scale):
+        """Traverse over a low-precision copy (decoded values, per-vector scales) and
+        re-rank the final W with the fp32 vectors; ``None`` restores the plain search."""
+        if decoded is None:
+            lib().or_set_lowp(self._h, None, None)
+            self._lowp = None
+            return
+        dq = np.ascontiguousarray(decoded, dtype=np.float32)
+        sc = np.ascontiguousarray(scale, dtype=np.float32)
+        assert dq.shape == self.X.shape and sc.shape == (self.X.shape[0],)
+        self._lowp = (dq, sc)
+        lib().or_set_lowp(self._h, _p(dq), _p(sc))
+
     def select_heuristic(self, base_id: int, cand, M: int, lc: int = 0, extend=False, keep_pruned=False):
         cand = np.ascontiguousarray(cand, dtype=np.uint32)
         out = np.empty(max(M, 1) + len(cand), dtype=np.uint32)
         m = lib().or_select_heuristic(self._h, base_id, _p(cand), len(cand), M, lc, int(extend),
                                       int(keep_pruned), _p(out))
         return out[:m]
+
+
+def quantize_bf16(X):
+    """fp32 -> bf16 codes (round to nearest even) and their exact float values."""
+    X = np.ascontiguousarray(X, dtype=np.float32)
+    codes = np.empty(X.shape, dtype=np.uint16)
+    dec = np.empty(X.shape, dtype=np.float32)
+    lib().or_quantize_bf16(_p(X), X.shape[0], X.shape[1], _p(codes), _p(dec))
+    return codes, dec, np.ones(X.shape[0], dtype=np.float32)
+
+
+def quantize_fp8(X):
+    """fp32 -> per-vector scaled FP8-E4M3 codes, scales, and the codes' exact float values."""
+    X = np.ascontiguousarray(X, dtype=np.float32)
+    codes = np.empty(X.shape, dtype=np.uint8)
+    dec = np.empty(X.shape, dtype=np.float32)
+    sc = np.empty(X.shape[0], dtype=np.float32)
+    lib().or_quantize_fp8(_p(X), X.shape[0], X.shape[1], _p(codes), _p(sc), _p(dec))
+    return codes, dec, sc
+
+
+def e4m3_value(code: int) -> float:
+    return float(lib().or_e4m3_value(code))
+
+
+def e4m3_rne(x: float) -> int:
+    return int(lib().or_e4m3_rne(x))
+
+
+def bf16_rne(x: float) -> int:
+    return int(lib().or_bf16_rne(x))
 
 
 def bruteforce(X, Q, K: int, metric=L2, by_f32=False, nthreads: int = 1):

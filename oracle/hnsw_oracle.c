@@ -82,7 +82,10 @@ typedef struct {
     double mL;
     uint64_t seed;
     int heuristic, extend, keep_pruned;
+    int rerank;        /* re-score the final W with the fp32 vectors (Alg. 5's last line) */
     const float *X;    /* [n][dim], borrowed from the caller                */
+    const float *XQ;   /* [n][dim] decoded low-precision values, or NULL    */
+    const float *SQ;   /* [n] per-vector scale of XQ                         */
     uint8_t *level;    /* [n]                                               */
     uint32_t *cnt0;    /* [n]          layer-0 list lengths                 */
     uint32_t *adj0;    /* [n][Mmax0+1] layer-0 lists                        */
@@ -106,7 +109,27 @@ static uint32_t *nbr(const graph *g, uint32_t e, int lc, uint32_t **cnt) {
     return g->uadj + row * (g->Mmax + 1);
 }
 
+/*
+ * Distance to a low-precision copy: the stored value of coordinate j is
+ * s * xq_j, formed exactly in double (xq_j is a decoded bf16/fp8 value, s a
+ * float), so only the final rounding to float differs from exact arithmetic.
+ */
+static double dist64_q(int metric, const float *q, const float *xq, double s, uint32_t dim) {
+    double acc = 0.0;
+    if (metric == OR_L2) {
+        for (uint32_t j = 0; j < dim; ++j) {
+            double t = (double)q[j] - s * (double)xq[j];
+            acc += t * t;
+        }
+        return acc;
+    }
+    for (uint32_t j = 0; j < dim; ++j) acc += (double)q[j] * (s * (double)xq[j]);
+    return 1.0 - acc;
+}
+
 static float dkey(const graph *g, const float *q, uint32_t e) {
+    if (g->XQ)
+        return (float)dist64_q((int)g->metric, q, g->XQ + (uint64_t)e * g->dim, (double)g->SQ[e], g->dim);
     return (float)dist64((int)g->metric, q, g->X + (uint64_t)e * g->dim, g->dim);
 }
 
@@ -462,6 +485,9 @@ static void knn_search(const graph *g, searcher *s, const float *q, uint32_t K, 
         }
         search_layer(g, s, q, &ep, 1, efe, 0);
         nres = s->W.n;
+        if (g->rerank) /* K nearest of W by the exact distance to the fp32 vectors */
+            for (size_t i = 0; i < nres; ++i)
+                s->W.a[i].d = (float)dist64((int)g->metric, q, g->X + (uint64_t)s->W.a[i].id * g->dim, g->dim);
         qsort(s->W.a, nres, sizeof(item), cmp_item);
     }
     for (uint32_t k = 0; k < K; ++k) {
@@ -681,5 +707,96 @@ OR_EXPORT graph *or_import(const float *X, uint32_t n, uint32_t dim, uint32_t me
     return g;
 }
 
-/* Swap the vector store (same shape), e.g. for the dequantised low-precision copy. */
+/* Swap the vector store (same shape). */
 OR_EXPORT void or_set_vectors(graph *g, const float *X) { g->X = X; }
+
+/*
+ * Traverse over a low-precision copy (decoded values XQ [n][dim] and scales
+ * SQ [n]) and re-rank the final W with the fp32 vectors; NULL restores the
+ * plain search.
+ */
+OR_EXPORT void or_set_lowp(graph *g, const float *XQ, const float *SQ) {
+    g->XQ = XQ;
+    g->SQ = SQ;
+    g->rerank = XQ != NULL;
+}
+
+/* ------------------------------------------------------- quantisation */
+
+/* float -> bfloat16, round to nearest even (NaN kept quiet). */
+static uint16_t bf16_rne(float f) {
+    uint32_t u;
+    memcpy(&u, &f, 4);
+    if ((u & 0x7FFFFFFFu) > 0x7F800000u) return (uint16_t)((u >> 16) | 0x40u);
+    uint32_t lsb = (u >> 16) & 1u;
+    return (uint16_t)((u + 0x7FFFu + lsb) >> 16);
+}
+
+static float bf16_value(uint16_t b) {
+    uint32_t u = (uint32_t)b << 16;
+    float f;
+    memcpy(&f, &u, 4);
+    return f;
+}
+
+/*
+ * OCP FP8 E4M3: 1 sign, 4 exponent bits (bias 7), 3 mantissa bits; no
+ * infinities; S.1111.111 is NaN; largest finite magnitude 448 (S.1111.110);
+ * subnormals m * 2^-9.
+ */
+static float e4m3_value(uint8_t b) {
+    int sgn = b >> 7, e = (b >> 3) & 15, m = b & 7;
+    double v = e == 0 ? ldexp((double)m, -9) : ldexp(1.0 + m / 8.0, e - 7);
+    if (e == 15 && m == 7) v = NAN;
+    return (float)(sgn ? -v : v);
+}
+
+/* Nearest E4M3 code to a finite float, ties to the even code, saturating at +-448. */
+static uint8_t e4m3_rne(float f) {
+    uint8_t sgn = signbit(f) ? 0x80 : 0; /* E4M3 encodes -0 as S=1, all else 0 */
+    double a = fabs((double)f);
+    if (a >= 448.0) return sgn | 0x7E;
+    /* scan the 127 non-negative finite codes: they increase with the code */
+    uint8_t best = 0;
+    for (int c = 1; c <= 0x7E; ++c) {
+        double v = (double)e4m3_value((uint8_t)c);
+        if (v <= a) best = (uint8_t)c;
+    }
+    double lo = (double)e4m3_value(best);
+    if (best < 0x7E) {
+        double hi = (double)e4m3_value((uint8_t)(best + 1));
+        double dl = a - lo, dh = hi - a;
+        if (dh < dl || (dh == dl && (best & 1))) best = (uint8_t)(best + 1);
+    }
+    return (uint8_t)(sgn | best);
+}
+
+OR_EXPORT void or_quantize_bf16(const float *X, uint64_t n, uint32_t dim, uint16_t *out, float *decoded) {
+    for (uint64_t i = 0; i < n * dim; ++i) {
+        out[i] = bf16_rne(X[i]);
+        if (decoded) decoded[i] = bf16_value(out[i]);
+    }
+}
+
+/*
+ * Per-vector scaled FP8: s = max_j |x_j| / 448 (s = 1 for an all-zero row),
+ * code_j = E4M3 nearest to x_j / s (both divisions in float).
+ */
+OR_EXPORT void or_quantize_fp8(const float *X, uint64_t n, uint32_t dim, uint8_t *out, float *scale, float *decoded) {
+    for (uint64_t i = 0; i < n; ++i) {
+        const float *x = X + i * dim;
+        float mx = 0.0f;
+        for (uint32_t j = 0; j < dim; ++j) mx = fabsf(x[j]) > mx ? fabsf(x[j]) : mx;
+        float s = mx > 0.0f ? mx / 448.0f : 1.0f;
+        scale[i] = s;
+        for (uint32_t j = 0; j < dim; ++j) {
+            uint8_t c = e4m3_rne(x[j] / s);
+            out[i * dim + j] = c;
+            if (decoded) decoded[i * dim + j] = e4m3_value(c);
+        }
+    }
+}
+
+OR_EXPORT float or_e4m3_value(uint8_t b) { return e4m3_value(b); }
+OR_EXPORT uint8_t or_e4m3_rne(float f) { return e4m3_rne(f); }
+OR_EXPORT uint16_t or_bf16_rne(float f) { return bf16_rne(f); }

@@ -51,6 +51,8 @@ SIGNATURES = {
     "hnsw_search_batch": (C.c_int, [_vp, _vp, _u32, _u32, _u32, _vp, _vp, _vp]),
     "hnsw_search_batch_ex": (C.c_int, [_vp, _vp, _u32, _u32, _u32, _i32, _vp, _vp, _vp, _vp, _vp]),
     "hnsw_bruteforce_knn": (C.c_int, [_vp, _vp, _u32, _u32, _vp, _vp, _vp]),
+    "hnsw_index_add_lowp": (C.c_int, [_vp, _i32, _vp]),
+    "hnsw_index_read_lowp": (C.c_int, [_vp, _i32, _vp, _vp]),
 }
 
 _lib = None
@@ -125,6 +127,23 @@ class Index:
         _check("hnsw_index_info", lib().hnsw_index_info(self._h, _np(out)))
         keys = ["n", "dim", "metric", "M", "Mmax", "Mmax0", "max_level", "entry_point", "device_bytes"]
         return {k: int(v) for k, v in zip(keys, out)}
+
+    def add_lowp(self, kind: int, stream=None):
+        """Quantise the store on the device (``MODE_BF16`` or ``MODE_FP8``)."""
+        _check("hnsw_index_add_lowp", lib().hnsw_index_add_lowp(self._h, kind, _stream_ptr(stream)))
+
+    def read_lowp(self, kind: int):
+        """(codes, scales): the device copy as numpy (BF16 uint16 [n][dim];
+        FP8 uint8 [n][dim] and fp32 scales [n])."""
+        lay = np.zeros(3, dtype=np.uint64)
+        _check("hnsw_index_read_lowp", lib().hnsw_index_read_lowp(self._h, kind, None, _np(lay)))
+        row = int(lay[0])
+        raw = np.empty((self.n, row), dtype=np.uint8)
+        _check("hnsw_index_read_lowp", lib().hnsw_index_read_lowp(self._h, kind, _np(raw), _np(lay)))
+        if kind == MODE_BF16:
+            return raw.view(np.uint16)[:, :self.dim].copy(), np.ones(self.n, np.float32)
+        off = int(lay[2])
+        return raw[:, :self.dim].copy(), raw[:, off:off + 4].copy().view(np.float32)[:, 0]
 
     def close(self):
         if getattr(self, "_h", None):

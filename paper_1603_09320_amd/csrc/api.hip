@@ -211,7 +211,9 @@ hnsw_status hnsw_search_batch_ex(const hnsw_index *index, const float *queries, 
                                  void *stream) {
     if (!index) return HNSW_ERR_INVALID_ARG;
     if (k == 0 || ef == 0) return HNSW_ERR_INVALID_ARG;
-    if (mode != HNSW_MODE_PLAIN) return HNSW_ERR_UNSUPPORTED;
+    if (mode < HNSW_MODE_PLAIN || mode > HNSW_MODE_FP8) return HNSW_ERR_UNSUPPORTED;
+    if (mode == HNSW_MODE_BF16 && !index->ix.vbf16) return HNSW_ERR_INVALID_ARG;
+    if (mode == HNSW_MODE_FP8 && !index->ix.vfp8) return HNSW_ERR_INVALID_ARG;
     (void)mlp;
     const uint32_t efe = ef < k ? k : ef;
     if (efe > HNSW_EF_MAX) return HNSW_ERR_UNSUPPORTED;
@@ -228,6 +230,8 @@ hnsw_status hnsw_search_batch_ex(const hnsw_index *index, const float *queries, 
     a.dists = dists_out;
     a.counters = counters;
     a.wcap = (efe + 63) & ~63u;
+    a.wpow2 = 64;
+    while (a.wpow2 < a.wcap) a.wpow2 <<= 1;
     // visited table: about 8 slots per unit of ef, 1024..4096 slots
     uint32_t lg = 10;
     while (lg < 12 && (1u << lg) < 8u * efe) ++lg;
@@ -235,6 +239,69 @@ hnsw_status hnsw_search_batch_ex(const hnsw_index *index, const float *queries, 
     a.mode = mode;
     a.mlp = mlp;
     if (hnsw::launch_search(index->ix, a, static_cast<hipStream_t>(stream)) != hipSuccess) {
+        (void)hipGetLastError();
+        return HNSW_ERR_DEVICE;
+    }
+    return HNSW_OK;
+}
+
+hnsw_status hnsw_index_add_lowp(hnsw_index *index, int kind, void *stream) {
+    if (!index || (kind != HNSW_MODE_BF16 && kind != HNSW_MODE_FP8)) return HNSW_ERR_INVALID_ARG;
+    hnsw::DevIndex &ix = index->ix;
+    if ((kind == HNSW_MODE_BF16 && ix.vbf16) || (kind == HNSW_MODE_FP8 && ix.vfp8)) return HNSW_OK;
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    hnsw::DevIndex nx = ix;
+    size_t bytes;
+    if (kind == HNSW_MODE_BF16) {
+        nx.bf16_stride16 = ((ix.dim + 7) / 8 + 3) & ~3u;
+        bytes = (static_cast<size_t>(ix.n) + 1) * nx.bf16_stride16 * 16;
+    } else {
+        nx.fp8_pieces = (ix.dim + 15) / 16;
+        nx.fp8_scale_off = nx.fp8_pieces * 16;
+        nx.fp8_stride16 = ((nx.fp8_scale_off + 4 + 63) / 64) * 4;
+        bytes = (static_cast<size_t>(ix.n) + 1) * nx.fp8_stride16 * 16;
+    }
+    if (index->bytes + bytes > mem_cap()) return HNSW_ERR_OUT_OF_MEMORY;
+    void *p = nullptr;
+    if (hipMalloc(&p, bytes) != hipSuccess) {
+        (void)hipGetLastError();
+        return HNSW_ERR_OUT_OF_MEMORY;
+    }
+    bool ok = hipMemsetAsync(p, 0, bytes, st) == hipSuccess;
+    if (kind == HNSW_MODE_BF16) ok = ok && hnsw::launch_quantize_bf16(nx, static_cast<uint16_t *>(p), st) == hipSuccess;
+    else ok = ok && hnsw::launch_quantize_fp8(nx, static_cast<uint8_t *>(p), st) == hipSuccess;
+    ok = ok && hipStreamSynchronize(st) == hipSuccess;
+    if (!ok) {
+        (void)hipGetLastError();
+        (void)hipFree(p);
+        return HNSW_ERR_DEVICE;
+    }
+    if (kind == HNSW_MODE_BF16) {
+        ix.vbf16 = static_cast<uint16_t *>(p);
+        ix.bf16_stride16 = nx.bf16_stride16;
+    } else {
+        ix.vfp8 = static_cast<uint8_t *>(p);
+        ix.fp8_stride16 = nx.fp8_stride16;
+        ix.fp8_pieces = nx.fp8_pieces;
+        ix.fp8_scale_off = nx.fp8_scale_off;
+    }
+    index->allocations.push_back(p);
+    index->bytes += bytes;
+    return HNSW_OK;
+}
+
+hnsw_status hnsw_index_read_lowp(const hnsw_index *index, int kind, void *host_out, uint64_t layout[3]) {
+    if (!index || !layout) return HNSW_ERR_INVALID_ARG;
+    const hnsw::DevIndex &ix = index->ix;
+    const void *src = kind == HNSW_MODE_BF16 ? static_cast<const void *>(ix.vbf16)
+                                             : (kind == HNSW_MODE_FP8 ? static_cast<const void *>(ix.vfp8) : nullptr);
+    if (!src) return HNSW_ERR_INVALID_ARG;
+    const uint64_t row = kind == HNSW_MODE_BF16 ? ix.bf16_stride16 * 16ull : ix.fp8_stride16 * 16ull;
+    layout[0] = row;
+    layout[1] = kind == HNSW_MODE_BF16 ? ix.bf16_stride16 : ix.fp8_pieces;
+    layout[2] = kind == HNSW_MODE_FP8 ? ix.fp8_scale_off : 0;
+    if (!host_out) return HNSW_OK;
+    if (hipMemcpy(host_out, src, row * ix.n, hipMemcpyDeviceToHost) != hipSuccess) {
         (void)hipGetLastError();
         return HNSW_ERR_DEVICE;
     }

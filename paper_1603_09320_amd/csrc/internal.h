@@ -16,10 +16,13 @@ struct DevIndex {
     const uint32_t *adj0;  // [n][Mmax0] layer-0 lists, kNoLink padded
     const int32_t *uoff;   // [n] row of layer 1 in adjU, -1 for level 0
     const uint32_t *adjU;  // [rows][Mmax] lists of layers >= 1
-    const uint16_t *vbf16; // [n][stride4 * 4] BF16 copy or null
-    const uint8_t *vfp8;   // [n][fp8_stride] FP8-E4M3 copy or null
-    const float *scale8;   // [n] per-vector scale of the FP8 copy
-    uint32_t n, dim, dv4, stride4, fp8_stride;
+    const uint16_t *vbf16; // [n + 1][bf16_stride16 * 8] BF16 copy or null; row n all zero
+    const uint8_t *vfp8;   // [n + 1][fp8_stride16 * 16] FP8-E4M3 copy or null; row n all zero
+    uint32_t bf16_stride16;  // 16-byte pieces per BF16 row
+    uint32_t fp8_stride16;   // 16-byte pieces per FP8 row (values, scale, padding)
+    uint32_t fp8_pieces;     // pieces of an FP8 row that hold values
+    uint32_t fp8_scale_off;  // byte offset of the row's fp32 scale
+    uint32_t n, dim, dv4, stride4;
     uint32_t Mmax, Mmax0, entry, max_level, metric;
 };
 
@@ -31,6 +34,7 @@ struct SearchArgs {
     float *dists;          // [nq][k]
     uint32_t *counters;    // [nq][4] or null
     uint32_t wcap;         // capacity of W in LDS, multiple of 64, >= ef
+    uint32_t wpow2;        // power of two >= wcap (LDS reserved for W)
     uint32_t ht_log2;      // visited-table slots = 1 << ht_log2
     int mode;              // hnsw_mode
     const void *mlp;       // device parameters of the learned stop rule or null
@@ -41,7 +45,11 @@ struct SearchArgs {
 struct TileShape {
     int G, F;
 };
-TileShape tile_for_dim(uint32_t dim);
+TileShape tile_for(int kind, uint32_t dim);
+
+// Quantisation of the fp32 store into the low-precision copies.
+hipError_t launch_quantize_bf16(const DevIndex &ix, uint16_t *out, hipStream_t stream);
+hipError_t launch_quantize_fp8(const DevIndex &ix, uint8_t *out, hipStream_t stream);
 
 size_t search_lds_bytes(const SearchArgs &a);
 

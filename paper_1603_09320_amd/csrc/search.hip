@@ -123,71 +123,132 @@ __device__ __forceinline__ double group_sum(double v) {
     return v;
 }
 
-template <int G, int F>
-struct QueryRegs {
-    double q[F][4];  // components 4c..4c+3 of float4 pieces c = sub + f*G
+// Vector stores the traversal can read.  A row is a sequence of 16-byte
+// pieces: 4 fp32, 8 bf16 or 16 fp8-E4M3 values; the FP8 row carries its
+// fp32 scale at byte offset lp_scale_off.
+enum StoreKind { kF32 = 0, kBF16 = 1, kFP8 = 2 };
+
+template <int KIND>
+struct Store;
+template <>
+struct Store<kF32> {
+    static constexpr int VPP = 4;  // values per 16-byte piece
+    using QT = double;             // query element as held in registers
+};
+template <>
+struct Store<kBF16> {
+    static constexpr int VPP = 8;
+    using QT = float;
+};
+template <>
+struct Store<kFP8> {
+    static constexpr int VPP = 16;
+    using QT = float;
 };
 
-template <int G, int F>
-__device__ __forceinline__ void load_query(const float *qrow, uint32_t dim, QueryRegs<G, F> &Q) {
+// E4M3 (OCP) code -> float: exponent bias 7, 3 mantissa bits, subnormals m * 2^-9.
+__device__ __forceinline__ float e4m3_to_float(uint32_t b) {
+    const uint32_t e = (b >> 3) & 15u, m = b & 7u;
+    const float mag = e ? __uint_as_float(((e + 120u) << 23) | (m << 20)) : static_cast<float>(m) * 0x1.0p-9f;
+    return (b & 0x80u) ? -mag : mag;
+}
+
+// Value j of a 16-byte piece.
+template <int KIND>
+__device__ __forceinline__ float piece_value(const uint4 &p, int j) {
+    const uint32_t w = j < Store<KIND>::VPP / 4 ? p.x : (j < Store<KIND>::VPP / 2 ? p.y : (j < 3 * Store<KIND>::VPP / 4 ? p.z : p.w));
+    if (KIND == kF32) return __uint_as_float(w);
+    if (KIND == kBF16) return __uint_as_float((j & 1) ? (w & 0xFFFF0000u) : (w << 16));
+    return e4m3_to_float((w >> (8 * (j & 3))) & 0xFFu);
+}
+
+template <int G, int F, int KIND>
+struct QueryRegs {
+    typename Store<KIND>::QT q[F][Store<KIND>::VPP];  // values of pieces c = sub + f*G
+};
+
+template <int G, int F, int KIND>
+__device__ __forceinline__ void load_query(const float *qrow, uint32_t dim, QueryRegs<G, F, KIND> &Q) {
+    constexpr int V = Store<KIND>::VPP;
     const int sub = lane_id() % G;
 #pragma unroll
     for (int f = 0; f < F; ++f)
 #pragma unroll
-        for (int j = 0; j < 4; ++j) {
-            const uint32_t e = 4u * static_cast<uint32_t>(sub + f * G) + j;
+        for (int j = 0; j < V; ++j) {
+            const uint32_t e = static_cast<uint32_t>(V * (sub + f * G) + j);
             const float x = qrow[e < dim ? e : dim - 1];
-            Q.q[f][j] = e < dim ? static_cast<double>(x) : 0.0;
+            Q.q[f][j] = e < dim ? static_cast<typename Store<KIND>::QT>(x) : 0;
         }
+}
+
+// Where the pieces of a row live.
+struct RowSource {
+    const uint4 *base;   // piece 0 of row 0
+    uint32_t stride;     // pieces per row
+    uint32_t pieces;     // pieces holding values (the rest of the row is padding/scale)
+    uint32_t scale_off;  // FP8: byte offset of the scale within the row
+};
+
+__device__ __forceinline__ RowSource rows_of(const DevIndex &ix, const SearchArgs &a, int kind) {
+    if (kind == kF32) return {reinterpret_cast<const uint4 *>(ix.vec), ix.stride4, ix.stride4, 0};
+    if (kind == kBF16) return {reinterpret_cast<const uint4 *>(ix.vbf16), ix.bf16_stride16, ix.bf16_stride16, 0};
+    return {reinterpret_cast<const uint4 *>(ix.vfp8), ix.fp8_stride16, ix.fp8_pieces, ix.fp8_scale_off};
 }
 
 // Scores ids[0..m) against the query; keys[slot] receives the key of ids[slot].
 // Lane group grp = lane / G handles slots grp, grp + P, ... (P = 64 / G).
 // Every load is unconditional so that all of a chunk's loads are in flight
-// together: an unused slot, and a piece beyond the end of a row, read from the
-// all-zero row n of the vector store instead (the address is chosen, not the
-// value, so no load is split or predicated).
-template <int G, int F, int METRIC>
-__device__ __forceinline__ void score_ids(const DevIndex &ix, const QueryRegs<G, F> &Q, const uint32_t *ids, int m,
-                                          uint64_t *keys) {
+// together: an unused slot, and a piece beyond a row's values, read from the
+// all-zero row n instead (the address is chosen, not the value, so no load is
+// split or predicated).  Distances: sum over coordinates of (q_j - s*x_j)^2,
+// or 1 - sum q_j*s*x_j, in double (s = 1 except for FP8), rounded once to float.
+template <int G, int F, int METRIC, int KIND>
+__device__ __forceinline__ void score_ids(const DevIndex &ix, const RowSource &src, const QueryRegs<G, F, KIND> &Q,
+                                          const uint32_t *ids, int m, uint64_t *keys) {
     constexpr int P = 64 / G;
     constexpr int B = (32 / P) < 1 ? 1 : ((32 / P) > 4 ? 4 : (32 / P));
+    constexpr int V = Store<KIND>::VPP;
     const int lane = lane_id();
     const int grp = lane / G, sub = lane % G;
-    const float4 *vec = reinterpret_cast<const float4 *>(ix.vec);
-    const size_t zero_row = static_cast<size_t>(ix.n) * ix.stride4;
+    const size_t zero_row = static_cast<size_t>(ix.n) * src.stride;
     for (int base = 0; base < m; base += P * B) {
         uint32_t idv[B];
 #pragma unroll
         for (int b = 0; b < B; ++b) idv[b] = ids[(base + b * P + grp) & 63];
 #pragma unroll
         for (int b = 0; b < B; ++b) idv[b] = base + b * P + grp < m ? idv[b] : ix.n;
-        float4 v[B][F];
+        uint4 v[B][F];
+        float sc[B];
 #pragma unroll
         for (int b = 0; b < B; ++b) {
-            const size_t row = static_cast<size_t>(idv[b]) * ix.stride4;
+            const size_t row = static_cast<size_t>(idv[b]) * src.stride;
 #pragma unroll
             for (int f = 0; f < F; ++f) {
                 const uint32_t c = static_cast<uint32_t>(sub + f * G);
-                v[b][f] = vec[c < ix.stride4 ? row + c : zero_row];
+                v[b][f] = src.base[c < src.pieces ? row + c : zero_row];
             }
+            if (KIND == kFP8)
+                sc[b] = *reinterpret_cast<const float *>(reinterpret_cast<const uint8_t *>(src.base + row) +
+                                                         src.scale_off);
         }
 #pragma unroll
         for (int b = 0; b < B; ++b) {
             double acc = 0.0;
+            const double s = KIND == kFP8 ? static_cast<double>(sc[b]) : 1.0;
 #pragma unroll
-            for (int f = 0; f < F; ++f) {
-                const float x[4] = {v[b][f].x, v[b][f].y, v[b][f].z, v[b][f].w};
+            for (int f = 0; f < F; ++f)
 #pragma unroll
-                for (int j = 0; j < 4; ++j) {
+                for (int j = 0; j < V; ++j) {
+                    const double x = KIND == kFP8 ? s * static_cast<double>(piece_value<KIND>(v[b][f], j))
+                                                  : static_cast<double>(piece_value<KIND>(v[b][f], j));
+                    const double qj = static_cast<double>(Q.q[f][j]);
                     if (METRIC == HNSW_L2SQ) {
-                        const double t = Q.q[f][j] - static_cast<double>(x[j]);
+                        const double t = qj - x;
                         acc = __fma_rn(t, t, acc);
                     } else {
-                        acc = __fma_rn(Q.q[f][j], static_cast<double>(x[j]), acc);
+                        acc = __fma_rn(qj, x, acc);
                     }
                 }
-            }
             acc = group_sum<G>(acc);
             const int slot = base + b * P + grp;
             if (sub == 0 && slot < m) {
@@ -196,6 +257,41 @@ __device__ __forceinline__ void score_ids(const DevIndex &ix, const QueryRegs<G,
             }
         }
     }
+}
+
+// Exact fp32-input distance of one element, one lane alone (the re-rank of a
+// low-precision traversal): float4 pieces of the fp32 row, double accumulation.
+template <int METRIC>
+__device__ __forceinline__ float exact_dist(const DevIndex &ix, const float *qrow, uint32_t id) {
+    const float4 *row = reinterpret_cast<const float4 *>(ix.vec) + static_cast<size_t>(id) * ix.stride4;
+    const uint32_t full = ix.dim / 4;
+    double acc = 0.0;
+#pragma unroll 4
+    for (uint32_t c = 0; c < full; ++c) {
+        const float4 x = row[c];
+        const float xs[4] = {x.x, x.y, x.z, x.w};
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            const double qj = static_cast<double>(qrow[4 * c + j]);
+            if (METRIC == HNSW_L2SQ) {
+                const double t = qj - static_cast<double>(xs[j]);
+                acc = __fma_rn(t, t, acc);
+            } else {
+                acc = __fma_rn(qj, static_cast<double>(xs[j]), acc);
+            }
+        }
+    }
+    const float *rowf = reinterpret_cast<const float *>(row);
+    for (uint32_t e = 4 * full; e < ix.dim; ++e) {
+        const double qj = static_cast<double>(qrow[e]);
+        if (METRIC == HNSW_L2SQ) {
+            const double t = qj - static_cast<double>(rowf[e]);
+            acc = __fma_rn(t, t, acc);
+        } else {
+            acc = __fma_rn(qj, static_cast<double>(rowf[e]), acc);
+        }
+    }
+    return static_cast<float>(METRIC == HNSW_L2SQ ? acc : 1.0 - acc);
 }
 
 struct WaveLds {
@@ -209,7 +305,7 @@ struct WaveLds {
 __device__ __forceinline__ WaveLds carve(uint8_t *base, const SearchArgs &a) {
     WaveLds s;
     s.W = reinterpret_cast<uint64_t *>(base);
-    s.keys = s.W + a.wcap;
+    s.keys = s.W + a.wpow2;
     s.sorted = s.keys + 64;
     s.ids = reinterpret_cast<uint32_t *>(s.sorted + 64);
     s.ht = s.ids + 64;
@@ -283,16 +379,39 @@ __device__ __forceinline__ int merge_into_w(const WaveLds &s, int m, uint32_t ef
     return lbmin;
 }
 
-template <int G, int F, int METRIC>
+// Sorts W[0..n) ascending in LDS (n <= cap, cap a power of two; the tail is
+// padded with the largest key).
+__device__ __forceinline__ void sort_w(uint64_t *W, uint32_t n, uint32_t cap) {
+    const int lane = lane_id();
+    for (uint32_t i = n + lane; i < cap; i += 64) W[i] = ~0ull;
+    wave_sync();
+    for (uint32_t k = 2; k <= cap; k <<= 1)
+        for (uint32_t j = k >> 1; j > 0; j >>= 1) {
+            for (uint32_t t = lane; t < cap / 2; t += 64) {
+                const uint32_t i = 2 * j * (t / j) + (t % j), l = i + j;
+                const bool up = (i & k) == 0;
+                const uint64_t x = W[i], y = W[l];
+                if ((x > y) == up) {
+                    W[i] = y;
+                    W[l] = x;
+                }
+            }
+            wave_sync();
+        }
+}
+
+template <int G, int F, int METRIC, int KIND>
 __global__ __launch_bounds__(64) void search_kernel(DevIndex ix, SearchArgs a) {
     extern __shared__ __align__(16) uint8_t smem[];
     const uint32_t qi = blockIdx.x;
     if (qi >= a.nq) return;
     const int lane = lane_id();
     WaveLds s = carve(smem, a);
+    const RowSource src = rows_of(ix, a, KIND);
+    const float *qrow = a.queries + static_cast<size_t>(qi) * ix.dim;
 
-    QueryRegs<G, F> Q;
-    load_query<G, F>(a.queries + static_cast<size_t>(qi) * ix.dim, ix.dim, Q);
+    QueryRegs<G, F, KIND> Q;
+    load_query<G, F, KIND>(qrow, ix.dim, Q);
 
     const uint32_t ht_slots = 1u << a.ht_log2;
     for (uint32_t i = lane; i < ht_slots; i += 64) s.ht[i] = kNoLink;
@@ -302,7 +421,7 @@ __global__ __launch_bounds__(64) void search_kernel(DevIndex ix, SearchArgs a) {
     // Entry point (Alg. 5): its distance seeds the descent.
     if (lane == 0) s.ids[0] = ix.entry;
     wave_sync();
-    score_ids<G, F, METRIC>(ix, Q, s.ids, 1, s.keys);
+    score_ids<G, F, METRIC, KIND>(ix, src, Q, s.ids, 1, s.keys);
     wave_sync();
     uint64_t cur = s.keys[0];
     n_dist += 1;
@@ -319,7 +438,7 @@ __global__ __launch_bounds__(64) void search_kernel(DevIndex ix, SearchArgs a) {
             const int m = __popcll(vm);
             if (valid) s.ids[rank_in(vm)] = e;
             wave_sync();
-            score_ids<G, F, METRIC>(ix, Q, s.ids, m, s.keys);
+            score_ids<G, F, METRIC, KIND>(ix, src, Q, s.ids, m, s.keys);
             wave_sync();
             uint64_t best = cur;
             for (int i = lane; i < m; i += 64) best = s.keys[i] < best ? s.keys[i] : best;
@@ -367,12 +486,25 @@ __global__ __launch_bounds__(64) void search_kernel(DevIndex ix, SearchArgs a) {
         const int m = __popcll(fm);
         if (fresh) s.ids[rank_in(fm)] = e;
         wave_sync();
-        score_ids<G, F, METRIC>(ix, Q, s.ids, m, s.keys);
+        score_ids<G, F, METRIC, KIND>(ix, src, Q, s.ids, m, s.keys);
         wave_sync();
         n_dist0 += m;
         n_exp0 += 1;
         const int lbmin = merge_into_w(s, m, ef, wsize);
         if (lbmin < cursor) cursor = lbmin;
+    }
+
+    uint32_t n_rerank = 0;
+    if (KIND != kF32) {
+        // Low-precision traversal: re-score every element of W exactly from the
+        // fp32 vectors and keep the K nearest by that distance.
+        for (uint32_t i = lane; i < wsize; i += 64) {
+            const uint32_t id = key_id(s.W[i]);
+            s.W[i] = make_key(exact_dist<METRIC>(ix, qrow, id), id);
+        }
+        wave_sync();
+        sort_w(s.W, wsize, a.wpow2);
+        n_rerank = wsize;
     }
 
     // The K nearest of W (Alg. 5, last line); W is sorted.
@@ -389,49 +521,74 @@ __global__ __launch_bounds__(64) void search_kernel(DevIndex ix, SearchArgs a) {
     }
     if (a.counters && lane == 0) {
         uint32_t *c4 = a.counters + static_cast<size_t>(qi) * 4;
-        c4[0] = n_dist + n_dist0;
+        c4[0] = n_dist + n_dist0 + n_rerank;
         c4[1] = n_exp + n_exp0;
         c4[2] = n_dist0;
         c4[3] = n_exp0;
     }
 }
 
-template <int G, int F>
-hipError_t launch_gf(const DevIndex &ix, const SearchArgs &a, hipStream_t stream) {
+template <int G, int F, int KIND>
+hipError_t launch_gfk(const DevIndex &ix, const SearchArgs &a, hipStream_t stream) {
     const size_t lds = search_lds_bytes(a);
     if (ix.metric == HNSW_IP)
-        hipLaunchKernelGGL((search_kernel<G, F, HNSW_IP>), dim3(a.nq), dim3(64), lds, stream, ix, a);
+        hipLaunchKernelGGL((search_kernel<G, F, HNSW_IP, KIND>), dim3(a.nq), dim3(64), lds, stream, ix, a);
     else
-        hipLaunchKernelGGL((search_kernel<G, F, HNSW_L2SQ>), dim3(a.nq), dim3(64), lds, stream, ix, a);
+        hipLaunchKernelGGL((search_kernel<G, F, HNSW_L2SQ, KIND>), dim3(a.nq), dim3(64), lds, stream, ix, a);
     return hipGetLastError();
+}
+
+template <int KIND>
+hipError_t launch_kind(const DevIndex &ix, const SearchArgs &a, hipStream_t stream) {
+    const TileShape t = tile_for(KIND, ix.dim);
+    switch (t.G * 16 + t.F) {
+        case 1 * 16 + 1: return launch_gfk<1, 1, KIND>(ix, a, stream);
+        case 2 * 16 + 1: return launch_gfk<2, 1, KIND>(ix, a, stream);
+        case 2 * 16 + 2: return launch_gfk<2, 2, KIND>(ix, a, stream);
+        case 4 * 16 + 1: return launch_gfk<4, 1, KIND>(ix, a, stream);
+        case 4 * 16 + 2: return launch_gfk<4, 2, KIND>(ix, a, stream);
+        case 8 * 16 + 1: return launch_gfk<8, 1, KIND>(ix, a, stream);
+        case 8 * 16 + 2: return launch_gfk<8, 2, KIND>(ix, a, stream);
+        case 16 * 16 + 1: return launch_gfk<16, 1, KIND>(ix, a, stream);
+        case 16 * 16 + 2: return launch_gfk<16, 2, KIND>(ix, a, stream);
+        case 16 * 16 + 4: return launch_gfk<16, 4, KIND>(ix, a, stream);
+        default: return hipErrorInvalidValue;
+    }
 }
 
 }  // namespace
 
-TileShape tile_for_dim(uint32_t dim) {
-    const uint32_t dv4 = (dim + 3) / 4;
-    if (dv4 <= 1) return {1, 1};
-    if (dv4 <= 4) return {2, 2};
-    if (dv4 <= 8) return {4, 2};
-    if (dv4 <= 16) return {8, 2};
-    if (dv4 <= 32) return {16, 2};
-    return {16, 4};
+// Lane-group tile for a store: G lanes per vector, F pieces per lane.
+// fp32 rows use two pieces per lane up to 128 dimensions; low-precision
+// rows (8 or 16 values per piece) use one piece per lane up to 16 pieces.
+TileShape tile_for(int kind, uint32_t dim) {
+    const uint32_t vpp = kind == kF32 ? 4 : (kind == kBF16 ? 8 : 16);
+    const uint32_t pieces = (dim + vpp - 1) / vpp;
+    if (kind == kF32) {
+        if (pieces <= 1) return {1, 1};
+        if (pieces <= 4) return {2, 2};
+        if (pieces <= 8) return {4, 2};
+        if (pieces <= 16) return {8, 2};
+        if (pieces <= 32) return {16, 2};
+        return {16, 4};
+    }
+    if (pieces <= 1) return {1, 1};
+    if (pieces <= 2) return {2, 1};
+    if (pieces <= 4) return {4, 1};
+    if (pieces <= 8) return {8, 1};
+    if (pieces <= 16) return {16, 1};
+    return {16, 2};
 }
 
 size_t search_lds_bytes(const SearchArgs &a) {
-    return static_cast<size_t>(a.wcap) * 8 + 64 * 8 * 2 + 64 * 4 + (static_cast<size_t>(1) << a.ht_log2) * 4;
+    return static_cast<size_t>(a.wpow2) * 8 + 64 * 8 * 2 + 64 * 4 + (static_cast<size_t>(1) << a.ht_log2) * 4;
 }
 
 hipError_t launch_search(const DevIndex &ix, const SearchArgs &a, hipStream_t stream) {
-    const TileShape t = tile_for_dim(ix.dim);
-    switch (t.G * 16 + t.F) {
-        case 1 * 16 + 1: return launch_gf<1, 1>(ix, a, stream);
-        case 2 * 16 + 2: return launch_gf<2, 2>(ix, a, stream);
-        case 4 * 16 + 2: return launch_gf<4, 2>(ix, a, stream);
-        case 8 * 16 + 2: return launch_gf<8, 2>(ix, a, stream);
-        case 16 * 16 + 2: return launch_gf<16, 2>(ix, a, stream);
-        case 16 * 16 + 4: return launch_gf<16, 4>(ix, a, stream);
-        default: return hipErrorInvalidValue;
+    switch (a.mode) {
+        case HNSW_MODE_BF16: return launch_kind<kBF16>(ix, a, stream);
+        case HNSW_MODE_FP8: return launch_kind<kFP8>(ix, a, stream);
+        default: return launch_kind<kF32>(ix, a, stream);
     }
 }
 

@@ -1,0 +1,116 @@
+"""Low-precision traversal (BF16 / FP8-E4M3 with per-vector scale) plus an
+exact fp32 re-rank, on the GPU through the C ABI, against the oracle."""
+import numpy as np
+import pytest
+
+import oracle
+import synthdata
+from tests import parity
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module")
+def hnsw():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_1603_09320_amd as h
+
+    h.lib()
+    return h
+
+
+def _special_rows(dim):
+    rows = [np.zeros(dim), np.full(dim, 1e-30), np.linspace(-3, 3, dim), np.full(dim, -7.0)]
+    r = np.linspace(-448.0, 448.0, dim)
+    r[::3] *= 1e-3
+    rows.append(r)
+    rows.append(np.geomspace(1e-6, 1e6, dim) * np.where(np.arange(dim) % 2, 1, -1))
+    return np.array(rows, dtype=np.float32)
+
+
+@pytest.mark.parametrize("workload,n", [("deep_like", 20000), ("sift_like", 5000), ("glove_like", 5000)])
+def test_quantized_codes_match_oracle(hnsw, workload, n):
+    print(f"case quantize {workload} n={n}", flush=True)
+    X = synthdata.base(workload, n)
+    X = np.concatenate([X, _special_rows(X.shape[1])])
+    idx = hnsw.Index(dict(n=len(X), dim=X.shape[1], metric=0, M=4, Mmax=4, Mmax0=4, max_level=0, entry_point=0,
+                          levels=np.zeros(len(X), np.uint8), adj0=np.full((len(X), 4), 0xFFFFFFFF, np.uint32),
+                          upper_off=np.full(len(X), -1, np.int32), adjU=np.zeros((0, 4), np.uint32)), X)
+    idx.add_lowp(hnsw.MODE_BF16)
+    idx.add_lowp(hnsw.MODE_FP8)
+    gb, _ = idx.read_lowp(hnsw.MODE_BF16)
+    ob, _, _ = oracle.quantize_bf16(X)
+    assert np.array_equal(gb, ob)
+    g8, gs = idx.read_lowp(hnsw.MODE_FP8)
+    o8, _, osc = oracle.quantize_fp8(X)
+    assert np.array_equal(gs, osc)
+    assert np.array_equal(g8, o8)
+
+
+def _lowp_parity(hnsw, X, Q, G, K, ef, kind, metric):
+    p = G.packed()
+    idx = hnsw.Index(p, X)
+    idx.add_lowp(kind)
+    ids, ds, cnt = idx.search(torch.from_numpy(Q).cuda(), K, ef, mode=kind, counters=True)
+    torch.cuda.synchronize()
+    ids, ds, cnt = ids.cpu().numpy(), ds.cpu().numpy(), cnt.cpu().numpy().astype(np.uint32)
+    codes, dec, sc = (oracle.quantize_bf16 if kind == hnsw.MODE_BF16 else oracle.quantize_fp8)(X)
+    G.set_lowp(dec, sc)
+    oi, od, oc = G.search(Q, K, ef, nthreads=8, counters=True)
+    G.set_lowp(None, None)
+    r = parity.compare(ids, ds, oi, od, X, Q, metric)
+    print(f"lowp kind={kind} K={K} ef={ef}: {r['equal']} equal, {r['exempt']} exempt, {r['fail']} fail", flush=True)
+    assert r["fail"] == 0 and r["exempt"] == 0
+    assert np.array_equal(cnt[:, 3], oc[:, 3].astype(np.uint32))
+    return ids, ds
+
+
+@pytest.mark.parametrize("kind", [1, 2])
+def test_lowp_parity_deep_like(hnsw, kind):
+    print(f"case lowp deep_like 20k x 96 kind={kind}", flush=True)
+    X = synthdata.base("deep_like", 20000)
+    Q = synthdata.queries("deep_like", 300)
+    G = oracle.Graph.build(X, M=24, efC=100, seed=4003)
+    for ef in (10, 64, 256):
+        _lowp_parity(hnsw, X, Q, G, 10, ef, kind, oracle.L2)
+
+
+@pytest.mark.parametrize("kind", [1, 2])
+def test_lowp_parity_inner_product_and_dims(hnsw, kind):
+    print(f"case lowp glove_like 8k x 100 IP kind={kind}", flush=True)
+    X = synthdata.base("glove_like", 8000)
+    Q = synthdata.queries("glove_like", 200)
+    G = oracle.Graph.build(X, metric=oracle.IP, M=16, efC=80, seed=3004)
+    _lowp_parity(hnsw, X, Q, G, 10, 100, kind, oracle.IP)
+    for dim in (3, 17, 40, 130, 256):
+        rng = np.random.default_rng(dim)
+        X = rng.normal(size=(2500, dim)).astype(np.float32)
+        Q = rng.normal(size=(100, dim)).astype(np.float32)
+        G = oracle.Graph.build(X, M=8, efC=40, seed=2)
+        _lowp_parity(hnsw, X, Q, G, 10, 50, kind, oracle.L2)
+
+
+def test_bf16_equals_fp32_on_integer_data(hnsw):
+    """Integer coordinates are exact in BF16: the BF16 search returns exactly the fp32 search's output."""
+    X = synthdata.base("sift_like", 30000)
+    Q = synthdata.queries("sift_like", 500)
+    G = oracle.Graph.build(X, M=16, efC=200, seed=2003)
+    idx = hnsw.Index(G.packed(), X)
+    idx.add_lowp(hnsw.MODE_BF16)
+    q = torch.from_numpy(Q).cuda()
+    for ef in (10, 64, 300):
+        a = idx.search(q, 10, ef)
+        b = idx.search(q, 10, ef, mode=hnsw.MODE_BF16)
+        torch.cuda.synchronize()
+        assert torch.equal(a[0], b[0]) and torch.equal(a[1], b[1])
+
+
+def test_lowp_requires_copy(hnsw):
+    X = synthdata.base("uniform16", 500)
+    G = oracle.Graph.build(X, M=8, efC=20, seed=1)
+    idx = hnsw.Index(G.packed(), X)
+    with pytest.raises(hnsw.HnswError) as e:
+        idx.search(torch.from_numpy(X[:3]).cuda(), 5, 10, mode=hnsw.MODE_FP8)
+    assert e.value.code == 1

@@ -5,12 +5,16 @@ sigma 20, integer coordinates 0..255), graph built by the oracle's INSERT
 with M = 16, Mmax0 = 32, efConstruction = 200; 10,000 seeded queries, K = 10.
 A step is one batched search of all 10,000 queries (one kernel launch).
 
-The ef sweep picks the smallest swept ef whose mean tie-aware recall@10
-against exact brute force reaches 0.95; that ef is timed.  Recall ground
-truth: the library's exact brute-force kernel (checked against the oracle's
-brute force by the test suite).  Printed: one JSON line.
+For every form of the search (plain fp32 traversal, BF16 and FP8-E4M3
+traversal with an exact fp32 re-rank, and the learned early-termination
+search where a trained net is given) the ef sweep picks the smallest swept
+ef whose mean tie-aware recall@10 against exact brute force reaches 0.95;
+that ef is timed.  `value` is the plain form's throughput; every form is
+reported under `forms`.  Recall ground truth comes from the library's exact
+brute-force kernel (checked against the oracle's brute force by the tests).
+Printed: one JSON line.
 
-    python bench.py [--gpus 1] [--steps 20] [--warmup 3]
+    python bench.py [--gpus 1] [--steps 20] [--warmup 3] [--workload sift_like]
 """
 from __future__ import annotations
 
@@ -27,12 +31,15 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 WORKLOADS = {
-    # name: (graph file, number of base vectors, queries, K)
+    # name: (graph file, base vectors, queries, K)
     "sift_like": ("graphs/sift_like_1M.bin", 1_000_000, 10_000, 10),
     "glove_like": ("graphs/glove_like_1200k.bin", 1_200_000, 10_000, 10),
+    "deep_like": ("graphs/deep_like_1M.bin", 1_000_000, 10_000, 10),
+    "uniform4": ("graphs/uniform4_1M.bin", 1_000_000, 10_000, 10),
 }
 EF_SWEEP = [10, 16, 24, 32, 48, 64, 96, 128, 192, 256, 384, 512, 800]
 HBM_PEAK_GBS = 8000.0
+METRIC = "QPS at recall@10≥0.95, plain vs learned/low-precision; HBM GB/s"
 
 
 def log(msg):
@@ -59,14 +66,23 @@ def recall(ids, X, Q, gt_d64, metric=0):
     return (d <= gt_d64[:, K - 1:K]).sum(1) / K
 
 
-def algorithmic_bytes(cnt, dim, K, Mmax, Mmax0, vec_bytes):
+def row_bytes(mode: int, dim: int) -> int:
+    """Bytes of one vector as the traversal reads it (values only, plus the FP8 scale)."""
+    return {0: 4 * dim, 1: 2 * dim, 2: dim + 4, 3: 4 * dim}[mode]
+
+
+def algorithmic_bytes(cnt, graph, K, mode, ef):
     """Bytes the method must move per step: one adjacency row per expansion
-    (layer 0: 4*Mmax0, upper: 4*Mmax), one vector per distance evaluation,
-    the query and the K results."""
+    (layer 0: 4*Mmax0, upper layers: 4*Mmax), one vector per distance
+    evaluation, the query and the K results; the low-precision forms add one
+    fp32 row per re-ranked element of W."""
     c = cnt.astype(np.int64)
+    dim = graph["dim"]
     exp_u = c[:, 1] - c[:, 3]
-    dist_u = c[:, 0] - c[:, 2]
-    per_q = c[:, 3] * 4 * Mmax0 + exp_u * 4 * Mmax + (c[:, 2] + dist_u) * vec_bytes + 4 * dim + 8 * K
+    rer = np.minimum(ef, graph["n"]) if mode in (1, 2) else 0
+    trav = c[:, 0] - rer
+    per_q = (c[:, 3] * 4 * graph["Mmax0"] + exp_u * 4 * graph["Mmax"] + trav * row_bytes(mode, dim)
+             + rer * 4 * dim + 4 * dim + 8 * K)
     return int(per_q.sum())
 
 
@@ -94,7 +110,6 @@ def cpu_baseline(graph, X, Q, K, ef, seconds=15.0):
     t0 = time.time()
     G.search(Q[:n], K, ef, nthreads=threads)
     dt = time.time() - t0
-    # grow the sample toward the time budget
     n2 = int(min(len(Q), max(n, n * seconds / max(dt, 1e-3) * 0.5)))
     if n2 > n:
         t0 = time.time()
@@ -104,13 +119,59 @@ def cpu_baseline(graph, X, Q, K, ef, seconds=15.0):
             "sample": f"first {n} of {len(Q)} queries, K={K}, ef={ef}, same graph"}
 
 
+class Runner:
+    def __init__(self, index, q, X, Q, K, gt_d64, metric, stream, mlp=None):
+        self.index, self.q, self.X, self.Q, self.K = index, q, X, Q, K
+        self.gt, self.metric, self.stream, self.mlp = gt_d64, metric, stream, mlp
+
+    def search(self, ef, mode, out=None, counters=False):
+        return self.index.search(self.q, self.K, ef, mode=mode, mlp=self.mlp if mode == 3 else None,
+                                 counters=counters, out=out)
+
+    def sweep(self, mode, efs, target):
+        import torch
+
+        curve = []
+        for ef in efs:
+            ids, _ = self.search(ef, mode)
+            torch.cuda.synchronize()
+            r = float(recall(ids.cpu().numpy(), self.X, self.Q, self.gt, self.metric).mean())
+            curve.append({"ef": ef, "recall": round(r, 5)})
+            log(f"[bench] mode={mode} ef={ef} recall@{self.K}={r:.4f}")
+            if r >= target:
+                return ef, r, curve
+        return curve[-1]["ef"], curve[-1]["recall"], curve
+
+    def time(self, ef, mode, steps, warmup):
+        import torch
+
+        n = self.q.shape[0]
+        dev = self.q.device
+        ids = torch.empty((n, self.K), dtype=torch.int32, device=dev)
+        dists = torch.empty((n, self.K), dtype=torch.float32, device=dev)
+        for _ in range(warmup):
+            self.search(ef, mode, out=(ids, dists))
+        torch.cuda.synchronize()
+        evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(steps)]
+        t0 = time.perf_counter()
+        for s, e in evs:
+            s.record(self.stream)
+            self.search(ef, mode, out=(ids, dists))
+            e.record(self.stream)
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        return wall * 1000.0 / steps, float(np.mean([s.elapsed_time(e) for s, e in evs]))
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="sift_like", choices=sorted(WORKLOADS))
-    ap.add_argument("--ef", type=int, default=0, help="time this ef instead of sweeping")
+    ap.add_argument("--ef", type=int, default=0, help="time this ef (plain form only) instead of sweeping")
+    ap.add_argument("--forms", default="plain,bf16,fp8,learned",
+                    help="comma list of plain,bf16,fp8,learned (learned needs a trained net file)")
     ap.add_argument("--target-recall", type=float, default=0.95)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--copy-probe-bytes", type=int, default=0,
@@ -118,7 +179,7 @@ def main():
     a = ap.parse_args()
     if a.gpus != 1:
         print(f"bench.py runs on one GPU only; --gpus {a.gpus} is not supported "
-              "(the path shards by queries with a replicated index, see the design notes)", file=sys.stderr)
+              "(the path shards by queries over replicated indices; not built here)", file=sys.stderr)
         sys.exit(2)
 
     import torch
@@ -139,8 +200,8 @@ def main():
     log(f"[bench] {a.workload}: n={graph['n']} dim={graph['dim']} nq={nq} K={K} L={graph['max_level']}")
     index = hnsw.Index(graph, X)
     q = torch.from_numpy(Q).to(dev)
-
     stream = torch.cuda.current_stream()
+
     # exact ground truth on the GPU (matrix-core scan + fp64 rerank), timed
     hnsw.bruteforce(index, q[:64], K)
     torch.cuda.synchronize()
@@ -153,46 +214,42 @@ def main():
     gt_d64 = gt_d.cpu().numpy()
     log(f"[bench] brute-force ground truth: {nq} queries in {bf_ms:.1f} ms")
 
-    sweep = []
-    chosen = None
-    for ef in ([a.ef] if a.ef else EF_SWEEP):
-        ids, ds = index.search(q, K, ef)
+    mlp = None
+    forms = [f for f in a.forms.split(",") if f]
+    if "learned" in forms:
+        mpath = os.path.join(ROOT, "graphs", f"{a.workload}.mlp.npz")
+        if os.path.exists(mpath) and hasattr(hnsw, "Mlp"):
+            mlp = hnsw.Mlp.load(mpath)
+        else:
+            forms.remove("learned")
+    run = Runner(index, q, X, Q, K, gt_d64, graph["metric"], stream, mlp)
+    mode_of = {"plain": 0, "bf16": 1, "fp8": 2, "learned": 3}
+    results = {}
+    for form in forms:
+        mode = mode_of[form]
+        if mode in (1, 2):
+            index.add_lowp(mode)
+        if form == "plain" and a.ef:
+            ids, _ = run.search(a.ef, 0)
+            torch.cuda.synchronize()
+            ef, rec = a.ef, float(recall(ids.cpu().numpy(), X, Q, gt_d64, graph["metric"]).mean())
+            curve = [{"ef": ef, "recall": round(rec, 5)}]
+        else:
+            ef, rec, curve = run.sweep(mode, EF_SWEEP, a.target_recall)
+        _, _, cnt = run.search(ef, mode, counters=True)
         torch.cuda.synchronize()
-        r = float(recall(ids.cpu().numpy(), X, Q, gt_d64, graph["metric"]).mean())
-        sweep.append({"ef": ef, "recall": round(r, 5)})
-        log(f"[bench] ef={ef} recall@{K}={r:.4f}")
-        if chosen is None and (r >= a.target_recall or a.ef):
-            chosen = (ef, r)
-            break
-    if chosen is None:
-        chosen = (sweep[-1]["ef"], sweep[-1]["recall"])
-    ef, rec = chosen
-
-    _, _, cnt = index.search(q, K, ef, counters=True)
-    torch.cuda.synchronize()
-    cnt = cnt.cpu().numpy().astype(np.uint32)
-    vec_bytes = graph["dim"] * 4
-    alg_bytes = algorithmic_bytes(cnt, graph["dim"], K, graph["Mmax"], graph["Mmax0"], vec_bytes)
-
-    ids = torch.empty((nq, K), dtype=torch.int32, device=dev)
-    dists = torch.empty((nq, K), dtype=torch.float32, device=dev)
-    for _ in range(a.warmup):
-        index.search(q, K, ef, out=(ids, dists))
-    torch.cuda.synchronize()
-    evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(a.steps)]
-    t0 = time.perf_counter()
-    for s, e in evs:
-        s.record(stream)
-        index.search(q, K, ef, out=(ids, dists))
-        e.record(stream)
-    torch.cuda.synchronize()
-    wall = time.perf_counter() - t0
-    kern_ms = float(np.mean([s.elapsed_time(e) for s, e in evs]))
-    ms_per_step = wall * 1000.0 / a.steps
-    qps = nq / (ms_per_step / 1000.0)
-    achieved = alg_bytes / (kern_ms / 1000.0) / 1e9
-    khash = kernel_source_hash()
-    traffic = load_traffic(khash, a.workload, ef)
+        cnt = cnt.cpu().numpy().astype(np.uint32)
+        ms, kern_ms = run.time(ef, mode, a.steps, a.warmup)
+        alg = algorithmic_bytes(cnt, graph, K, mode, ef)
+        c = cnt.astype(np.float64)
+        results[form] = {"ef": ef, "recall": round(rec, 5), "qps": round(nq / (ms / 1000.0), 1),
+                         "ms_per_step": round(ms, 4), "kernel_ms": round(kern_ms, 4),
+                         "algorithmic_GBs": round(alg / (kern_ms / 1000.0) / 1e9, 1),
+                         "bytes_per_query": round(alg / nq, 1),
+                         "dist_evals_per_query": round(float(c[:, 0].mean()), 2),
+                         "expansions_per_query": round(float(c[:, 1].mean()), 2),
+                         "sweep": curve}
+        log(f"[bench] {form}: {results[form]}")
 
     if a.copy_probe_bytes:
         src = torch.ones(a.copy_probe_bytes // 4, dtype=torch.float32, device=dev)
@@ -203,36 +260,37 @@ def main():
         log(f"[bench] copy probe: {a.copy_probe_bytes} bytes read and written, twice")
         del src, dst
 
+    head = results.get("plain") or next(iter(results.values()))
     cpu = None
     if not a.no_cpu_baseline:
-        cpu = cpu_baseline(graph, X, Q, K, ef)
+        cpu = cpu_baseline(graph, X, Q, K, head["ef"])
         log(f"[bench] cpu baseline: {cpu}")
-
-    c = cnt.astype(np.float64)
+    khash = kernel_source_hash()
+    achieved = head["algorithmic_GBs"]
+    alg_launch = int(round(head["bytes_per_query"] * nq))
     out = {
-        "metric": f"QPS at recall@{K}>=0.95 (plain fp32 path)",
-        "value": round(qps, 1),
+        "metric": METRIC,
+        "value": head["qps"],
         "unit": "queries/s",
         "n_gpus": 1,
         "steps": a.steps,
         "warmup": a.warmup,
-        "ms_per_step": round(ms_per_step, 4),
+        "ms_per_step": head["ms_per_step"],
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
         "dtype": "f32",
         "data": "synthetic",
-        "config": {"workload": f"{a.workload} {graph['n']}x{graph['dim']}, {nq} queries, K={K}",
-                   "ef": ef, "recall": round(rec, 5), "M": graph["M"], "Mmax0": graph["Mmax0"],
-                   "efConstruction": graph["efC"], "sweep": sweep},
-        "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
-                     "kernel": "search_kernel", "kernel_ms": round(kern_ms, 4),
-                     "algorithmic_bytes_per_launch": alg_bytes, "kernel_hash": khash},
-        "counters_per_query": {"dist_evals": round(float(c[:, 0].mean()), 2),
-                               "expansions": round(float(c[:, 1].mean()), 2),
-                               "dist_evals_layer0": round(float(c[:, 2].mean()), 2),
-                               "expansions_layer0": round(float(c[:, 3].mean()), 2)},
+        "config": {"workload": f"{a.workload} {graph['n']}x{graph['dim']}, {nq} queries, K={K}, plain fp32 "
+                               f"traversal at the smallest swept ef with recall@{K}>=0.95",
+                   "ef": head["ef"], "recall": head["recall"], "M": graph["M"], "Mmax0": graph["Mmax0"],
+                   "efConstruction": graph["efC"]},
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": round(achieved / HBM_PEAK_GBS, 4),
+                     "traffic": load_traffic(khash, a.workload, head["ef"]),
+                     "kernel": "search_kernel", "kernel_ms": head["kernel_ms"],
+                     "algorithmic_bytes_per_launch": alg_launch, "kernel_hash": khash},
+        "forms": results,
         "bruteforce": {"ms": round(bf_ms, 3), "queries": nq,
                        "tflops": round(2.0 * nq * graph["n"] * graph["dim"] / (bf_ms / 1000.0) / 1e12, 2)},
         "cpu_baseline": cpu,

@@ -128,6 +128,7 @@ typedef enum {
  *              vectors; the output is the K nearest by that exact distance.
  *   mlp        for HNSW_MODE_LEARNED: a network from hnsw_mlp_create (NULL
  *              otherwise); a NULL net in learned mode runs the plain search.
+ *              Learned mode needs k <= 64.
  *   counters   NULL or device u32 [n][4]: distance evaluations (all layers),
  *              expansions (all layers), distance evaluations on layer 0,
  *              expansions on layer 0.
@@ -170,6 +171,40 @@ hnsw_status hnsw_index_add_lowp(hnsw_index *index, int kind, void *stream);
  * [n][layout[0]] bytes (synchronous copy).
  */
 hnsw_status hnsw_index_read_lowp(const hnsw_index *index, int kind, void *host_out, uint64_t layout[3]);
+
+/*
+ * The learned stop rule (an addition to the paper's search; its own stop
+ * test, Alg. 2, remains in force).  A 24-64-64-2 perceptron scores a feature
+ * vector of the layer-0 search state every `period` expansions (at most
+ * `max_ckpt` times per query): output 0 > tau ends the search; output 1, at
+ * the first checkpoint, halves ef j = clamp(floor(0.5 - out1), 0, jmax)
+ * times.  Inference uses BF16 weights and activations with float
+ * accumulation in a fixed order, so results are reproducible bit for bit.
+ *
+ * Parameter layout (fp32, HNSW_MLP_PARAMS values): W1[64][24], b1[64],
+ * W2[64][64], b2[64], W3[2][64], b3[2].
+ */
+#define HNSW_MLP_PARAMS 5890u
+typedef struct hnsw_mlp hnsw_mlp;
+
+/* Build an inference net from host fp32 parameters (weights rounded to BF16,
+ * nearest even).  NaN/huge parameters or period == 0 -> HNSW_ERR_INVALID_ARG. */
+hnsw_status hnsw_mlp_create(const float *params, float tau, int jmax, uint32_t period, uint32_t max_ckpt,
+                            hnsw_mlp **out);
+void hnsw_mlp_free(hnsw_mlp *mlp);
+
+/* FP32 training kernels (all pointers device memory, enqueued on `stream`):
+ *   forward: out[n][2] = perceptron(x[n][24]) with parameters `params`.
+ *   grad:    gradient (HNSW_MLP_PARAMS values) and mean loss of
+ *            L = (1/n) sum_s [ c_s * BCE(z0_s, y0_s) + lambda * m_s * (z1_s - y1_s)^2 ]
+ *            for labels y[n][4] = (y0, c, y1, m); stream-ordered scratch of
+ *            about n/64 * HNSW_MLP_PARAMS floats.
+ *   adam:    one Adam step (bias-corrected, step >= 1) on params with moments m, v. */
+hnsw_status hnsw_mlp_forward(const float *params, const float *x, uint32_t n, float *out, void *stream);
+hnsw_status hnsw_mlp_grad(const float *params, const float *x, const float *y, uint32_t n, float lambda, float *grad,
+                          float *loss, void *stream);
+hnsw_status hnsw_mlp_adam(float *params, const float *grad, float *m, float *v, float lr, float beta1, float beta2,
+                          float eps, uint32_t step, void *stream);
 
 /* Human-readable name of a status code (static storage). */
 const char *hnsw_status_str(hnsw_status s);

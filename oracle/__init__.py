@@ -83,6 +83,9 @@ def lib():
         L.or_e4m3_rne.argtypes = [C.c_float]
         L.or_bf16_rne.restype = C.c_uint16
         L.or_bf16_rne.argtypes = [C.c_float]
+        L.or_search_learned.argtypes = [vp, vp, u32, u32, u32, i32, i32, vp, C.c_float, i32, vp, vp, vp, vp, vp,
+                                        vp, i32]
+        L.or_mlp_forward.argtypes = [vp, vp, u32, vp]
         _lib = L
     return _lib
 
@@ -205,6 +208,34 @@ class Graph:
         m = lib().or_search_layer(self._h, _p(q), _p(ep), len(ep), ef, lc, _p(ids), _p(ds), _p(nd))
         return ids[:m], ds[:m], int(nd[0])
 
+    def search_learned(self, Q, K: int, ef: int, net=None, tau: float = 0.0, jmax: int = 0, T: int = 8,
+                       max_ckpt: int = 64, trace: bool = False, nthreads: int = 1):
+        """K-NN-SEARCH with the learned stop rule (``net``: flat float32 parameters,
+        weights already BF16 values) or, with ``net=None``, the plain search
+        with a trace of checkpoint features and top-K lists.
+
+        Returns dict(ids, dists, counters, info[, feat, topk]); info[i] =
+        (checkpoints reached, checkpoint where the rule stopped or 0, ef at the end).
+        """
+        Q = np.ascontiguousarray(Q, dtype=np.float32)
+        nq = Q.shape[0]
+        ids = np.empty((nq, K), dtype=np.int32)
+        ds = np.empty((nq, K), dtype=np.float32)
+        cnt = np.zeros((nq, 4), dtype=np.uint64)
+        info = np.zeros((nq, 3), dtype=np.int32)
+        feat = np.zeros((nq, max_ckpt, MLP_IN), dtype=np.float32) if trace else None
+        topk = np.full((nq, max_ckpt, K), -1, dtype=np.int32) if trace else None
+        w = None if net is None else np.ascontiguousarray(net, dtype=np.float32)
+        if w is not None:
+            assert w.size == MLP_PARAMS
+        lib().or_search_learned(self._h, _p(Q), nq, K, ef, T, max_ckpt, _p(w) if w is not None else None,
+                                float(tau), jmax, _p(ids), _p(ds), _p(cnt), _p(feat) if trace else None,
+                                _p(topk) if trace else None, _p(info), nthreads)
+        out = dict(ids=ids, dists=ds, counters=cnt, info=info)
+        if trace:
+            out.update(feat=feat, topk=topk)
+        return out
+
     def set_lowp(self, decoded, scale):
         """Traverse over a low-precision copy (decoded values, per-vector scales) and
         re-rank the final W with the fp32 vectors; ``None`` restores the plain search."""
@@ -224,6 +255,20 @@ class Graph:
         m = lib().or_select_heuristic(self._h, base_id, _p(cand), len(cand), M, lc, int(extend),
                                       int(keep_pruned), _p(out))
         return out[:m]
+
+
+MLP_IN, MLP_HID, MLP_OUT = 24, 64, 2
+MLP_PARAMS = MLP_HID * MLP_IN + MLP_HID + MLP_HID * MLP_HID + MLP_HID + MLP_OUT * MLP_HID + MLP_OUT
+
+
+def mlp_forward_bf16(net, feat):
+    """The stop-rule perceptron exactly as the search applies it (BF16 inputs and
+    hidden values, float accumulation in input order)."""
+    w = np.ascontiguousarray(net, dtype=np.float32)
+    f = np.ascontiguousarray(feat, dtype=np.float32).reshape(-1, MLP_IN)
+    out = np.empty((f.shape[0], MLP_OUT), dtype=np.float32)
+    lib().or_mlp_forward(_p(w), _p(f), f.shape[0], _p(out))
+    return out
 
 
 def quantize_bf16(X):

@@ -215,12 +215,173 @@ static uint32_t next_gen(searcher *s) {
     return s->gen;
 }
 
+/* --------------------------------------------- learned early termination */
+
+/*
+ * The learned stop rule (an addition to the paper, which stops only when the
+ * nearest candidate is further than the furthest element of W, Alg. 2).
+ * Every LT layer-0 expansions (at most LMAX checkpoints) a 24-value feature
+ * vector of the search state is formed; a 24-64-64-2 perceptron with BF16
+ * weights scores it.  Output 0 is a stop logit: the search ends when it
+ * exceeds tau.  Output 1, at the first checkpoint only, asks for j halvings
+ * of ef (j = floor(0.5 - out1) clamped to [0, jmax]); W then keeps its ef
+ * nearest elements.  All feature arithmetic is IEEE float (add, subtract,
+ * multiply, divide); the network multiplies BF16 values (exact in float) and
+ * accumulates in float in input order, so the result is reproducible bit for
+ * bit.
+ */
+static int cmp_item(const void *pa, const void *pb);
+
+#define LF 24 /* features */
+#define LH 64 /* hidden width */
+
+typedef struct {
+    int T, max_ckpt, K, jmax;
+    const float *w1, *b1, *w2, *b2, *w3, *b3; /* NULL w1: trace only, no decisions */
+    float tau;
+    /* per-query outputs (trace arrays may be NULL) */
+    float *feat;     /* [max_ckpt][LF]                         */
+    int32_t *topk;   /* [max_ckpt][K]                          */
+    int n_ckpt;      /* checkpoints reached                    */
+    int stopped_at;  /* checkpoint at which the rule stopped, 0 */
+    uint32_t ef_end; /* ef after the adaptive step             */
+    /* state */
+    uint32_t n_exp_upper;
+    float d_start, d_best_prev, d_k_prev;
+    int32_t prev[64];
+    int n_prev;
+} learn_ctx;
+
+static float lratio(float a, float b) {
+    float den = fabsf(b) + 1e-20f;
+    float r = a / den;
+    return r > 1e6f ? 1e6f : (r < -1e6f ? -1e6f : r);
+}
+
+static float bf16_round(float f) {
+    uint32_t u;
+    memcpy(&u, &f, 4);
+    uint32_t lsb = (u >> 16) & 1u;
+    u = (u + 0x7FFFu + lsb) & 0xFFFF0000u;
+    float r;
+    memcpy(&r, &u, 4);
+    return r;
+}
+
+/* The perceptron on one feature vector: out[0] stop logit, out[1] ef step. */
+static void mlp_forward(const learn_ctx *lx, const float *f, float *out) {
+    float x[LF], h1[LH], h2[LH];
+    for (int i = 0; i < LF; ++i) x[i] = bf16_round(f[i]);
+    for (int o = 0; o < LH; ++o) {
+        float acc = lx->b1[o];
+        for (int i = 0; i < LF; ++i) acc = acc + lx->w1[o * LF + i] * x[i];
+        h1[o] = bf16_round(acc > 0.0f ? acc : 0.0f);
+    }
+    for (int o = 0; o < LH; ++o) {
+        float acc = lx->b2[o];
+        for (int i = 0; i < LH; ++i) acc = acc + lx->w2[o * LH + i] * h1[i];
+        h2[o] = bf16_round(acc > 0.0f ? acc : 0.0f);
+    }
+    for (int o = 0; o < 2; ++o) {
+        float acc = lx->b3[o];
+        for (int i = 0; i < LH; ++i) acc = acc + lx->w3[o * LH + i] * h2[i];
+        out[o] = acc;
+    }
+}
+
+/*
+ * Checkpoint after `e` layer-0 expansions.  W (max-heap) and C (min-heap) are
+ * the state of Alg. 2; the next element Alg. 2 would expand is the top of C
+ * when its key does not exceed the furthest key of W.  Returns 1 to stop.
+ */
+static int checkpoint(learn_ctx *lx, heap *W, heap *C, uint32_t e, uint32_t *ef) {
+    int ck = ++lx->n_ckpt;
+    size_t n = W->n;
+    item *ws = (item *)malloc(sizeof(item) * (n ? n : 1));
+    memcpy(ws, W->a, sizeof(item) * n);
+    qsort(ws, n, sizeof(item), cmp_item);
+    uint32_t K = (uint32_t)lx->K;
+    uint32_t kk = n < K ? (uint32_t)n : K;
+    float d_best = ws[0].d, d_k = ws[kk - 1].d, d_f = ws[n - 1].d;
+    item f = ws[n - 1];
+    int has_next = C->n > 0 && !key_less(f, C->a[0]);
+    uint32_t pos = (uint32_t)n, n_unexp = 0;
+    if (has_next) {
+        pos = 0;
+        while (pos < n && key_less(ws[pos], C->a[0])) ++pos;
+    }
+    for (size_t i = 0; i < C->n; ++i) n_unexp += !key_less(f, C->a[i]);
+    float d_next = has_next ? ws[pos].d : d_f;
+    uint32_t changed = 0;
+    for (uint32_t i = 0; i < kk; ++i) {
+        int seen = 0;
+        for (int j = 0; j < lx->n_prev; ++j) seen |= lx->prev[j] == (int32_t)ws[i].id;
+        changed += !seen;
+    }
+    if (ck == 1) {
+        lx->d_best_prev = d_best;
+        lx->d_k_prev = d_k;
+    }
+    float ff[LF];
+    float fe = (float)*ef;
+    ff[0] = (float)e / fe;
+    ff[1] = (float)e / 256.0f;
+    ff[2] = (float)lx->n_exp_upper / 16.0f;
+    ff[3] = (float)n / fe;
+    ff[4] = (float)pos / fe;
+    ff[5] = (float)n_unexp / fe;
+    ff[6] = (float)changed / (float)K;
+    ff[7] = (float)ck / 32.0f;
+    ff[8] = lratio(d_best, lx->d_start);
+    ff[9] = lratio(d_k, lx->d_start);
+    ff[10] = lratio(d_f, lx->d_start);
+    ff[11] = lratio(d_next, lx->d_start);
+    ff[12] = lratio(d_best, d_k);
+    ff[13] = lratio(d_k, d_f);
+    ff[14] = lratio(d_next, d_k);
+    ff[15] = lratio(lx->d_k_prev, d_k);
+    ff[16] = lratio(lx->d_best_prev, d_best);
+    ff[17] = lratio(d_k - d_best, d_f - d_best);
+    ff[18] = fe / 512.0f;
+    ff[19] = (float)K / 100.0f;
+    ff[20] = lratio(d_next - d_k, d_f - d_best);
+    ff[21] = d_next < d_k ? 1.0f : 0.0f;
+    ff[22] = pos < K ? 1.0f : 0.0f;
+    ff[23] = 1.0f;
+    if (lx->feat) memcpy(lx->feat + (size_t)(ck - 1) * LF, ff, sizeof(ff));
+    if (lx->topk)
+        for (uint32_t i = 0; i < K; ++i) lx->topk[(size_t)(ck - 1) * K + i] = i < kk ? (int32_t)ws[i].id : -1;
+    lx->n_prev = (int)kk;
+    for (uint32_t i = 0; i < kk; ++i) lx->prev[i] = (int32_t)ws[i].id;
+    lx->d_best_prev = d_best;
+    lx->d_k_prev = d_k;
+    free(ws);
+    if (!lx->w1) return 0;
+    float out[2];
+    mlp_forward(lx, ff, out);
+    if (ck == 1 && lx->jmax > 0) {
+        int j = (int)floorf(0.5f - out[1]);
+        j = j < 0 ? 0 : (j > lx->jmax ? lx->jmax : j);
+        uint32_t ne = *ef >> j;
+        if (ne < K) ne = K;
+        if (ne < *ef) {
+            *ef = ne;
+            while (W->n > ne) h_pop(W);
+        }
+    }
+    if (out[0] > lx->tau) {
+        lx->stopped_at = ck;
+        return 1;
+    }
+    return 0;
+}
+
 /*
  * SEARCH-LAYER (Alg. 2).  On return s->W holds the result (heap order).
  * ep: enter points (ids), q: query vector.
  */
-static void search_layer(const graph *g, searcher *s, const float *q, const uint32_t *ep, size_t n_ep,
-                         uint32_t ef, int lc) {
+static void search_layer_l(const graph *g, searcher *s, const float *q, const uint32_t *ep, size_t n_ep,
+                           uint32_t ef, int lc, learn_ctx *lx) {
     uint32_t gen = next_gen(s);
     s->C.n = 0;
     s->W.n = 0;
@@ -232,11 +393,14 @@ static void search_layer(const graph *g, searcher *s, const float *q, const uint
         h_push(&s->C, it);
         h_push(&s->W, it);
     }
+    if (lx) lx->d_start = s->W.a[0].d;
+    uint32_t n_exp_here = 0;
     while (s->C.n > 0) {
         item c = h_pop(&s->C);        /* nearest element of C            */
         item f = s->W.a[0];           /* furthest element of W           */
         if (key_less(f, c)) break;    /* all elements of W are evaluated */
         s->n_exp[lc]++;
+        ++n_exp_here;
         uint32_t *cnt;
         const uint32_t *nb = nbr(g, c.id, lc, &cnt);
         uint32_t m = *cnt;
@@ -253,7 +417,16 @@ static void search_layer(const graph *g, searcher *s, const float *q, const uint
                 if (s->W.n > ef) h_pop(&s->W);
             }
         }
+        if (lx && n_exp_here % (uint32_t)lx->T == 0 && lx->n_ckpt < lx->max_ckpt &&
+            checkpoint(lx, &s->W, &s->C, n_exp_here, &ef))
+            break;
     }
+    if (lx) lx->ef_end = ef;
+}
+
+static void search_layer(const graph *g, searcher *s, const float *q, const uint32_t *ep, size_t n_ep,
+                         uint32_t ef, int lc) {
+    search_layer_l(g, s, q, ep, n_ep, ef, lc, NULL);
 }
 
 static int cmp_item(const void *pa, const void *pb) {
@@ -468,8 +641,8 @@ OR_EXPORT void or_free(graph *g) {
 /* -------------------------------------------------------- K-NN-SEARCH */
 
 /* K-NN-SEARCH (Alg. 5) of one query using workspace s. */
-static void knn_search(const graph *g, searcher *s, const float *q, uint32_t K, uint32_t ef, int32_t *ids,
-                       float *dists, uint64_t *counters) {
+static void knn_search_l(const graph *g, searcher *s, const float *q, uint32_t K, uint32_t ef, int32_t *ids,
+                         float *dists, uint64_t *counters, learn_ctx *lx) {
     memset(s->n_dist, 0, sizeof(s->n_dist));
     memset(s->n_exp, 0, sizeof(s->n_exp));
     uint32_t efe = ef < K ? K : ef;
@@ -483,7 +656,9 @@ static void knn_search(const graph *g, searcher *s, const float *q, uint32_t K, 
                 if (key_less(s->W.a[i], best)) best = s->W.a[i];
             ep = best.id;
         }
-        search_layer(g, s, q, &ep, 1, efe, 0);
+        if (lx) lx->n_exp_upper = (uint32_t)(s->n_exp[1] + s->n_exp[2] + s->n_exp[3] + s->n_exp[4] + s->n_exp[5] +
+                                             s->n_exp[6] + s->n_exp[7] + s->n_exp[8]);
+        search_layer_l(g, s, q, &ep, 1, efe, 0, lx);
         nres = s->W.n;
         if (g->rerank) /* K nearest of W by the exact distance to the fp32 vectors */
             for (size_t i = 0; i < nres; ++i)
@@ -502,6 +677,11 @@ static void knn_search(const graph *g, searcher *s, const float *q, uint32_t K, 
         counters[2] = s->n_dist[0];   /* distance evaluations, layer 0     */
         counters[3] = s->n_exp[0];    /* expansions, layer 0               */
     }
+}
+
+static void knn_search(const graph *g, searcher *s, const float *q, uint32_t K, uint32_t ef, int32_t *ids,
+                       float *dists, uint64_t *counters) {
+    knn_search_l(g, s, q, K, ef, ids, dists, counters, NULL);
 }
 
 typedef struct {
@@ -800,3 +980,90 @@ OR_EXPORT void or_quantize_fp8(const float *X, uint64_t n, uint32_t dim, uint8_t
 OR_EXPORT float or_e4m3_value(uint8_t b) { return e4m3_value(b); }
 OR_EXPORT uint8_t or_e4m3_rne(float f) { return e4m3_rne(f); }
 OR_EXPORT uint16_t or_bf16_rne(float f) { return bf16_rne(f); }
+
+/* ---------------------------------------------- learned search, traces */
+
+typedef struct {
+    const graph *g;
+    const float *Q;
+    uint32_t K, ef, lo, hi;
+    learn_ctx proto;
+    int32_t *ids;
+    float *dists;
+    uint64_t *counters;
+    float *feat;     /* [nq][max_ckpt][LF] or NULL */
+    int32_t *topk;   /* [nq][max_ckpt][K] or NULL  */
+    int32_t *info;   /* [nq][3]: checkpoints, stopped_at, ef at the end */
+} learn_job;
+
+static void *learn_worker(void *p) {
+    learn_job *j = (learn_job *)p;
+    searcher *s = ws_new(j->g->n);
+    for (uint32_t i = j->lo; i < j->hi; ++i) {
+        learn_ctx lx = j->proto;
+        lx.feat = j->feat ? j->feat + (size_t)i * lx.max_ckpt * LF : NULL;
+        lx.topk = j->topk ? j->topk + (size_t)i * lx.max_ckpt * lx.K : NULL;
+        knn_search_l(j->g, s, j->Q + (uint64_t)i * j->g->dim, j->K, j->ef, j->ids + (uint64_t)i * j->K,
+                     j->dists + (uint64_t)i * j->K, j->counters ? j->counters + 4ull * i : NULL, &lx);
+        if (j->info) {
+            j->info[3 * i] = lx.n_ckpt;
+            j->info[3 * i + 1] = lx.stopped_at;
+            j->info[3 * i + 2] = (int32_t)lx.ef_end;
+        }
+    }
+    ws_free(s);
+    return NULL;
+}
+
+/*
+ * K-NN-SEARCH with the learned stop rule (net != NULL) or with a trace of
+ * the checkpoint features and top-K lists only (net == NULL).
+ * net: w1[64][24], b1[64], w2[64][64], b2[64], w3[2][64], b3[2] as floats
+ * (weights already BF16 values), concatenated.
+ */
+OR_EXPORT void or_search_learned(const graph *g, const float *Q, uint32_t nq, uint32_t K, uint32_t ef, int T,
+                                 int max_ckpt, const float *net, float tau, int jmax, int32_t *ids, float *dists,
+                                 uint64_t *counters, float *feat, int32_t *topk, int32_t *info, int nthreads) {
+    learn_ctx proto;
+    memset(&proto, 0, sizeof(proto));
+    proto.T = T;
+    proto.max_ckpt = max_ckpt;
+    proto.K = (int)K;
+    proto.jmax = jmax;
+    proto.tau = tau;
+    if (net) {
+        proto.w1 = net;
+        proto.b1 = proto.w1 + LH * LF;
+        proto.w2 = proto.b1 + LH;
+        proto.b2 = proto.w2 + LH * LH;
+        proto.w3 = proto.b2 + LH;
+        proto.b3 = proto.w3 + 2 * LH;
+    }
+    if (nthreads < 1) nthreads = 1;
+    if ((uint32_t)nthreads > nq) nthreads = nq ? (int)nq : 1;
+    if (nthreads > 256) nthreads = 256;
+    pthread_t th[256];
+    learn_job jobs[256];
+    for (int t = 0; t < nthreads; ++t) {
+        jobs[t] = (learn_job){g, Q, K, ef, (uint32_t)((uint64_t)nq * t / nthreads),
+                              (uint32_t)((uint64_t)nq * (t + 1) / nthreads), proto, ids, dists, counters, feat, topk,
+                              info};
+        if (nthreads == 1) learn_worker(&jobs[t]);
+        else pthread_create(&th[t], NULL, learn_worker, &jobs[t]);
+    }
+    if (nthreads > 1)
+        for (int t = 0; t < nthreads; ++t) pthread_join(th[t], NULL);
+}
+
+/* The perceptron alone on n feature vectors (for tests of the network arithmetic). */
+OR_EXPORT void or_mlp_forward(const float *net, const float *feat, uint32_t n, float *out) {
+    learn_ctx lx;
+    memset(&lx, 0, sizeof(lx));
+    lx.w1 = net;
+    lx.b1 = lx.w1 + LH * LF;
+    lx.w2 = lx.b1 + LH;
+    lx.b2 = lx.w2 + LH * LH;
+    lx.w3 = lx.b2 + LH;
+    lx.b3 = lx.w3 + 2 * LH;
+    for (uint32_t i = 0; i < n; ++i) mlp_forward(&lx, feat + (size_t)i * LF, out + 2 * i);
+}

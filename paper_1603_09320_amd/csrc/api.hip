@@ -9,6 +9,11 @@
 
 #include "internal.h"
 
+struct hnsw_mlp {
+    hnsw::DevMlp net;
+    void *mem;
+};
+
 struct hnsw_index {
     hnsw::DevIndex ix;
     float *xnorm;  // [n] squared norms of the vectors (brute-force ranking)
@@ -211,10 +216,11 @@ hnsw_status hnsw_search_batch_ex(const hnsw_index *index, const float *queries, 
                                  void *stream) {
     if (!index) return HNSW_ERR_INVALID_ARG;
     if (k == 0 || ef == 0) return HNSW_ERR_INVALID_ARG;
-    if (mode < HNSW_MODE_PLAIN || mode > HNSW_MODE_FP8) return HNSW_ERR_UNSUPPORTED;
+    if (mode < HNSW_MODE_PLAIN || mode > HNSW_MODE_LEARNED) return HNSW_ERR_UNSUPPORTED;
     if (mode == HNSW_MODE_BF16 && !index->ix.vbf16) return HNSW_ERR_INVALID_ARG;
     if (mode == HNSW_MODE_FP8 && !index->ix.vfp8) return HNSW_ERR_INVALID_ARG;
-    (void)mlp;
+    if (mode == HNSW_MODE_LEARNED && !mlp) mode = HNSW_MODE_PLAIN;  // no net: the plain search
+    if (mode == HNSW_MODE_LEARNED && k > 64) return HNSW_ERR_UNSUPPORTED;
     const uint32_t efe = ef < k ? k : ef;
     if (efe > HNSW_EF_MAX) return HNSW_ERR_UNSUPPORTED;
     if (n == 0) return HNSW_OK;
@@ -233,11 +239,17 @@ hnsw_status hnsw_search_batch_ex(const hnsw_index *index, const float *queries, 
     a.wpow2 = 64;
     while (a.wpow2 < a.wcap) a.wpow2 <<= 1;
     // visited table: about 8 slots per unit of ef, 1024..4096 slots
+    // (HNSW_VISITED_LOG2 = 8..14 overrides the size, for tuning)
     uint32_t lg = 10;
     while (lg < 12 && (1u << lg) < 8u * efe) ++lg;
+    if (const char *v = getenv("HNSW_VISITED_LOG2")) {
+        const long x = strtol(v, nullptr, 10);
+        if (x >= 8 && x <= 14) lg = static_cast<uint32_t>(x);
+    }
     a.ht_log2 = lg;
     a.mode = mode;
-    a.mlp = mlp;
+    a.mlp = hnsw::DevMlp{};
+    if (mode == HNSW_MODE_LEARNED) a.mlp = static_cast<const hnsw_mlp *>(mlp)->net;
     if (hnsw::launch_search(index->ix, a, static_cast<hipStream_t>(stream)) != hipSuccess) {
         (void)hipGetLastError();
         return HNSW_ERR_DEVICE;
@@ -328,6 +340,104 @@ hnsw_status hnsw_bruteforce_knn(const hnsw_index *index, const float *queries, u
                                                  dists_out, st);
     (void)hipFreeAsync(partial, st);
     if (e != hipSuccess) {
+        (void)hipGetLastError();
+        return HNSW_ERR_DEVICE;
+    }
+    return HNSW_OK;
+}
+
+static uint16_t bf16_rne_host(float f) {
+    uint32_t u;
+    memcpy(&u, &f, 4);
+    u += 0x7FFFu + ((u >> 16) & 1u);
+    return static_cast<uint16_t>(u >> 16);
+}
+
+hnsw_status hnsw_mlp_create(const float *params, float tau, int jmax, uint32_t period, uint32_t max_ckpt,
+                            hnsw_mlp **out) {
+    if (!out) return HNSW_ERR_INVALID_ARG;
+    *out = nullptr;
+    if (!params || period == 0 || jmax < 0 || jmax > 8) return HNSW_ERR_INVALID_ARG;
+    for (int i = 0; i < hnsw::kMlpParams; ++i)
+        if (!(params[i] == params[i]) || params[i] > 1e30f || params[i] < -1e30f) return HNSW_ERR_INVALID_ARG;
+    if (!device_count_ok()) return HNSW_ERR_DEVICE;
+    using namespace hnsw;
+    const int nW1 = kMlpHid * kMlpIn, nW2 = kMlpHid * kMlpHid, nW3 = kMlpOut * kMlpHid;
+    const int ob1 = nW1, oW2 = ob1 + kMlpHid, ob2 = oW2 + nW2, oW3 = ob2 + kMlpHid, ob3 = oW3 + nW3;
+    std::vector<uint16_t> w(nW1 + nW2 + nW3);
+    for (int i = 0; i < nW1; ++i) w[i] = bf16_rne_host(params[i]);
+    for (int i = 0; i < nW2; ++i) w[nW1 + i] = bf16_rne_host(params[oW2 + i]);
+    for (int i = 0; i < nW3; ++i) w[nW1 + nW2 + i] = bf16_rne_host(params[oW3 + i]);
+    std::vector<float> b(kMlpHid + kMlpHid + kMlpOut);
+    memcpy(b.data(), params + ob1, kMlpHid * 4);
+    memcpy(b.data() + kMlpHid, params + ob2, kMlpHid * 4);
+    memcpy(b.data() + 2 * kMlpHid, params + ob3, kMlpOut * 4);
+    const size_t wbytes = w.size() * 2, bytes = wbytes + b.size() * 4;
+    void *mem = nullptr;
+    if (hipMalloc(&mem, bytes) != hipSuccess) {
+        (void)hipGetLastError();
+        return HNSW_ERR_OUT_OF_MEMORY;
+    }
+    if (hipMemcpy(mem, w.data(), wbytes, hipMemcpyHostToDevice) != hipSuccess ||
+        hipMemcpy(static_cast<uint8_t *>(mem) + wbytes, b.data(), b.size() * 4, hipMemcpyHostToDevice) != hipSuccess) {
+        (void)hipGetLastError();
+        (void)hipFree(mem);
+        return HNSW_ERR_DEVICE;
+    }
+    hnsw_mlp *m = new hnsw_mlp();
+    m->mem = mem;
+    const uint16_t *wd = static_cast<const uint16_t *>(mem);
+    const float *bd = reinterpret_cast<const float *>(static_cast<uint8_t *>(mem) + wbytes);
+    m->net = DevMlp{wd, wd + nW1, wd + nW1 + nW2, bd, bd + kMlpHid, bd + 2 * kMlpHid, tau, jmax, period, max_ckpt};
+    *out = m;
+    return HNSW_OK;
+}
+
+void hnsw_mlp_free(hnsw_mlp *mlp) {
+    if (!mlp) return;
+    (void)hipFree(mlp->mem);
+    delete mlp;
+}
+
+hnsw_status hnsw_mlp_forward(const float *params, const float *x, uint32_t n, float *out, void *stream) {
+    if (n == 0) return HNSW_OK;
+    if (!is_device_ptr(params) || !is_device_ptr(x) || !is_device_ptr(out)) return HNSW_ERR_INVALID_ARG;
+    if (hnsw::launch_mlp_forward(params, x, n, out, static_cast<hipStream_t>(stream)) != hipSuccess) {
+        (void)hipGetLastError();
+        return HNSW_ERR_DEVICE;
+    }
+    return HNSW_OK;
+}
+
+hnsw_status hnsw_mlp_grad(const float *params, const float *x, const float *y, uint32_t n, float lambda,
+                          float *grad, float *loss, void *stream) {
+    if (n == 0) return HNSW_ERR_INVALID_ARG;
+    if (!is_device_ptr(params) || !is_device_ptr(x) || !is_device_ptr(y) || !is_device_ptr(grad))
+        return HNSW_ERR_INVALID_ARG;
+    if (loss && !is_device_ptr(loss)) return HNSW_ERR_INVALID_ARG;
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    const size_t waves = hnsw::mlp_grad_waves(n);
+    void *scratch = nullptr;
+    if (hipMallocAsync(&scratch, waves * (hnsw::kMlpParams + 1) * 4, st) != hipSuccess) {
+        (void)hipGetLastError();
+        return HNSW_ERR_OUT_OF_MEMORY;
+    }
+    const hipError_t e = hnsw::launch_mlp_grad(params, x, y, n, lambda, grad, loss, static_cast<float *>(scratch), st);
+    (void)hipFreeAsync(scratch, st);
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        return HNSW_ERR_DEVICE;
+    }
+    return HNSW_OK;
+}
+
+hnsw_status hnsw_mlp_adam(float *params, const float *grad, float *m, float *v, float lr, float beta1, float beta2,
+                          float eps, uint32_t step, void *stream) {
+    if (step == 0) return HNSW_ERR_INVALID_ARG;
+    if (!is_device_ptr(params) || !is_device_ptr(grad) || !is_device_ptr(m) || !is_device_ptr(v))
+        return HNSW_ERR_INVALID_ARG;
+    if (hnsw::launch_adam(params, grad, m, v, hnsw::kMlpParams, lr, beta1, beta2, eps, step,
+                          static_cast<hipStream_t>(stream)) != hipSuccess) {
         (void)hipGetLastError();
         return HNSW_ERR_DEVICE;
     }

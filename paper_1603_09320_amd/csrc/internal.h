@@ -26,6 +26,19 @@ struct DevIndex {
     uint32_t Mmax, Mmax0, entry, max_level, metric;
 };
 
+// The learned stop rule's network as the search kernel reads it: BF16
+// weights (W1[64][24], W2[64][64], W3[2][64]) and fp32 biases.
+constexpr int kMlpIn = 24, kMlpHid = 64, kMlpOut = 2;
+constexpr int kMlpParams = kMlpHid * kMlpIn + kMlpHid + kMlpHid * kMlpHid + kMlpHid + kMlpOut * kMlpHid + kMlpOut;
+struct DevMlp {
+    const uint16_t *w1, *w2, *w3;
+    const float *b1, *b2, *b3;
+    float tau;        // stop when output 0 exceeds tau
+    int jmax;         // most halvings of ef at the first checkpoint
+    uint32_t period;  // layer-0 expansions between checkpoints
+    uint32_t max_ckpt;
+};
+
 // One batched search launch.
 struct SearchArgs {
     const float *queries;  // [nq][dim]
@@ -37,7 +50,7 @@ struct SearchArgs {
     uint32_t wpow2;        // power of two >= wcap (LDS reserved for W)
     uint32_t ht_log2;      // visited-table slots = 1 << ht_log2
     int mode;              // hnsw_mode
-    const void *mlp;       // device parameters of the learned stop rule or null
+    DevMlp mlp;            // learned stop rule (mode HNSW_MODE_LEARNED)
 };
 
 // Vector tile shape for a dimension: G lanes share one vector, each lane
@@ -46,6 +59,14 @@ struct TileShape {
     int G, F;
 };
 TileShape tile_for(int kind, uint32_t dim);
+
+// Perceptron training kernels.
+hipError_t launch_mlp_forward(const float *P, const float *X, uint32_t n, float *out, hipStream_t stream);
+uint32_t mlp_grad_waves(uint32_t n);
+hipError_t launch_mlp_grad(const float *P, const float *X, const float *Y, uint32_t n, float lambda, float *grad,
+                           float *loss, float *scratch, hipStream_t stream);
+hipError_t launch_adam(float *P, const float *G, float *M, float *V, uint32_t np, float lr, float b1, float b2,
+                       float eps, uint32_t step, hipStream_t stream);
 
 // Quantisation of the fp32 store into the low-precision copies.
 hipError_t launch_quantize_bf16(const DevIndex &ix, uint16_t *out, hipStream_t stream);

@@ -54,12 +54,20 @@ __device__ __forceinline__ uint64_t make_key(float d, uint32_t id) {
 __device__ __forceinline__ uint32_t key_id(uint64_t k) { return static_cast<uint32_t>(k) >> 1; }
 __device__ __forceinline__ float key_dist(uint64_t k) { return float_of(static_cast<uint32_t>(k >> 32)); }
 
-// Orders LDS traffic of the wave: every lane's earlier LDS accesses are
-// complete before any later one starts.
+// Keeps the compiler from moving LDS accesses across this point.  A wave's
+// own LDS instructions are executed in issue order, so a later access (by
+// any lane) sees every earlier one; only the compiler's order must be pinned
+// (each workgroup is a single wave).
 __device__ __forceinline__ void wave_sync() {
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+    __atomic_signal_fence(__ATOMIC_SEQ_CST);
     __builtin_amdgcn_wave_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+    __atomic_signal_fence(__ATOMIC_SEQ_CST);
+}
+
+__device__ __forceinline__ uint64_t readlane64(uint64_t v, int lane) {
+    const uint32_t lo = __builtin_amdgcn_readlane(static_cast<uint32_t>(v), lane);
+    const uint32_t hi = __builtin_amdgcn_readlane(static_cast<uint32_t>(v >> 32), lane);
+    return (static_cast<uint64_t>(hi) << 32) | lo;
 }
 
 __device__ __forceinline__ int lane_id() { return __builtin_amdgcn_mbcnt_hi(~0u, __builtin_amdgcn_mbcnt_lo(~0u, 0)); }
@@ -295,10 +303,11 @@ __device__ __forceinline__ float exact_dist(const DevIndex &ix, const float *qro
 }
 
 struct WaveLds {
-    uint64_t *W;       // [wcap]
+    uint64_t *W;       // [wpow2]
     uint64_t *keys;    // [64] keys of the current batch
-    uint64_t *sorted;  // [64] admitted keys in ascending order
     uint32_t *ids;     // [64] ids of the current batch
+    uint32_t *prevk;   // [64] top-K ids at the previous checkpoint (learned mode)
+    float *hid;        // [2][64] hidden layers of the stop-rule network
     uint32_t *ht;      // [1 << ht_log2]
 };
 
@@ -306,9 +315,10 @@ __device__ __forceinline__ WaveLds carve(uint8_t *base, const SearchArgs &a) {
     WaveLds s;
     s.W = reinterpret_cast<uint64_t *>(base);
     s.keys = s.W + a.wpow2;
-    s.sorted = s.keys + 64;
-    s.ids = reinterpret_cast<uint32_t *>(s.sorted + 64);
-    s.ht = s.ids + 64;
+    s.ids = reinterpret_cast<uint32_t *>(s.keys + 64);
+    s.prevk = s.ids + 64;
+    s.hid = reinterpret_cast<float *>(s.prevk + 64);
+    s.ht = reinterpret_cast<uint32_t *>(s.hid + 128);
     return s;
 }
 
@@ -316,67 +326,195 @@ __device__ __forceinline__ WaveLds carve(uint8_t *base, const SearchArgs &a) {
 // wsize: W <- the ef smallest of W and the new keys, dropping keys whose
 // (distance, id) is already in W.  Returns the insertion position of the
 // smallest admitted key (INT_MAX when none was admitted).
+// Positions come from wave-wide comparisons: for each admitted key (broadcast
+// with readlane) a ballot over each 64-entry chunk of W counts the smaller
+// entries and detects an equal one; no LDS access depends on another.
 __device__ __forceinline__ int merge_into_w(const WaveLds &s, int m, uint32_t ef, uint32_t &wsize) {
     const int lane = lane_id();
-    uint64_t a = 0;
-    bool keep = false;
+    const int ws = static_cast<int>(wsize);
+    const uint64_t thr = wsize < ef ? ~0ull : s.W[ef - 1];
+    const uint64_t a = lane < m ? s.keys[lane] : ~0ull;
+    const bool cand = lane < m && a < thr;
+    const uint64_t cm = __ballot(cand);
+    if (cm == 0) return INT_MAX;
     int lb = 0;
-    if (lane < m) {
-        a = s.keys[lane];
-        keep = wsize < ef || a < s.W[ef - 1];
-        if (keep) {
-            const uint64_t ak = a >> 1;
-            int lo = 0, hi = static_cast<int>(wsize);
-            while (lo < hi) {
-                const int mid = (lo + hi) >> 1;
-                if ((s.W[mid] >> 1) < ak) lo = mid + 1;
-                else hi = mid;
+    bool dup = false;
+    for (int cb = 0; cb < ws; cb += 64) {
+        const int i = cb + lane;
+        const uint64_t w = i < ws ? (s.W[i] >> 1) : ~0ull;
+        uint64_t mm = cm;
+        while (mm) {
+            const int t = __ffsll(static_cast<unsigned long long>(mm)) - 1;
+            mm &= mm - 1;
+            const uint64_t at = readlane64(a, t) >> 1;
+            const int below = __popcll(__ballot(w < at));
+            const bool eq = __ballot(w == at) != 0;
+            if (lane == t) {
+                lb += below;
+                dup = dup || eq;
             }
-            lb = lo;
-            if (lb < static_cast<int>(wsize) && (s.W[lb] >> 1) == ak) keep = false;
         }
     }
+    const bool keep = cand && !dup;
     const uint64_t km = __ballot(keep);
     if (km == 0) return INT_MAX;
     const int cnt = __popcll(km);
     int r = 0;
-    if (keep) {
+    {
         uint64_t mm = km;
         while (mm) {
             const int t = __ffsll(static_cast<unsigned long long>(mm)) - 1;
             mm &= mm - 1;
-            const uint64_t kt = s.keys[t];
-            r += (kt < a) || (kt == a && t < lane);
+            const uint64_t at = readlane64(a, t);
+            r += (at < a) || (at == a && t < lane);
         }
-        s.sorted[r] = a;
     }
     const int lbmin = wave_min_int(keep ? lb : INT_MAX);
-    wave_sync();
     // Old elements at positions >= lbmin move right by the number of admitted
     // keys below them; chunks are moved top first so no unread slot is overwritten.
-    const int ws = static_cast<int>(wsize);
     for (int cb = (ws - 1) & ~63; cb >= (lbmin & ~63); cb -= 64) {
         const int i = cb + lane;
-        uint64_t w = 0;
-        int np = -1;
-        if (i >= lbmin && i < ws) {
-            w = s.W[i];
-            int lo = 0, hi = cnt;
-            while (lo < hi) {
-                const int mid = (lo + hi) >> 1;
-                if (s.sorted[mid] < w) lo = mid + 1;
-                else hi = mid;
-            }
-            np = i + lo;
+        const bool live = i >= lbmin && i < ws;
+        const uint64_t w = live ? s.W[i] : 0ull;
+        int below = 0;
+        uint64_t mm = km;
+        while (mm) {
+            const int t = __ffsll(static_cast<unsigned long long>(mm)) - 1;
+            mm &= mm - 1;
+            below += readlane64(a, t) < w;
         }
+        const int np = i + below;
         wave_sync();
-        if (np >= 0 && np < static_cast<int>(ef)) s.W[np] = w;
+        if (live && np < static_cast<int>(ef)) s.W[np] = w;
         wave_sync();
     }
     if (keep && lb + r < static_cast<int>(ef)) s.W[lb + r] = a;
     wave_sync();
     wsize = min(ef, wsize + static_cast<uint32_t>(cnt));
     return lbmin;
+}
+
+// ------------------------------------------------ learned stop rule
+//
+// Every `period` layer-0 expansions (at most max_ckpt times) the wave forms 24
+// features of the search state (IEEE float arithmetic only), runs the
+// 24-64-64-2 perceptron (BF16 weights and activations, products exact in
+// float, accumulation in float in input order, lane j = hidden unit j), and
+// (1) at the first checkpoint halves ef j = clamp(floor(0.5 - out1), 0, jmax)
+// times (W keeps its ef nearest), (2) stops the search when out0 > tau.
+
+struct LearnState {
+    uint32_t ckpt, n_prev, n_exp_upper;
+    float d_start, d_best_prev, d_k_prev;
+};
+
+__device__ __forceinline__ float lratio(float a, float b) {
+    const float den = fabsf(b) + 1e-20f;
+    const float r = a / den;
+    return r > 1e6f ? 1e6f : (r < -1e6f ? -1e6f : r);
+}
+
+__device__ __forceinline__ float bf16_round(float f) {
+    uint32_t u = __float_as_uint(f);
+    u = (u + 0x7FFFu + ((u >> 16) & 1u)) & 0xFFFF0000u;
+    return __uint_as_float(u);
+}
+
+__device__ __forceinline__ float bf16_value(uint16_t b) { return __uint_as_float(static_cast<uint32_t>(b) << 16); }
+
+// Returns true when the rule stops the search; may lower ef and wsize.
+__device__ bool learned_checkpoint(const WaveLds &s, const DevMlp &net, LearnState &st, uint32_t n_exp0,
+                                   uint32_t K, int cursor, uint32_t &ef, uint32_t &wsize) {
+    const int lane = lane_id();
+    const uint32_t ck = ++st.ckpt;
+    const uint32_t n = wsize;
+    const uint32_t kk = n < K ? n : K;
+    const float d_best = key_dist(s.W[0]), d_k = key_dist(s.W[kk - 1]), d_f = key_dist(s.W[n - 1]);
+    uint32_t pos = n;
+    for (int cb = cursor; cb < static_cast<int>(n); cb += 64) {
+        const int i = cb + lane;
+        const uint64_t um = __ballot(i < static_cast<int>(n) && !(s.W[i] & 1ull));
+        if (um) {
+            pos = static_cast<uint32_t>(cb + __ffsll(static_cast<unsigned long long>(um)) - 1);
+            break;
+        }
+    }
+    uint32_t n_unexp = 0;
+    for (int cb = 0; cb < static_cast<int>(n); cb += 64) {
+        const int i = cb + lane;
+        n_unexp += __popcll(__ballot(i < static_cast<int>(n) && !(s.W[i] & 1ull)));
+    }
+    const float d_next = pos < n ? key_dist(s.W[pos]) : d_f;
+    bool fresh_top = false;
+    uint32_t my_id = 0;
+    if (lane < static_cast<int>(kk)) {
+        my_id = key_id(s.W[lane]);
+        bool seen = false;
+        for (uint32_t j = 0; j < st.n_prev; ++j) seen |= s.prevk[j] == my_id;
+        fresh_top = !seen;
+    }
+    const uint32_t changed = __popcll(__ballot(fresh_top));
+    wave_sync();
+    if (lane < static_cast<int>(kk)) s.prevk[lane] = my_id;
+    st.n_prev = kk;
+    if (ck == 1) {
+        st.d_best_prev = d_best;
+        st.d_k_prev = d_k;
+    }
+    const float fe = static_cast<float>(ef);
+    float f[kMlpIn];
+    f[0] = static_cast<float>(n_exp0) / fe;
+    f[1] = static_cast<float>(n_exp0) / 256.0f;
+    f[2] = static_cast<float>(st.n_exp_upper) / 16.0f;
+    f[3] = static_cast<float>(n) / fe;
+    f[4] = static_cast<float>(pos) / fe;
+    f[5] = static_cast<float>(n_unexp) / fe;
+    f[6] = static_cast<float>(changed) / static_cast<float>(K);
+    f[7] = static_cast<float>(ck) / 32.0f;
+    f[8] = lratio(d_best, st.d_start);
+    f[9] = lratio(d_k, st.d_start);
+    f[10] = lratio(d_f, st.d_start);
+    f[11] = lratio(d_next, st.d_start);
+    f[12] = lratio(d_best, d_k);
+    f[13] = lratio(d_k, d_f);
+    f[14] = lratio(d_next, d_k);
+    f[15] = lratio(st.d_k_prev, d_k);
+    f[16] = lratio(st.d_best_prev, d_best);
+    f[17] = lratio(d_k - d_best, d_f - d_best);
+    f[18] = fe / 512.0f;
+    f[19] = static_cast<float>(K) / 100.0f;
+    f[20] = lratio(d_next - d_k, d_f - d_best);
+    f[21] = d_next < d_k ? 1.0f : 0.0f;
+    f[22] = pos < K ? 1.0f : 0.0f;
+    f[23] = 1.0f;
+    st.d_best_prev = d_best;
+    st.d_k_prev = d_k;
+    // layer 1 (lane = hidden unit)
+    float a = net.b1[lane];
+#pragma unroll
+    for (int i = 0; i < kMlpIn; ++i) a = fmaf(bf16_value(net.w1[lane * kMlpIn + i]), bf16_round(f[i]), a);
+    s.hid[lane] = bf16_round(a > 0.0f ? a : 0.0f);
+    wave_sync();
+    a = net.b2[lane];
+    for (int i = 0; i < kMlpHid; ++i) a = fmaf(bf16_value(net.w2[lane * kMlpHid + i]), s.hid[i], a);
+    s.hid[64 + lane] = bf16_round(a > 0.0f ? a : 0.0f);
+    wave_sync();
+    const int o = lane < kMlpOut ? lane : 0;
+    a = net.b3[o];
+    for (int i = 0; i < kMlpHid; ++i) a = fmaf(bf16_value(net.w3[o * kMlpHid + i]), s.hid[64 + i], a);
+    const float out0 = __shfl(a, 0, 64), out1 = __shfl(a, 1, 64);
+    wave_sync();
+    if (ck == 1 && net.jmax > 0) {
+        int j = static_cast<int>(floorf(0.5f - out1));
+        j = j < 0 ? 0 : (j > net.jmax ? net.jmax : j);
+        uint32_t ne = ef >> j;
+        if (ne < K) ne = K;
+        if (ne < ef) {
+            ef = ne;
+            if (wsize > ne) wsize = ne;
+        }
+    }
+    return out0 > net.tau;
 }
 
 // Sorts W[0..n) ascending in LDS (n <= cap, cap a power of two; the tail is
@@ -400,7 +538,7 @@ __device__ __forceinline__ void sort_w(uint64_t *W, uint32_t n, uint32_t cap) {
         }
 }
 
-template <int G, int F, int METRIC, int KIND>
+template <int G, int F, int METRIC, int KIND, bool LEARN>
 __global__ __launch_bounds__(64) void search_kernel(DevIndex ix, SearchArgs a) {
     extern __shared__ __align__(16) uint8_t smem[];
     const uint32_t qi = blockIdx.x;
@@ -452,7 +590,8 @@ __global__ __launch_bounds__(64) void search_kernel(DevIndex ix, SearchArgs a) {
     }
 
     // SEARCH-LAYER on layer 0 with ef candidates, starting from the descent's result.
-    const uint32_t ef = a.ef;
+    uint32_t ef = a.ef;
+    LearnState lst{0u, 0u, n_exp, key_dist(cur), 0.f, 0.f};
     const uint32_t ht_shift = 32u - a.ht_log2, ht_mask = ht_slots - 1u;
     if (lane == 0) {
         s.W[0] = cur;
@@ -464,18 +603,19 @@ __global__ __launch_bounds__(64) void search_kernel(DevIndex ix, SearchArgs a) {
     n_dist0 = 1;
     for (;;) {
         int c = -1;
+        uint64_t ck = 0;
         for (int cb = cursor; cb < static_cast<int>(wsize); cb += 64) {
             const int i = cb + lane;
-            const bool un = i < static_cast<int>(wsize) && !(s.W[i] & 1ull);
-            const uint64_t um = __ballot(un);
+            const uint64_t w = i < static_cast<int>(wsize) ? s.W[i] : 1ull;
+            const uint64_t um = __ballot(!(w & 1ull));
             if (um) {
-                c = cb + __ffsll(static_cast<unsigned long long>(um)) - 1;
+                const int t = __ffsll(static_cast<unsigned long long>(um)) - 1;
+                c = cb + t;
+                ck = readlane64(w, t);
                 break;
             }
         }
         if (c < 0) break;  // every element of W has been expanded
-        const uint64_t ck = s.W[c];
-        wave_sync();
         if (lane == 0) s.W[c] = ck | 1ull;
         cursor = c + 1;
         const uint32_t cid = key_id(ck);
@@ -492,6 +632,9 @@ __global__ __launch_bounds__(64) void search_kernel(DevIndex ix, SearchArgs a) {
         n_exp0 += 1;
         const int lbmin = merge_into_w(s, m, ef, wsize);
         if (lbmin < cursor) cursor = lbmin;
+        if (LEARN && n_exp0 % a.mlp.period == 0 && lst.ckpt < a.mlp.max_ckpt &&
+            learned_checkpoint(s, a.mlp, lst, n_exp0, a.k, cursor, ef, wsize))
+            break;
     }
 
     uint32_t n_rerank = 0;
@@ -531,10 +674,20 @@ __global__ __launch_bounds__(64) void search_kernel(DevIndex ix, SearchArgs a) {
 template <int G, int F, int KIND>
 hipError_t launch_gfk(const DevIndex &ix, const SearchArgs &a, hipStream_t stream) {
     const size_t lds = search_lds_bytes(a);
+    if constexpr (KIND == kF32) {
+        if (a.mode == HNSW_MODE_LEARNED) {
+            if (ix.metric == HNSW_IP)
+                hipLaunchKernelGGL((search_kernel<G, F, HNSW_IP, KIND, true>), dim3(a.nq), dim3(64), lds, stream, ix, a);
+            else
+                hipLaunchKernelGGL((search_kernel<G, F, HNSW_L2SQ, KIND, true>), dim3(a.nq), dim3(64), lds, stream, ix,
+                                   a);
+            return hipGetLastError();
+        }
+    }
     if (ix.metric == HNSW_IP)
-        hipLaunchKernelGGL((search_kernel<G, F, HNSW_IP, KIND>), dim3(a.nq), dim3(64), lds, stream, ix, a);
+        hipLaunchKernelGGL((search_kernel<G, F, HNSW_IP, KIND, false>), dim3(a.nq), dim3(64), lds, stream, ix, a);
     else
-        hipLaunchKernelGGL((search_kernel<G, F, HNSW_L2SQ, KIND>), dim3(a.nq), dim3(64), lds, stream, ix, a);
+        hipLaunchKernelGGL((search_kernel<G, F, HNSW_L2SQ, KIND, false>), dim3(a.nq), dim3(64), lds, stream, ix, a);
     return hipGetLastError();
 }
 
@@ -581,7 +734,8 @@ TileShape tile_for(int kind, uint32_t dim) {
 }
 
 size_t search_lds_bytes(const SearchArgs &a) {
-    return static_cast<size_t>(a.wpow2) * 8 + 64 * 8 * 2 + 64 * 4 + (static_cast<size_t>(1) << a.ht_log2) * 4;
+    return static_cast<size_t>(a.wpow2) * 8 + 64 * 8 + 64 * 4 * 2 + 128 * 4 +
+           (static_cast<size_t>(1) << a.ht_log2) * 4;
 }
 
 hipError_t launch_search(const DevIndex &ix, const SearchArgs &a, hipStream_t stream) {

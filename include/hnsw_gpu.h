@@ -193,6 +193,16 @@ hnsw_status hnsw_mlp_create(const float *params, float tau, int jmax, uint32_t p
                             hnsw_mlp **out);
 void hnsw_mlp_free(hnsw_mlp *mlp);
 
+/*
+ * hnsw_search_batch_ex in HNSW_MODE_LEARNED that also records, for each
+ * query and checkpoint, the 24 features and the two network outputs:
+ * trace_out is device fp32 [n][max_ckpt][26] (rows of checkpoints not
+ * reached are left untouched).  For inspecting and testing the stop rule.
+ */
+hnsw_status hnsw_search_learned_trace(const hnsw_index *index, const float *queries, uint32_t n, uint32_t k,
+                                      uint32_t ef, const hnsw_mlp *mlp, int32_t *ids_out, float *dists_out,
+                                      uint32_t *counters, float *trace_out, void *stream);
+
 /* FP32 training kernels (all pointers device memory, enqueued on `stream`):
  *   forward: out[n][2] = perceptron(x[n][24]) with parameters `params`.
  *   grad:    gradient (HNSW_MLP_PARAMS values) and mean loss of

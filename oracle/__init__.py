@@ -261,6 +261,17 @@ MLP_IN, MLP_HID, MLP_OUT = 24, 64, 2
 MLP_PARAMS = MLP_HID * MLP_IN + MLP_HID + MLP_HID * MLP_HID + MLP_HID + MLP_OUT * MLP_HID + MLP_OUT
 
 
+def bf16_net(params):
+    """The inference form of fp32 parameters: weights rounded to BF16 (nearest
+    even, by the oracle's own rounding), biases kept in float."""
+    p = np.array(params, dtype=np.float32, copy=True)
+    nW1, nW2, nW3 = MLP_HID * MLP_IN, MLP_HID * MLP_HID, MLP_OUT * MLP_HID
+    for lo, n in ((0, nW1), (nW1 + MLP_HID, nW2), (nW1 + MLP_HID + nW2 + MLP_HID, nW3)):
+        _, dec, _ = quantize_bf16(p[lo:lo + n].reshape(1, -1))
+        p[lo:lo + n] = dec.ravel()
+    return p
+
+
 def mlp_forward_bf16(net, feat):
     """The stop-rule perceptron exactly as the search applies it (BF16 inputs and
     hidden values, float accumulation in input order)."""

@@ -53,7 +53,15 @@ SIGNATURES = {
     "hnsw_bruteforce_knn": (C.c_int, [_vp, _vp, _u32, _u32, _vp, _vp, _vp]),
     "hnsw_index_add_lowp": (C.c_int, [_vp, _i32, _vp]),
     "hnsw_index_read_lowp": (C.c_int, [_vp, _i32, _vp, _vp]),
+    "hnsw_search_learned_trace": (C.c_int, [_vp, _vp, _u32, _u32, _u32, _vp, _vp, _vp, _vp, _vp, _vp]),
+    "hnsw_mlp_create": (C.c_int, [_vp, C.c_float, _i32, _u32, _u32, C.POINTER(_vp)]),
+    "hnsw_mlp_free": (None, [_vp]),
+    "hnsw_mlp_forward": (C.c_int, [_vp, _vp, _u32, _vp, _vp]),
+    "hnsw_mlp_grad": (C.c_int, [_vp, _vp, _vp, _u32, C.c_float, _vp, _vp, _vp]),
+    "hnsw_mlp_adam": (C.c_int, [_vp, _vp, _vp, _vp, C.c_float, C.c_float, C.c_float, C.c_float, _u32, _vp]),
 }
+
+MLP_PARAMS = 5890
 
 _lib = None
 
@@ -128,6 +136,22 @@ class Index:
         keys = ["n", "dim", "metric", "M", "Mmax", "Mmax0", "max_level", "entry_point", "device_bytes"]
         return {k: int(v) for k, v in zip(keys, out)}
 
+    def search_learned_trace(self, queries, k: int, ef: int, mlp, stream=None):
+        """Learned search that also returns per-checkpoint features and outputs
+        (float32 [n][max_ckpt][26], NaN where a checkpoint was not reached)."""
+        import torch
+
+        q = queries.contiguous()
+        n = q.shape[0]
+        ids = torch.empty((n, k), dtype=torch.int32, device=q.device)
+        dists = torch.empty((n, k), dtype=torch.float32, device=q.device)
+        cnt = torch.zeros((n, 4), dtype=torch.int32, device=q.device)
+        tr = torch.full((n, mlp.max_ckpt, 26), float("nan"), dtype=torch.float32, device=q.device)
+        _check("hnsw_search_learned_trace", lib().hnsw_search_learned_trace(
+            self._h, _dptr(q), n, k, ef, mlp.handle, _dptr(ids), _dptr(dists), _dptr(cnt), _dptr(tr),
+            _stream_ptr(stream)))
+        return ids, dists, cnt, tr
+
     def add_lowp(self, kind: int, stream=None):
         """Quantise the store on the device (``MODE_BF16`` or ``MODE_FP8``)."""
         _check("hnsw_index_add_lowp", lib().hnsw_index_add_lowp(self._h, kind, _stream_ptr(stream)))
@@ -184,6 +208,69 @@ class Index:
                                           _dptr(cnt) if cnt is not None else None, _stream_ptr(stream))
         _check("hnsw_search_batch_ex", code)
         return (ids, dists, cnt) if counters else (ids, dists)
+
+
+class Mlp:
+    """An inference net of the learned stop rule (``hnsw_mlp``).
+
+    ``params``: fp32 [MLP_PARAMS] (W1[64][24], b1, W2[64][64], b2, W3[2][64], b3);
+    ``tau``: stop threshold on output 0; ``jmax``: most ef halvings at the first
+    checkpoint; ``period``/``max_ckpt``: checkpoint spacing and count.
+    """
+
+    def __init__(self, params, tau=0.0, jmax=0, period=8, max_ckpt=64):
+        p = np.ascontiguousarray(params, dtype=np.float32)
+        if p.size != MLP_PARAMS:
+            raise ValueError(f"expected {MLP_PARAMS} parameters, got {p.size}")
+        h = C.c_void_p()
+        _check("hnsw_mlp_create", lib().hnsw_mlp_create(_np(p), float(tau), int(jmax), int(period), int(max_ckpt),
+                                                        C.byref(h)))
+        self._h = h
+        self.params, self.tau, self.jmax, self.period, self.max_ckpt = p, tau, jmax, period, max_ckpt
+
+    @property
+    def handle(self):
+        return self._h
+
+    def save(self, path: str):
+        np.savez(path, params=self.params, tau=self.tau, jmax=self.jmax, period=self.period, max_ckpt=self.max_ckpt)
+
+    @classmethod
+    def load(cls, path: str) -> "Mlp":
+        z = np.load(path)
+        return cls(z["params"], float(z["tau"]), int(z["jmax"]), int(z["period"]), int(z["max_ckpt"]))
+
+    def __del__(self):
+        if getattr(self, "_h", None):
+            lib().hnsw_mlp_free(self._h)
+            self._h = None
+
+
+def mlp_forward(params, x, stream=None):
+    """FP32 forward of the perceptron: out [n][2] for device tensors params [MLP_PARAMS], x [n][24]."""
+    import torch
+
+    out = torch.empty((x.shape[0], 2), dtype=torch.float32, device=x.device)
+    _check("hnsw_mlp_forward", lib().hnsw_mlp_forward(_dptr(params), _dptr(x), x.shape[0], _dptr(out),
+                                                      _stream_ptr(stream)))
+    return out
+
+
+def mlp_grad(params, x, y, lam=1.0, stream=None):
+    """Gradient [MLP_PARAMS] and mean loss of the training objective (device tensors)."""
+    import torch
+
+    g = torch.empty(MLP_PARAMS, dtype=torch.float32, device=x.device)
+    loss = torch.empty(1, dtype=torch.float32, device=x.device)
+    _check("hnsw_mlp_grad", lib().hnsw_mlp_grad(_dptr(params), _dptr(x), _dptr(y), x.shape[0], float(lam), _dptr(g),
+                                                _dptr(loss), _stream_ptr(stream)))
+    return g, loss
+
+
+def mlp_adam(params, grad, m, v, lr, step, beta1=0.9, beta2=0.999, eps=1e-8, stream=None):
+    _check("hnsw_mlp_adam", lib().hnsw_mlp_adam(_dptr(params), _dptr(grad), _dptr(m), _dptr(v), float(lr),
+                                                float(beta1), float(beta2), float(eps), int(step),
+                                                _stream_ptr(stream)))
 
 
 def bruteforce(index: Index, queries, k: int, stream=None):

@@ -211,9 +211,9 @@ hnsw_status hnsw_index_info(const hnsw_index *index, uint64_t out[9]) {
     return HNSW_OK;
 }
 
-hnsw_status hnsw_search_batch_ex(const hnsw_index *index, const float *queries, uint32_t n, uint32_t k, uint32_t ef,
-                                 int mode, const void *mlp, int32_t *ids_out, float *dists_out, uint32_t *counters,
-                                 void *stream) {
+static hnsw_status search_impl(const hnsw_index *index, const float *queries, uint32_t n, uint32_t k, uint32_t ef,
+                               int mode, const void *mlp, int32_t *ids_out, float *dists_out, uint32_t *counters,
+                               float *trace, void *stream) {
     if (!index) return HNSW_ERR_INVALID_ARG;
     if (k == 0 || ef == 0) return HNSW_ERR_INVALID_ARG;
     if (mode < HNSW_MODE_PLAIN || mode > HNSW_MODE_LEARNED) return HNSW_ERR_UNSUPPORTED;
@@ -226,6 +226,7 @@ hnsw_status hnsw_search_batch_ex(const hnsw_index *index, const float *queries, 
     if (n == 0) return HNSW_OK;
     if (!is_device_ptr(queries) || !is_device_ptr(ids_out) || !is_device_ptr(dists_out)) return HNSW_ERR_INVALID_ARG;
     if (counters && !is_device_ptr(counters)) return HNSW_ERR_INVALID_ARG;
+    if (trace && !is_device_ptr(trace)) return HNSW_ERR_INVALID_ARG;
 
     hnsw::SearchArgs a{};
     a.queries = queries;
@@ -250,11 +251,26 @@ hnsw_status hnsw_search_batch_ex(const hnsw_index *index, const float *queries, 
     a.mode = mode;
     a.mlp = hnsw::DevMlp{};
     if (mode == HNSW_MODE_LEARNED) a.mlp = static_cast<const hnsw_mlp *>(mlp)->net;
+    a.ckpt_trace = mode == HNSW_MODE_LEARNED ? trace : nullptr;
     if (hnsw::launch_search(index->ix, a, static_cast<hipStream_t>(stream)) != hipSuccess) {
         (void)hipGetLastError();
         return HNSW_ERR_DEVICE;
     }
     return HNSW_OK;
+}
+
+hnsw_status hnsw_search_batch_ex(const hnsw_index *index, const float *queries, uint32_t n, uint32_t k, uint32_t ef,
+                                 int mode, const void *mlp, int32_t *ids_out, float *dists_out, uint32_t *counters,
+                                 void *stream) {
+    return search_impl(index, queries, n, k, ef, mode, mlp, ids_out, dists_out, counters, nullptr, stream);
+}
+
+hnsw_status hnsw_search_learned_trace(const hnsw_index *index, const float *queries, uint32_t n, uint32_t k,
+                                      uint32_t ef, const hnsw_mlp *mlp, int32_t *ids_out, float *dists_out,
+                                      uint32_t *counters, float *trace_out, void *stream) {
+    if (!mlp || !trace_out) return HNSW_ERR_INVALID_ARG;
+    return search_impl(index, queries, n, k, ef, HNSW_MODE_LEARNED, mlp, ids_out, dists_out, counters, trace_out,
+                       stream);
 }
 
 hnsw_status hnsw_index_add_lowp(hnsw_index *index, int kind, void *stream) {

@@ -51,6 +51,7 @@ struct SearchArgs {
     uint32_t ht_log2;      // visited-table slots = 1 << ht_log2
     int mode;              // hnsw_mode
     DevMlp mlp;            // learned stop rule (mode HNSW_MODE_LEARNED)
+    float *ckpt_trace;     // learned mode: [nq][max_ckpt][26] features + outputs per checkpoint, or null
 };
 
 // Vector tile shape for a dimension: G lanes share one vector, each lane

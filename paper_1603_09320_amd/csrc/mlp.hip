@@ -105,8 +105,7 @@ __global__ __launch_bounds__(256) void mlp_wave_kernel(const float *P, const flo
     pp[oW3 + lane] = gW3[0];
     pp[oW3 + kHid + lane] = gW3[1];
     if (lane < kOut) pp[ob3 + lane] = gb3[lane];
-    const float l = wave_sum(loss);
-    if (lane == 0) loss_part[wave] = l;
+    if (lane == 0) loss_part[wave] = loss;  // every lane holds the same per-sample sum
 }
 
 // grad[p] = sum over waves of partial[wave][p] (fixed order); loss likewise.

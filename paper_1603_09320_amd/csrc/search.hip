@@ -424,7 +424,7 @@ __device__ __forceinline__ float bf16_value(uint16_t b) { return __uint_as_float
 
 // Returns true when the rule stops the search; may lower ef and wsize.
 __device__ bool learned_checkpoint(const WaveLds &s, const DevMlp &net, LearnState &st, uint32_t n_exp0,
-                                   uint32_t K, int cursor, uint32_t &ef, uint32_t &wsize) {
+                                   uint32_t K, int cursor, uint32_t &ef, uint32_t &wsize, float *trace) {
     const int lane = lane_id();
     const uint32_t ck = ++st.ckpt;
     const uint32_t n = wsize;
@@ -504,6 +504,12 @@ __device__ bool learned_checkpoint(const WaveLds &s, const DevMlp &net, LearnSta
     for (int i = 0; i < kMlpHid; ++i) a = fmaf(bf16_value(net.w3[o * kMlpHid + i]), s.hid[64 + i], a);
     const float out0 = __shfl(a, 0, 64), out1 = __shfl(a, 1, 64);
     wave_sync();
+    if (trace && lane == 0) {
+        float *t = trace + static_cast<size_t>(ck - 1) * (kMlpIn + 2);
+        for (int i = 0; i < kMlpIn; ++i) t[i] = f[i];
+        t[kMlpIn] = out0;
+        t[kMlpIn + 1] = out1;
+    }
     if (ck == 1 && net.jmax > 0) {
         int j = static_cast<int>(floorf(0.5f - out1));
         j = j < 0 ? 0 : (j > net.jmax ? net.jmax : j);
@@ -633,7 +639,9 @@ __global__ __launch_bounds__(64) void search_kernel(DevIndex ix, SearchArgs a) {
         const int lbmin = merge_into_w(s, m, ef, wsize);
         if (lbmin < cursor) cursor = lbmin;
         if (LEARN && n_exp0 % a.mlp.period == 0 && lst.ckpt < a.mlp.max_ckpt &&
-            learned_checkpoint(s, a.mlp, lst, n_exp0, a.k, cursor, ef, wsize))
+            learned_checkpoint(s, a.mlp, lst, n_exp0, a.k, cursor, ef, wsize,
+                               a.ckpt_trace ? a.ckpt_trace + static_cast<size_t>(qi) * a.mlp.max_ckpt * (kMlpIn + 2)
+                                            : nullptr))
             break;
     }
 

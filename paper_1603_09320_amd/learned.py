@@ -1,0 +1,138 @@
+"""Training and calibration of the learned stop rule on the GPU.
+
+The perceptron (24-64-64-2) is trained in FP32 by the library's own forward/
+backward/Adam kernels on checkpoint traces (features and labels written by
+graph-side tooling from the reference search), then converted to the BF16
+inference net used inside the search kernel.  The stop threshold tau is
+calibrated on held-out queries against the exact brute-force answer: the
+largest-throughput tau whose mean recall@K reaches the target.
+
+    python -m paper_1603_09320_amd.learned train --traces T.npz --out net.npz
+    python -m paper_1603_09320_amd.learned calibrate --workload glove_like --net net.npz
+"""
+from __future__ import annotations
+
+import argparse
+import math
+import os
+import sys
+import time
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+ROOT = os.path.dirname(HERE)
+
+
+def init_params(seed: int = 0) -> np.ndarray:
+    """He-normal weights, zero biases, in the library's flat layout."""
+    g = np.random.default_rng(seed)
+    parts = [g.normal(0, math.sqrt(2 / 24), 64 * 24), np.zeros(64), g.normal(0, math.sqrt(2 / 64), 64 * 64),
+             np.zeros(64), g.normal(0, math.sqrt(1 / 64), 2 * 64), np.zeros(2)]
+    return np.concatenate(parts).astype(np.float32)
+
+
+def train(feats, labels, epochs=6, batch=4096, lr=2e-3, lam=0.25, seed=0, log=print):
+    """Mini-batch Adam on the GPU; returns the fp32 parameters."""
+    import torch
+
+    import paper_1603_09320_amd as hnsw
+
+    dev = torch.device("cuda")
+    X = torch.from_numpy(np.ascontiguousarray(feats, dtype=np.float32)).to(dev)
+    Y = torch.from_numpy(np.ascontiguousarray(labels, dtype=np.float32)).to(dev)
+    P = torch.from_numpy(init_params(seed)).to(dev)
+    M = torch.zeros_like(P)
+    V = torch.zeros_like(P)
+    n = X.shape[0]
+    gen = torch.Generator(device=dev)
+    gen.manual_seed(seed)
+    step = 0
+    for ep in range(epochs):
+        perm = torch.randperm(n, device=dev, generator=gen)
+        tot, nb = 0.0, 0
+        for s in range(0, n - batch + 1, batch):
+            sel = perm[s:s + batch]
+            xb, yb = X[sel].contiguous(), Y[sel].contiguous()
+            g, loss = hnsw.mlp_grad(P, xb, yb, lam=lam)
+            step += 1
+            hnsw.mlp_adam(P, g, M, V, lr, step)
+            tot += float(loss) if nb % 50 == 0 else 0.0
+            nb += 1
+        log(f"[train] epoch {ep}: {nb} steps, sampled loss {tot / max(1, (nb + 49) // 50):.4f}")
+    return P.cpu().numpy()
+
+
+def calibrate(workload, params, taus, K=10, ef=512, jmax=5, nq=2000, target=0.95, log=print):
+    """Recall and throughput of the learned search for each tau on held-out queries."""
+    import torch
+
+    import paper_1603_09320_amd as hnsw
+    import synthdata
+
+    paths = {"glove_like": "graphs/glove_like_1200k.bin", "sift_like": "graphs/sift_like_1M.bin",
+             "deep_like": "graphs/deep_like_1M.bin", "uniform4": "graphs/uniform4_1M.bin"}
+    g = hnsw.graphfile.read(os.path.join(ROOT, paths[workload]))
+    X = synthdata.base(workload, g["n"])
+    # held-out queries: the training seed's stream beyond the traced ones
+    Q = synthdata.queries(workload, 100000 + nq, train=True)[100000:]
+    idx = hnsw.Index(g, X)
+    q = torch.from_numpy(Q).cuda()
+    _, gt = hnsw.bruteforce(idx, q, K)
+    gt = gt.cpu().numpy()
+    rows = []
+    for tau in taus:
+        mlp = hnsw.Mlp(params, tau=tau, jmax=jmax)
+        ids, _ = idx.search(q, K, ef, mode=hnsw.MODE_LEARNED, mlp=mlp)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(3):
+            idx.search(q, K, ef, mode=hnsw.MODE_LEARNED, mlp=mlp)
+        torch.cuda.synchronize()
+        ms = (time.perf_counter() - t0) * 1000 / 3
+        idn = ids.cpu().numpy()
+        x = X[np.clip(idn, 0, None)].astype(np.float64)
+        if g["metric"] == 1:
+            d = 1.0 - (x * Q[:, None, :].astype(np.float64)).sum(-1)
+        else:
+            d = ((x - Q[:, None, :].astype(np.float64)) ** 2).sum(-1)
+        rec = float(((d <= gt[:, K - 1:K]).sum(1) / K).mean())
+        rows.append((tau, rec, ms))
+        log(f"[calibrate] tau={tau:+.3f} recall={rec:.4f} ms={ms:.3f}")
+    ok = [r for r in rows if r[1] >= target]
+    best = min(ok, key=lambda r: r[2]) if ok else max(rows, key=lambda r: r[1])
+    return best, rows
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    sub = ap.add_subparsers(dest="cmd", required=True)
+    t = sub.add_parser("train")
+    t.add_argument("--traces", required=True)
+    t.add_argument("--out", required=True)
+    t.add_argument("--epochs", type=int, default=6)
+    c = sub.add_parser("calibrate")
+    c.add_argument("--workload", required=True)
+    c.add_argument("--net", required=True)
+    c.add_argument("--ef", type=int, default=512)
+    c.add_argument("--jmax", type=int, default=5)
+    c.add_argument("--target", type=float, default=0.95)
+    a = ap.parse_args()
+    sys.path.insert(0, ROOT)
+    if a.cmd == "train":
+        z = np.load(a.traces)
+        P = train(z["feats"], z["labels"], epochs=a.epochs)
+        np.savez(a.out, params=P, tau=0.0, jmax=int(z["jmax"]), period=int(z["period"]),
+                 max_ckpt=int(z["max_ckpt"]), ef=int(z["ef"]))
+        print(f"[train] wrote {a.out}", flush=True)
+    else:
+        z = np.load(a.net)
+        taus = [4.0, 3.0, 2.0, 1.5, 1.0, 0.5, 0.0, -0.5]
+        best, rows = calibrate(a.workload, z["params"], taus, ef=a.ef, jmax=a.jmax, target=a.target)
+        np.savez(a.net, params=z["params"], tau=best[0], jmax=a.jmax, period=int(z["period"]),
+                 max_ckpt=int(z["max_ckpt"]), ef=a.ef, calib=np.array(rows))
+        print(f"[calibrate] chose tau={best[0]} recall={best[1]:.4f} ms={best[2]:.3f}", flush=True)
+
+
+if __name__ == "__main__":
+    main()

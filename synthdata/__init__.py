@@ -12,7 +12,8 @@ Workloads (stand-ins for the paper's datasets, which are not available):
   sigma 20, rounded half-to-even and clamped to the integers 0..255, stored fp32;
   10,000 queries from the same mixture.  Stand-in for SIFT 1M (Table 1).
 * ``glove_like``  -- 1,200,000 x 100 unit vectors from 2,000 clusters with
-  Zipf(1.1) sizes; inner-product metric.  Stand-in for GloVe 1.2M angular (Table 1).
+  Zipf(1.1) sizes, x = normalise(mu + 0.6 g / 10); inner-product metric.
+  Stand-in for GloVe 1.2M angular (Table 1).
 * ``deep_like``   -- d=96 Gaussian mixture with 10,000 centres N(0, I) and spread
   0.5.  Stand-in for DEEP (Table 1).
 * ``uniform4``    -- 1,000,000 x 4 U[0,1).  Stand-in for the d=4 random sets
@@ -77,7 +78,7 @@ def _glove_mixture(seed: int):
     return mu, w / w.sum()
 
 
-def _glove_points(n: int, seed: int, mix, sigma: float = 1.0) -> np.ndarray:
+def _glove_points(n: int, seed: int, mix, sigma: float = 0.6) -> np.ndarray:
     mu, w = mix
     ga, gn = _rng(seed, 1), _rng(seed, 2)
     counts = ga.multinomial(n, w)

@@ -1,0 +1,138 @@
+"""The learned stop rule on the GPU: perceptron training kernels against the
+fp64 reference (gradient check), and the learned search against the
+oracle's learned search with the same network."""
+import numpy as np
+import pytest
+
+import oracle
+import synthdata
+from oracle import mlp_ref
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module")
+def hnsw():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_1603_09320_amd as h
+
+    h.lib()
+    return h
+
+
+def _batch(n, seed):
+    g = np.random.default_rng(seed)
+    X = g.normal(size=(n, 24)).astype(np.float32)
+    Y = np.stack([g.integers(0, 2, n), g.uniform(0.5, 2.0, n), g.normal(size=n), g.integers(0, 2, n)],
+                 axis=1).astype(np.float32)
+    return X, Y
+
+
+@pytest.mark.parametrize("n", [1, 63, 1000, 4099])
+def test_mlp_forward_and_gradient_match_fp64(hnsw, n):
+    print(f"case mlp grad n={n}", flush=True)
+    p = mlp_ref.init(n)
+    X, Y = _batch(n, n + 1)
+    P, Xd, Yd = (torch.from_numpy(a).cuda() for a in (p, X, Y))
+    z = hnsw.mlp_forward(P, Xd).cpu().numpy().astype(np.float64)
+    zr, _ = mlp_ref.forward(p.astype(np.float64), X)
+    assert np.abs(z - zr).max() <= 1e-5 * max(1.0, np.abs(zr).max())
+    g, loss = hnsw.mlp_grad(P, Xd, Yd, lam=0.7)
+    lr, gr = mlp_ref.loss_and_grad(p.astype(np.float64), X, Y, lam=0.7)
+    g = g.cpu().numpy().astype(np.float64)
+    assert np.linalg.norm(g - gr) <= 1e-4 * np.linalg.norm(gr)
+    assert abs(float(loss.cpu()) - lr) <= 1e-5 * max(1.0, abs(lr))
+
+
+def test_adam_step_matches_reference(hnsw):
+    p = mlp_ref.init(1)
+    g = np.random.default_rng(2).normal(size=p.size).astype(np.float32)
+    m = np.zeros_like(p)
+    v = np.zeros_like(p)
+    P, G, Md, Vd = (torch.from_numpy(a.copy()).cuda() for a in (p, g, m, v))
+    pr, mr, vr = p.astype(np.float64), m.astype(np.float64), v.astype(np.float64)
+    for step in (1, 2, 3):
+        hnsw.mlp_adam(P, G, Md, Vd, 1e-3, step)
+        pr, mr, vr = mlp_ref.adam_step(pr, g.astype(np.float64), mr, vr, 1e-3, step)
+    assert np.allclose(P.cpu().numpy(), pr, rtol=1e-5, atol=1e-7)
+
+
+def _net_with_spread_stops(G, Q, K, ef, seed):
+    """A random net (weights already BF16 values) whose stop threshold sits
+    inside the spread of its logits."""
+    net = oracle.bf16_net(mlp_ref.init(seed))
+    r = G.search_learned(Q, K, ef, trace=True, nthreads=8)
+    feats = np.concatenate([r["feat"][i, :r["info"][i, 0]] for i in range(len(Q))])
+    out = oracle.mlp_forward_bf16(net, feats)
+    tau = float(np.quantile(out[:, 0], 0.8))
+    # centre output 1 around -1.5 so the first checkpoint halves ef 0..3 times
+    net[-1] = np.float32(net[-1] - np.median(out[:, 1]) - 1.5)
+    return net, tau
+
+
+@pytest.mark.parametrize("workload,metric,n", [("uniform16", oracle.L2, 10000), ("glove_like", oracle.IP, 20000)])
+def test_checkpoint_features_and_outputs_equal_oracle(hnsw, workload, metric, n):
+    """With a threshold that never stops, every checkpoint's 24 features and both
+    network outputs equal the oracle's bit for bit."""
+    print(f"case learned features {workload}", flush=True)
+    X = synthdata.base(workload, n)
+    Q = synthdata.queries(workload, 300)
+    G = oracle.Graph.build(X, metric=metric, M=16, efC=100, seed=7)
+    net = mlp_ref.init(5)
+    r = G.search_learned(Q, 10, 200, trace=True, nthreads=8)
+    mlp = hnsw.Mlp(net, tau=1e30, jmax=0)
+    net = oracle.bf16_net(net)
+    idx = hnsw.Index(G.packed(), X)
+    ids, ds, cnt, tr = idx.search_learned_trace(torch.from_numpy(Q).cuda(), 10, 200, mlp)
+    torch.cuda.synchronize()
+    tr = tr.cpu().numpy()
+    assert np.array_equal(ids.cpu().numpy(), r["ids"])
+    for i in range(len(Q)):
+        k = int(r["info"][i, 0])
+        assert np.isnan(tr[i, k:]).all() and not np.isnan(tr[i, :k]).any(), i
+        bad = np.argwhere(tr[i, :k, :24] != r["feat"][i, :k])
+        assert bad.size == 0, (i, bad[:5], tr[i, bad[0][0], bad[0][1]], r["feat"][i, bad[0][0], bad[0][1]])
+        out = oracle.mlp_forward_bf16(net, r["feat"][i, :k])
+        assert np.array_equal(tr[i, :k, 24:], out), i
+
+
+@pytest.mark.parametrize("workload,metric,n,dim_ef", [("uniform16", oracle.L2, 10000, 200),
+                                                      ("glove_like", oracle.IP, 20000, 256),
+                                                      ("sift_like", oracle.L2, 20000, 128)])
+def test_learned_search_parity(hnsw, workload, metric, n, dim_ef):
+    print(f"case learned parity {workload} n={n}", flush=True)
+    X = synthdata.base(workload, n)
+    Q = synthdata.queries(workload, 400)
+    G = oracle.Graph.build(X, metric=metric, M=16, efC=100, seed=7)
+    K, ef = 10, dim_ef
+    net, tau = _net_with_spread_stops(G, Q, K, ef, seed=11)
+    for jmax in (0, 3):
+        ro = G.search_learned(Q, K, ef, net=net, tau=tau, jmax=jmax, nthreads=8)
+        stopped = (ro["info"][:, 1] > 0).mean()
+        mlp = hnsw.Mlp(net, tau=tau, jmax=jmax)
+        idx = hnsw.Index(G.packed(), X)
+        ids, ds, cnt = idx.search(torch.from_numpy(Q).cuda(), K, ef, mode=hnsw.MODE_LEARNED, mlp=mlp,
+                                  counters=True)
+        torch.cuda.synchronize()
+        ids, ds, cnt = ids.cpu().numpy(), ds.cpu().numpy(), cnt.cpu().numpy().astype(np.uint32)
+        print(f"  jmax={jmax}: oracle stopped {stopped:.2f} of queries, efs {np.unique(ro['info'][:, 2])}",
+              flush=True)
+        assert 0.05 < stopped < 0.95
+        assert np.array_equal(ids, ro["ids"]) and np.array_equal(ds, ro["dists"])
+        assert np.array_equal(cnt[:, 3], ro["counters"][:, 3].astype(np.uint32))
+
+
+def test_learned_mode_without_net_is_plain(hnsw):
+    X = synthdata.base("uniform16", 5000)
+    Q = synthdata.queries("uniform16", 100)
+    G = oracle.Graph.build(X, M=16, efC=100, seed=1003)
+    idx = hnsw.Index(G.packed(), X)
+    q = torch.from_numpy(Q).cuda()
+    a = idx.search(q, 10, 64)
+    b = idx.search(q, 10, 64, mode=hnsw.MODE_LEARNED, mlp=None)
+    torch.cuda.synchronize()
+    assert torch.equal(a[0], b[0]) and torch.equal(a[1], b[1])
+    with pytest.raises(hnsw.HnswError):
+        hnsw.Mlp(np.full(hnsw.MLP_PARAMS, np.nan, np.float32))

@@ -44,7 +44,8 @@ typedef enum {
     HNSW_ERR_OUT_OF_MEMORY = 2, /* device allocation failed                          */
     HNSW_ERR_DEVICE = 3,        /* no device, launch or runtime failure              */
     HNSW_ERR_UNSUPPORTED = 4,   /* a size beyond the kernels' limits (dim, ef, deg)  */
-    HNSW_ERR_FORMAT = 5         /* inconsistent graph description                    */
+    HNSW_ERR_FORMAT = 5,        /* inconsistent graph description                    */
+    HNSW_ERR_BUSY = 6           /* serving: no free request slot, submit again later */
 } hnsw_status;
 
 typedef enum { HNSW_L2SQ = 0, HNSW_IP = 1 } hnsw_metric;
@@ -215,6 +216,52 @@ hnsw_status hnsw_mlp_grad(const float *params, const float *x, const float *y, u
                           float *loss, void *stream);
 hnsw_status hnsw_mlp_adam(float *params, const float *grad, float *m, float *v, float lr, float beta1, float beta2,
                           float eps, uint32_t step, void *stream);
+
+/*
+ * Continuous-batching server over one index: a persistent kernel whose waves
+ * take requests in submission order, each with its own k, ef and mode, while
+ * new requests keep arriving; a wave that finishes one request takes the next
+ * without waiting for the others (requests overlap on the device).
+ *   slots     ring size = most requests in flight (their outputs live in
+ *             pinned host memory: the output budget).
+ *   waves     persistent wavefronts (each reserves LDS for ef_max).
+ *   ef_max    largest ef (after ef := max(ef, k)) a request may use;
+ *   k_max     largest k; larger requests are refused (HNSW_ERR_UNSUPPORTED).
+ *   mlp       net for HNSW_MODE_LEARNED requests (NULL: those run plain).
+ *             Modes served: PLAIN, BF16 (after hnsw_index_add_lowp) and
+ *             LEARNED; FP8 requests are refused (HNSW_ERR_UNSUPPORTED).
+ *   budget_s  wall-clock seconds after which every wave exits even without a
+ *             stop (a bound on the kernel's lifetime).
+ * The server runs on a stream of its own.  Results are bit-identical to
+ * hnsw_search_batch_ex with the same (query, k, ef, mode).
+ */
+typedef struct hnsw_server hnsw_server;
+hnsw_status hnsw_server_start(const hnsw_index *index, const hnsw_mlp *mlp, uint32_t slots, uint32_t waves,
+                              uint32_t ef_max, uint32_t k_max, double budget_s, hnsw_server **out);
+/* Admit one request (host query [dim]); HNSW_ERR_BUSY while its slot is still
+ * occupied (backpressure).  *ticket identifies it for hnsw_server_poll. */
+hnsw_status hnsw_server_submit(hnsw_server *srv, const float *query, uint32_t k, uint32_t ef, int mode,
+                               uint64_t *ticket);
+/* Non-blocking: *done = 1 and the k results copied (host buffers) once the
+ * request has completed; its slot is then free again. */
+hnsw_status hnsw_server_poll(hnsw_server *srv, uint64_t ticket, int32_t *ids, float *dists, int *done);
+/* Stop the kernel (waits for every wave to exit) and release the server. */
+hnsw_status hnsw_server_stop(hnsw_server *srv);
+
+/*
+ * Open-loop replay of a request schedule against one or more servers (a
+ * native driver for serving measurements): request i arrives at
+ * arrival_s[i] seconds (non-decreasing) and goes to servers[server_of[i]]
+ * with query row qidx[i] of queries[server_of[i]] ([nq][dim] host), k[i],
+ * ef[i], mode[i].  It is submitted as soon as it has arrived and its slot is
+ * free, and polled until done.  Outputs (host): ids/dists [n][out_stride]
+ * (both NULL to discard results), t_submit/t_done seconds since the start.  HNSW_ERR_DEVICE if not every
+ * request completed within timeout_s.
+ */
+hnsw_status hnsw_serve_replay(hnsw_server *const *servers, uint32_t n_servers, const float *const *queries,
+                              uint64_t n, const double *arrival_s, const uint32_t *server_of, const uint32_t *qidx,
+                              const uint32_t *k, const uint32_t *ef, const int32_t *mode, uint32_t out_stride,
+                              int32_t *ids, float *dists, double *t_submit, double *t_done, double timeout_s);
 
 /* Human-readable name of a status code (static storage). */
 const char *hnsw_status_str(hnsw_status s);

@@ -22,7 +22,7 @@ MODE_PLAIN, MODE_BF16, MODE_FP8, MODE_LEARNED = 0, 1, 2, 3
 EF_MAX, DIM_MAX, DEG_MAX = 1024, 256, 64
 
 STATUS = {0: "ok", 1: "invalid argument", 2: "out of device memory", 3: "device error", 4: "unsupported size",
-          5: "malformed graph"}
+          5: "malformed graph", 6: "busy"}
 
 
 class HnswError(RuntimeError):
@@ -54,6 +54,12 @@ SIGNATURES = {
     "hnsw_index_add_lowp": (C.c_int, [_vp, _i32, _vp]),
     "hnsw_index_read_lowp": (C.c_int, [_vp, _i32, _vp, _vp]),
     "hnsw_search_learned_trace": (C.c_int, [_vp, _vp, _u32, _u32, _u32, _vp, _vp, _vp, _vp, _vp, _vp]),
+    "hnsw_server_start": (C.c_int, [_vp, _vp, _u32, _u32, _u32, _u32, C.c_double, C.POINTER(_vp)]),
+    "hnsw_server_submit": (C.c_int, [_vp, _vp, _u32, _u32, _i32, C.POINTER(_u64)]),
+    "hnsw_server_poll": (C.c_int, [_vp, _u64, _vp, _vp, C.POINTER(_i32)]),
+    "hnsw_server_stop": (C.c_int, [_vp]),
+    "hnsw_serve_replay": (C.c_int, [_vp, _u32, _vp, _u64, _vp, _vp, _vp, _vp, _vp, _vp, _u32, _vp, _vp, _vp, _vp,
+                                    C.c_double]),
     "hnsw_mlp_create": (C.c_int, [_vp, C.c_float, _i32, _u32, _u32, C.POINTER(_vp)]),
     "hnsw_mlp_free": (None, [_vp]),
     "hnsw_mlp_forward": (C.c_int, [_vp, _vp, _u32, _vp, _vp]),
@@ -271,6 +277,76 @@ def mlp_adam(params, grad, m, v, lr, step, beta1=0.9, beta2=0.999, eps=1e-8, str
     _check("hnsw_mlp_adam", lib().hnsw_mlp_adam(_dptr(params), _dptr(grad), _dptr(m), _dptr(v), float(lr),
                                                 float(beta1), float(beta2), float(eps), int(step),
                                                 _stream_ptr(stream)))
+
+
+class Server:
+    """A continuous-batching server over one index (``hnsw_server``)."""
+
+    def __init__(self, index: Index, mlp=None, slots=1024, waves=1024, ef_max=512, k_max=100, budget_s=60.0):
+        h = C.c_void_p()
+        _check("hnsw_server_start", lib().hnsw_server_start(index.handle, mlp.handle if mlp is not None else None,
+                                                            slots, waves, ef_max, k_max, float(budget_s),
+                                                            C.byref(h)))
+        self._h, self.index, self.mlp, self.k_max = h, index, mlp, k_max
+
+    @property
+    def handle(self):
+        return self._h
+
+    def submit(self, query, k: int, ef: int, mode: int = MODE_PLAIN) -> int:
+        q = np.ascontiguousarray(query, dtype=np.float32)
+        t = C.c_uint64()
+        _check("hnsw_server_submit", lib().hnsw_server_submit(self._h, _np(q), k, ef, mode, C.byref(t)))
+        return t.value
+
+    def poll(self, ticket: int, k: int):
+        ids = np.empty(k, dtype=np.int32)
+        ds = np.empty(k, dtype=np.float32)
+        d = C.c_int32()
+        _check("hnsw_server_poll", lib().hnsw_server_poll(self._h, ticket, _np(ids), _np(ds), C.byref(d)))
+        return (ids, ds) if d.value else None
+
+    def stop(self):
+        if getattr(self, "_h", None):
+            h, self._h = self._h, None
+            _check("hnsw_server_stop", lib().hnsw_server_stop(h))
+
+    def __del__(self):
+        try:
+            self.stop()
+        except Exception:
+            pass
+
+
+def replay(servers, queries, arrival_s, server_of, qidx, k, ef, mode, out_stride=None, keep_results=True,
+           timeout_s=60.0):
+    """Open-loop replay of a request schedule (``hnsw_serve_replay``).
+
+    ``queries``: one host float32 [nq][dim] array per server.  Returns dict of
+    t_submit/t_done (seconds from the start) and, with ``keep_results``,
+    ids/dists [n][out_stride].
+    """
+    n = len(arrival_s)
+    out_stride = out_stride or int(np.max(k))
+    qs = [np.ascontiguousarray(q, dtype=np.float32) for q in queries]
+    srv = (C.c_void_p * len(servers))(*[s.handle.value for s in servers])
+    qp = (C.c_void_p * len(qs))(*[q.ctypes.data for q in qs])
+    arr = np.ascontiguousarray(arrival_s, dtype=np.float64)
+    so, qi = np.ascontiguousarray(server_of, np.uint32), np.ascontiguousarray(qidx, np.uint32)
+    kk, ee, mm = np.ascontiguousarray(k, np.uint32), np.ascontiguousarray(ef, np.uint32), np.ascontiguousarray(
+        mode, np.int32)
+    ids = np.full((n, out_stride) if keep_results else (1, 1), -1, dtype=np.int32)
+    ds = np.full(ids.shape, np.inf, dtype=np.float32)
+    ts = np.zeros(n, dtype=np.float64)
+    td = np.zeros(n, dtype=np.float64)
+    code = lib().hnsw_serve_replay(srv, len(servers), qp, n, _np(arr), _np(so), _np(qi), _np(kk), _np(ee), _np(mm),
+                                   out_stride if keep_results else 0, _np(ids) if keep_results else None,
+                                   _np(ds) if keep_results else None, _np(ts), _np(td), float(timeout_s))
+    _check("hnsw_serve_replay", code)
+    out = dict(t_submit=ts, t_done=td)
+    if keep_results:
+        out.update(ids=ids, dists=ds)
+    return out
 
 
 def bruteforce(index: Index, queries, k: int, stream=None):

@@ -9,23 +9,8 @@
 
 #include "internal.h"
 
-struct hnsw_mlp {
-    hnsw::DevMlp net;
-    void *mem;
-};
 
-struct hnsw_index {
-    hnsw::DevIndex ix;
-    float *xnorm;  // [n] squared norms of the vectors (brute-force ranking)
-    uint32_t M;
-    int device;
-    uint64_t bytes;
-    std::vector<void *> allocations;
-};
-
-namespace {
-
-using hnsw::kNoLink;
+namespace hnsw {
 
 bool device_count_ok() {
     int n = 0;
@@ -54,6 +39,15 @@ uint64_t mem_cap() {
     if (!s || !*s) return UINT64_MAX;
     return strtoull(s, nullptr, 10);
 }
+
+}  // namespace hnsw
+
+namespace {
+
+using hnsw::device_count_ok;
+using hnsw::is_device_ptr;
+using hnsw::kNoLink;
+using hnsw::mem_cap;
 
 uint32_t row_floats(uint32_t dim) {
     const uint32_t v4 = (dim + 3) / 4;
@@ -130,6 +124,7 @@ const char *hnsw_status_str(hnsw_status s) {
         case HNSW_ERR_DEVICE: return "device error";
         case HNSW_ERR_UNSUPPORTED: return "unsupported size";
         case HNSW_ERR_FORMAT: return "malformed graph";
+        case HNSW_ERR_BUSY: return "busy";
     }
     return "unknown status";
 }

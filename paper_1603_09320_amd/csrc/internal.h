@@ -4,6 +4,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <vector>
+
 #include "../../include/hnsw_gpu.h"
 
 namespace hnsw {
@@ -84,4 +86,25 @@ hipError_t launch_bruteforce(const DevIndex &ix, const float *Q, uint32_t nq, ui
                              hipStream_t stream);
 hipError_t launch_search(const DevIndex &ix, const SearchArgs &a, hipStream_t stream);
 
+}  // namespace hnsw
+
+// Opaque handles of the C ABI.
+struct hnsw_mlp {
+    hnsw::DevMlp net;
+    void *mem;
+};
+
+struct hnsw_index {
+    hnsw::DevIndex ix;
+    float *xnorm;  // [n] squared norms of the vectors (brute-force ranking)
+    uint32_t M;
+    int device;
+    uint64_t bytes;
+    std::vector<void *> allocations;
+};
+
+namespace hnsw {
+bool device_count_ok();
+bool is_device_ptr(const void *p);
+uint64_t mem_cap();
 }  // namespace hnsw

@@ -1,682 +1,26 @@
-// Batched K-NN-SEARCH (Alg. 5 of arXiv:1603.09320) for gfx950.
-//
-// One wavefront (64 lanes) answers one query:
-//   1. the query is loaded into registers, split over lane groups;
-//   2. greedy descent with ef = 1 through layers L..1: SEARCH-LAYER with
-//      ef = 1 moves to the (dist, id)-smallest of the current element and its
-//      neighbours until none is smaller, so no visited set is needed there;
-//   3. SEARCH-LAYER (Alg. 2) on layer 0 with ef candidates;
-//   4. the K nearest of W are written out.
-//
-// Layer-0 state per wave, all in LDS:
-//   W    -- up to ef 64-bit keys sorted ascending; key = (ordered float bits
-//           of the distance) << 32 | id << 1 | expanded-flag.  Alg. 2 keeps
-//           the candidate set C and the list W; since an element that has
-//           left W can never be expanded again (its key exceeds that of the
-//           furthest element of W from then on), C is exactly the unexpanded
-//           part of W, so one sorted list with a flag holds both.
-//   ht   -- open-addressing visited table of element ids.  A probe run that
-//           finds no free slot reports "not visited" without recording the
-//           id: the table may forget (the element is scored again) but never
-//           reports an unseen element as visited.  A re-scored element has
-//           the same key; it is either in W (dropped by de-duplication) or
-//           above the furthest element of W (rejected), so results do not
-//           depend on the table size.
-// Each expansion reads the candidate's adjacency row (one coalesced load of
-// Mmax0 ids), filters it through ht, gathers the surviving vectors with G
-// lanes per vector, reduces each distance across its lane group with
-// cross-lane shuffles, then merges all new keys into W at once: W becomes the
-// ef smallest of W and the new keys, which is what processing the
-// neighbourhood one element at a time (Alg. 2, inner loop) produces.
-#include <climits>
-
-#include "internal.h"
+// Batched K-NN-SEARCH (Alg. 5 of arXiv:1603.09320) for gfx950: one workgroup
+// of one wavefront per query; the search itself is search_one in
+// search_device.h.
+#include "search_device.h"
 
 namespace hnsw {
 namespace {
-
-constexpr int kProbes = 4;
-
-__device__ __forceinline__ uint32_t ord_of(float f) {
-    uint32_t u = __float_as_uint(f);
-    if (u == 0x80000000u) u = 0u;  // -0 orders as +0
-    return (u & 0x80000000u) ? ~u : (u | 0x80000000u);
-}
-
-__device__ __forceinline__ float float_of(uint32_t o) {
-    const uint32_t u = (o & 0x80000000u) ? (o & 0x7FFFFFFFu) : ~o;
-    return __uint_as_float(u);
-}
-
-__device__ __forceinline__ uint64_t make_key(float d, uint32_t id) {
-    return (static_cast<uint64_t>(ord_of(d)) << 32) | (static_cast<uint64_t>(id) << 1);
-}
-__device__ __forceinline__ uint32_t key_id(uint64_t k) { return static_cast<uint32_t>(k) >> 1; }
-__device__ __forceinline__ float key_dist(uint64_t k) { return float_of(static_cast<uint32_t>(k >> 32)); }
-
-// Keeps the compiler from moving LDS accesses across this point.  A wave's
-// own LDS instructions are executed in issue order, so a later access (by
-// any lane) sees every earlier one; only the compiler's order must be pinned
-// (each workgroup is a single wave).
-__device__ __forceinline__ void wave_sync() {
-    __atomic_signal_fence(__ATOMIC_SEQ_CST);
-    __builtin_amdgcn_wave_barrier();
-    __atomic_signal_fence(__ATOMIC_SEQ_CST);
-}
-
-__device__ __forceinline__ uint64_t readlane64(uint64_t v, int lane) {
-    const uint32_t lo = __builtin_amdgcn_readlane(static_cast<uint32_t>(v), lane);
-    const uint32_t hi = __builtin_amdgcn_readlane(static_cast<uint32_t>(v >> 32), lane);
-    return (static_cast<uint64_t>(hi) << 32) | lo;
-}
-
-__device__ __forceinline__ int lane_id() { return __builtin_amdgcn_mbcnt_hi(~0u, __builtin_amdgcn_mbcnt_lo(~0u, 0)); }
-
-// Number of set bits of `mask` below this lane.
-__device__ __forceinline__ int rank_in(uint64_t mask) {
-    return __builtin_amdgcn_mbcnt_hi(static_cast<uint32_t>(mask >> 32),
-                                     __builtin_amdgcn_mbcnt_lo(static_cast<uint32_t>(mask), 0));
-}
-
-__device__ __forceinline__ uint64_t wave_min_u64(uint64_t v) {
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) {
-        const uint64_t w = __shfl_xor(v, o, 64);
-        v = w < v ? w : v;
-    }
-    return v;
-}
-
-__device__ __forceinline__ int wave_min_int(int v) {
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) {
-        const int w = __shfl_xor(v, o, 64);
-        v = w < v ? w : v;
-    }
-    return v;
-}
-
-// Test-and-set of `id` in the visited table; true when the id was not seen.
-__device__ __forceinline__ bool visit(uint32_t *ht, uint32_t shift, uint32_t mask, uint32_t id) {
-    const uint32_t h = (id * 0x9E3779B1u) >> shift;
-#pragma unroll
-    for (int p = 0; p < kProbes; ++p) {
-        const uint32_t slot = (h + p) & mask;
-        const uint32_t old = atomicCAS(&ht[slot], kNoLink, id);
-        if (old == kNoLink) return true;
-        if (old == id) return false;
-    }
-    return true;  // run full: forget, score again
-}
-
-// One DPP move of both halves of a double (gfx9 DPP controls, full rows/banks).
-template <int CTRL>
-__device__ __forceinline__ double dpp_f64(double v) {
-    const uint64_t u = static_cast<uint64_t>(__double_as_longlong(v));
-    const uint32_t lo = static_cast<uint32_t>(__builtin_amdgcn_update_dpp(0, static_cast<int>(u), CTRL, 0xF, 0xF, false));
-    const uint32_t hi =
-        static_cast<uint32_t>(__builtin_amdgcn_update_dpp(0, static_cast<int>(u >> 32), CTRL, 0xF, 0xF, false));
-    return __longlong_as_double(static_cast<long long>((static_cast<uint64_t>(hi) << 32) | lo));
-}
-
-// Sum over aligned groups of G lanes (G in {1,2,4,8,16}); every lane of a
-// group ends with the same bits: each step adds two equal-shaped partial sums
-// (xor-1 and xor-2 swaps inside a quad, then the mirrored half-row and row).
-template <int G>
-__device__ __forceinline__ double group_sum(double v) {
-    if (G >= 2) v += dpp_f64<0xB1>(v);   // quad_perm [1,0,3,2]
-    if (G >= 4) v += dpp_f64<0x4E>(v);   // quad_perm [2,3,0,1]
-    if (G >= 8) v += dpp_f64<0x141>(v);  // row_half_mirror
-    if (G >= 16) v += dpp_f64<0x140>(v); // row_mirror
-    return v;
-}
-
-// Vector stores the traversal can read.  A row is a sequence of 16-byte
-// pieces: 4 fp32, 8 bf16 or 16 fp8-E4M3 values; the FP8 row carries its
-// fp32 scale at byte offset lp_scale_off.
-enum StoreKind { kF32 = 0, kBF16 = 1, kFP8 = 2 };
-
-template <int KIND>
-struct Store;
-template <>
-struct Store<kF32> {
-    static constexpr int VPP = 4;  // values per 16-byte piece
-    using QT = double;             // query element as held in registers
-};
-template <>
-struct Store<kBF16> {
-    static constexpr int VPP = 8;
-    using QT = float;
-};
-template <>
-struct Store<kFP8> {
-    static constexpr int VPP = 16;
-    using QT = float;
-};
-
-// E4M3 (OCP) code -> float: exponent bias 7, 3 mantissa bits, subnormals m * 2^-9.
-__device__ __forceinline__ float e4m3_to_float(uint32_t b) {
-    const uint32_t e = (b >> 3) & 15u, m = b & 7u;
-    const float mag = e ? __uint_as_float(((e + 120u) << 23) | (m << 20)) : static_cast<float>(m) * 0x1.0p-9f;
-    return (b & 0x80u) ? -mag : mag;
-}
-
-// Value j of a 16-byte piece.
-template <int KIND>
-__device__ __forceinline__ float piece_value(const uint4 &p, int j) {
-    const uint32_t w = j < Store<KIND>::VPP / 4 ? p.x : (j < Store<KIND>::VPP / 2 ? p.y : (j < 3 * Store<KIND>::VPP / 4 ? p.z : p.w));
-    if (KIND == kF32) return __uint_as_float(w);
-    if (KIND == kBF16) return __uint_as_float((j & 1) ? (w & 0xFFFF0000u) : (w << 16));
-    return e4m3_to_float((w >> (8 * (j & 3))) & 0xFFu);
-}
-
-template <int G, int F, int KIND>
-struct QueryRegs {
-    typename Store<KIND>::QT q[F][Store<KIND>::VPP];  // values of pieces c = sub + f*G
-};
-
-template <int G, int F, int KIND>
-__device__ __forceinline__ void load_query(const float *qrow, uint32_t dim, QueryRegs<G, F, KIND> &Q) {
-    constexpr int V = Store<KIND>::VPP;
-    const int sub = lane_id() % G;
-#pragma unroll
-    for (int f = 0; f < F; ++f)
-#pragma unroll
-        for (int j = 0; j < V; ++j) {
-            const uint32_t e = static_cast<uint32_t>(V * (sub + f * G) + j);
-            const float x = qrow[e < dim ? e : dim - 1];
-            Q.q[f][j] = e < dim ? static_cast<typename Store<KIND>::QT>(x) : 0;
-        }
-}
-
-// Where the pieces of a row live.
-struct RowSource {
-    const uint4 *base;   // piece 0 of row 0
-    uint32_t stride;     // pieces per row
-    uint32_t pieces;     // pieces holding values (the rest of the row is padding/scale)
-    uint32_t scale_off;  // FP8: byte offset of the scale within the row
-};
-
-__device__ __forceinline__ RowSource rows_of(const DevIndex &ix, const SearchArgs &a, int kind) {
-    if (kind == kF32) return {reinterpret_cast<const uint4 *>(ix.vec), ix.stride4, ix.stride4, 0};
-    if (kind == kBF16) return {reinterpret_cast<const uint4 *>(ix.vbf16), ix.bf16_stride16, ix.bf16_stride16, 0};
-    return {reinterpret_cast<const uint4 *>(ix.vfp8), ix.fp8_stride16, ix.fp8_pieces, ix.fp8_scale_off};
-}
-
-// Scores ids[0..m) against the query; keys[slot] receives the key of ids[slot].
-// Lane group grp = lane / G handles slots grp, grp + P, ... (P = 64 / G).
-// Every load is unconditional so that all of a chunk's loads are in flight
-// together: an unused slot, and a piece beyond a row's values, read from the
-// all-zero row n instead (the address is chosen, not the value, so no load is
-// split or predicated).  Distances: sum over coordinates of (q_j - s*x_j)^2,
-// or 1 - sum q_j*s*x_j, in double (s = 1 except for FP8), rounded once to float.
-template <int G, int F, int METRIC, int KIND>
-__device__ __forceinline__ void score_ids(const DevIndex &ix, const RowSource &src, const QueryRegs<G, F, KIND> &Q,
-                                          const uint32_t *ids, int m, uint64_t *keys) {
-    constexpr int P = 64 / G;
-    constexpr int B = (32 / P) < 1 ? 1 : ((32 / P) > 4 ? 4 : (32 / P));
-    constexpr int V = Store<KIND>::VPP;
-    const int lane = lane_id();
-    const int grp = lane / G, sub = lane % G;
-    const size_t zero_row = static_cast<size_t>(ix.n) * src.stride;
-    for (int base = 0; base < m; base += P * B) {
-        uint32_t idv[B];
-#pragma unroll
-        for (int b = 0; b < B; ++b) idv[b] = ids[(base + b * P + grp) & 63];
-#pragma unroll
-        for (int b = 0; b < B; ++b) idv[b] = base + b * P + grp < m ? idv[b] : ix.n;
-        uint4 v[B][F];
-        float sc[B];
-#pragma unroll
-        for (int b = 0; b < B; ++b) {
-            const size_t row = static_cast<size_t>(idv[b]) * src.stride;
-#pragma unroll
-            for (int f = 0; f < F; ++f) {
-                const uint32_t c = static_cast<uint32_t>(sub + f * G);
-                v[b][f] = src.base[c < src.pieces ? row + c : zero_row];
-            }
-            if (KIND == kFP8)
-                sc[b] = *reinterpret_cast<const float *>(reinterpret_cast<const uint8_t *>(src.base + row) +
-                                                         src.scale_off);
-        }
-#pragma unroll
-        for (int b = 0; b < B; ++b) {
-            double acc = 0.0;
-            const double s = KIND == kFP8 ? static_cast<double>(sc[b]) : 1.0;
-#pragma unroll
-            for (int f = 0; f < F; ++f)
-#pragma unroll
-                for (int j = 0; j < V; ++j) {
-                    const double x = KIND == kFP8 ? s * static_cast<double>(piece_value<KIND>(v[b][f], j))
-                                                  : static_cast<double>(piece_value<KIND>(v[b][f], j));
-                    const double qj = static_cast<double>(Q.q[f][j]);
-                    if (METRIC == HNSW_L2SQ) {
-                        const double t = qj - x;
-                        acc = __fma_rn(t, t, acc);
-                    } else {
-                        acc = __fma_rn(qj, x, acc);
-                    }
-                }
-            acc = group_sum<G>(acc);
-            const int slot = base + b * P + grp;
-            if (sub == 0 && slot < m) {
-                const double d = METRIC == HNSW_L2SQ ? acc : 1.0 - acc;
-                keys[slot] = make_key(static_cast<float>(d), idv[b]);
-            }
-        }
-    }
-}
-
-// Exact fp32-input distance of one element, one lane alone (the re-rank of a
-// low-precision traversal): float4 pieces of the fp32 row, double accumulation.
-template <int METRIC>
-__device__ __forceinline__ float exact_dist(const DevIndex &ix, const float *qrow, uint32_t id) {
-    const float4 *row = reinterpret_cast<const float4 *>(ix.vec) + static_cast<size_t>(id) * ix.stride4;
-    const uint32_t full = ix.dim / 4;
-    double acc = 0.0;
-#pragma unroll 4
-    for (uint32_t c = 0; c < full; ++c) {
-        const float4 x = row[c];
-        const float xs[4] = {x.x, x.y, x.z, x.w};
-#pragma unroll
-        for (int j = 0; j < 4; ++j) {
-            const double qj = static_cast<double>(qrow[4 * c + j]);
-            if (METRIC == HNSW_L2SQ) {
-                const double t = qj - static_cast<double>(xs[j]);
-                acc = __fma_rn(t, t, acc);
-            } else {
-                acc = __fma_rn(qj, static_cast<double>(xs[j]), acc);
-            }
-        }
-    }
-    const float *rowf = reinterpret_cast<const float *>(row);
-    for (uint32_t e = 4 * full; e < ix.dim; ++e) {
-        const double qj = static_cast<double>(qrow[e]);
-        if (METRIC == HNSW_L2SQ) {
-            const double t = qj - static_cast<double>(rowf[e]);
-            acc = __fma_rn(t, t, acc);
-        } else {
-            acc = __fma_rn(qj, static_cast<double>(rowf[e]), acc);
-        }
-    }
-    return static_cast<float>(METRIC == HNSW_L2SQ ? acc : 1.0 - acc);
-}
-
-struct WaveLds {
-    uint64_t *W;       // [wpow2]
-    uint64_t *keys;    // [64] keys of the current batch
-    uint32_t *ids;     // [64] ids of the current batch
-    uint32_t *prevk;   // [64] top-K ids at the previous checkpoint (learned mode)
-    float *hid;        // [2][64] hidden layers of the stop-rule network
-    uint32_t *ht;      // [1 << ht_log2]
-};
-
-__device__ __forceinline__ WaveLds carve(uint8_t *base, const SearchArgs &a) {
-    WaveLds s;
-    s.W = reinterpret_cast<uint64_t *>(base);
-    s.keys = s.W + a.wpow2;
-    s.ids = reinterpret_cast<uint32_t *>(s.keys + 64);
-    s.prevk = s.ids + 64;
-    s.hid = reinterpret_cast<float *>(s.prevk + 64);
-    s.ht = reinterpret_cast<uint32_t *>(s.hid + 128);
-    return s;
-}
-
-// Merges keys[0..m) (lane j owns keys[j]) into the sorted list W of size
-// wsize: W <- the ef smallest of W and the new keys, dropping keys whose
-// (distance, id) is already in W.  Returns the insertion position of the
-// smallest admitted key (INT_MAX when none was admitted).
-// Positions come from wave-wide comparisons: for each admitted key (broadcast
-// with readlane) a ballot over each 64-entry chunk of W counts the smaller
-// entries and detects an equal one; no LDS access depends on another.
-__device__ __forceinline__ int merge_into_w(const WaveLds &s, int m, uint32_t ef, uint32_t &wsize) {
-    const int lane = lane_id();
-    const int ws = static_cast<int>(wsize);
-    const uint64_t thr = wsize < ef ? ~0ull : s.W[ef - 1];
-    const uint64_t a = lane < m ? s.keys[lane] : ~0ull;
-    const bool cand = lane < m && a < thr;
-    const uint64_t cm = __ballot(cand);
-    if (cm == 0) return INT_MAX;
-    int lb = 0;
-    bool dup = false;
-    for (int cb = 0; cb < ws; cb += 64) {
-        const int i = cb + lane;
-        const uint64_t w = i < ws ? (s.W[i] >> 1) : ~0ull;
-        uint64_t mm = cm;
-        while (mm) {
-            const int t = __ffsll(static_cast<unsigned long long>(mm)) - 1;
-            mm &= mm - 1;
-            const uint64_t at = readlane64(a, t) >> 1;
-            const int below = __popcll(__ballot(w < at));
-            const bool eq = __ballot(w == at) != 0;
-            if (lane == t) {
-                lb += below;
-                dup = dup || eq;
-            }
-        }
-    }
-    const bool keep = cand && !dup;
-    const uint64_t km = __ballot(keep);
-    if (km == 0) return INT_MAX;
-    const int cnt = __popcll(km);
-    int r = 0;
-    {
-        uint64_t mm = km;
-        while (mm) {
-            const int t = __ffsll(static_cast<unsigned long long>(mm)) - 1;
-            mm &= mm - 1;
-            const uint64_t at = readlane64(a, t);
-            r += (at < a) || (at == a && t < lane);
-        }
-    }
-    const int lbmin = wave_min_int(keep ? lb : INT_MAX);
-    // Old elements at positions >= lbmin move right by the number of admitted
-    // keys below them; chunks are moved top first so no unread slot is overwritten.
-    for (int cb = (ws - 1) & ~63; cb >= (lbmin & ~63); cb -= 64) {
-        const int i = cb + lane;
-        const bool live = i >= lbmin && i < ws;
-        const uint64_t w = live ? s.W[i] : 0ull;
-        int below = 0;
-        uint64_t mm = km;
-        while (mm) {
-            const int t = __ffsll(static_cast<unsigned long long>(mm)) - 1;
-            mm &= mm - 1;
-            below += readlane64(a, t) < w;
-        }
-        const int np = i + below;
-        wave_sync();
-        if (live && np < static_cast<int>(ef)) s.W[np] = w;
-        wave_sync();
-    }
-    if (keep && lb + r < static_cast<int>(ef)) s.W[lb + r] = a;
-    wave_sync();
-    wsize = min(ef, wsize + static_cast<uint32_t>(cnt));
-    return lbmin;
-}
-
-// ------------------------------------------------ learned stop rule
-//
-// Every `period` layer-0 expansions (at most max_ckpt times) the wave forms 24
-// features of the search state (IEEE float arithmetic only), runs the
-// 24-64-64-2 perceptron (BF16 weights and activations, products exact in
-// float, accumulation in float in input order, lane j = hidden unit j), and
-// (1) at the first checkpoint halves ef j = clamp(floor(0.5 - out1), 0, jmax)
-// times (W keeps its ef nearest), (2) stops the search when out0 > tau.
-
-struct LearnState {
-    uint32_t ckpt, n_prev, n_exp_upper;
-    float d_start, d_best_prev, d_k_prev;
-};
-
-__device__ __forceinline__ float lratio(float a, float b) {
-    const float den = fabsf(b) + 1e-20f;
-    const float r = a / den;
-    return r > 1e6f ? 1e6f : (r < -1e6f ? -1e6f : r);
-}
-
-__device__ __forceinline__ float bf16_round(float f) {
-    uint32_t u = __float_as_uint(f);
-    u = (u + 0x7FFFu + ((u >> 16) & 1u)) & 0xFFFF0000u;
-    return __uint_as_float(u);
-}
-
-__device__ __forceinline__ float bf16_value(uint16_t b) { return __uint_as_float(static_cast<uint32_t>(b) << 16); }
-
-// Returns true when the rule stops the search; may lower ef and wsize.
-__device__ bool learned_checkpoint(const WaveLds &s, const DevMlp &net, LearnState &st, uint32_t n_exp0,
-                                   uint32_t K, int cursor, uint32_t &ef, uint32_t &wsize, float *trace) {
-    const int lane = lane_id();
-    const uint32_t ck = ++st.ckpt;
-    const uint32_t n = wsize;
-    const uint32_t kk = n < K ? n : K;
-    const float d_best = key_dist(s.W[0]), d_k = key_dist(s.W[kk - 1]), d_f = key_dist(s.W[n - 1]);
-    uint32_t pos = n;
-    for (int cb = cursor; cb < static_cast<int>(n); cb += 64) {
-        const int i = cb + lane;
-        const uint64_t um = __ballot(i < static_cast<int>(n) && !(s.W[i] & 1ull));
-        if (um) {
-            pos = static_cast<uint32_t>(cb + __ffsll(static_cast<unsigned long long>(um)) - 1);
-            break;
-        }
-    }
-    uint32_t n_unexp = 0;
-    for (int cb = 0; cb < static_cast<int>(n); cb += 64) {
-        const int i = cb + lane;
-        n_unexp += __popcll(__ballot(i < static_cast<int>(n) && !(s.W[i] & 1ull)));
-    }
-    const float d_next = pos < n ? key_dist(s.W[pos]) : d_f;
-    bool fresh_top = false;
-    uint32_t my_id = 0;
-    if (lane < static_cast<int>(kk)) {
-        my_id = key_id(s.W[lane]);
-        bool seen = false;
-        for (uint32_t j = 0; j < st.n_prev; ++j) seen |= s.prevk[j] == my_id;
-        fresh_top = !seen;
-    }
-    const uint32_t changed = __popcll(__ballot(fresh_top));
-    wave_sync();
-    if (lane < static_cast<int>(kk)) s.prevk[lane] = my_id;
-    st.n_prev = kk;
-    if (ck == 1) {
-        st.d_best_prev = d_best;
-        st.d_k_prev = d_k;
-    }
-    const float fe = static_cast<float>(ef);
-    float f[kMlpIn];
-    f[0] = static_cast<float>(n_exp0) / fe;
-    f[1] = static_cast<float>(n_exp0) / 256.0f;
-    f[2] = static_cast<float>(st.n_exp_upper) / 16.0f;
-    f[3] = static_cast<float>(n) / fe;
-    f[4] = static_cast<float>(pos) / fe;
-    f[5] = static_cast<float>(n_unexp) / fe;
-    f[6] = static_cast<float>(changed) / static_cast<float>(K);
-    f[7] = static_cast<float>(ck) / 32.0f;
-    f[8] = lratio(d_best, st.d_start);
-    f[9] = lratio(d_k, st.d_start);
-    f[10] = lratio(d_f, st.d_start);
-    f[11] = lratio(d_next, st.d_start);
-    f[12] = lratio(d_best, d_k);
-    f[13] = lratio(d_k, d_f);
-    f[14] = lratio(d_next, d_k);
-    f[15] = lratio(st.d_k_prev, d_k);
-    f[16] = lratio(st.d_best_prev, d_best);
-    f[17] = lratio(d_k - d_best, d_f - d_best);
-    f[18] = fe / 512.0f;
-    f[19] = static_cast<float>(K) / 100.0f;
-    f[20] = lratio(d_next - d_k, d_f - d_best);
-    f[21] = d_next < d_k ? 1.0f : 0.0f;
-    f[22] = pos < K ? 1.0f : 0.0f;
-    f[23] = 1.0f;
-    st.d_best_prev = d_best;
-    st.d_k_prev = d_k;
-    // layer 1 (lane = hidden unit)
-    float a = net.b1[lane];
-#pragma unroll
-    for (int i = 0; i < kMlpIn; ++i) a = fmaf(bf16_value(net.w1[lane * kMlpIn + i]), bf16_round(f[i]), a);
-    s.hid[lane] = bf16_round(a > 0.0f ? a : 0.0f);
-    wave_sync();
-    a = net.b2[lane];
-    for (int i = 0; i < kMlpHid; ++i) a = fmaf(bf16_value(net.w2[lane * kMlpHid + i]), s.hid[i], a);
-    s.hid[64 + lane] = bf16_round(a > 0.0f ? a : 0.0f);
-    wave_sync();
-    const int o = lane < kMlpOut ? lane : 0;
-    a = net.b3[o];
-    for (int i = 0; i < kMlpHid; ++i) a = fmaf(bf16_value(net.w3[o * kMlpHid + i]), s.hid[64 + i], a);
-    const float out0 = __shfl(a, 0, 64), out1 = __shfl(a, 1, 64);
-    wave_sync();
-    if (trace && lane == 0) {
-        float *t = trace + static_cast<size_t>(ck - 1) * (kMlpIn + 2);
-        for (int i = 0; i < kMlpIn; ++i) t[i] = f[i];
-        t[kMlpIn] = out0;
-        t[kMlpIn + 1] = out1;
-    }
-    if (ck == 1 && net.jmax > 0) {
-        int j = static_cast<int>(floorf(0.5f - out1));
-        j = j < 0 ? 0 : (j > net.jmax ? net.jmax : j);
-        uint32_t ne = ef >> j;
-        if (ne < K) ne = K;
-        if (ne < ef) {
-            ef = ne;
-            if (wsize > ne) wsize = ne;
-        }
-    }
-    return out0 > net.tau;
-}
-
-// Sorts W[0..n) ascending in LDS (n <= cap, cap a power of two; the tail is
-// padded with the largest key).
-__device__ __forceinline__ void sort_w(uint64_t *W, uint32_t n, uint32_t cap) {
-    const int lane = lane_id();
-    for (uint32_t i = n + lane; i < cap; i += 64) W[i] = ~0ull;
-    wave_sync();
-    for (uint32_t k = 2; k <= cap; k <<= 1)
-        for (uint32_t j = k >> 1; j > 0; j >>= 1) {
-            for (uint32_t t = lane; t < cap / 2; t += 64) {
-                const uint32_t i = 2 * j * (t / j) + (t % j), l = i + j;
-                const bool up = (i & k) == 0;
-                const uint64_t x = W[i], y = W[l];
-                if ((x > y) == up) {
-                    W[i] = y;
-                    W[l] = x;
-                }
-            }
-            wave_sync();
-        }
-}
 
 template <int G, int F, int METRIC, int KIND, bool LEARN>
 __global__ __launch_bounds__(64) void search_kernel(DevIndex ix, SearchArgs a) {
     extern __shared__ __align__(16) uint8_t smem[];
     const uint32_t qi = blockIdx.x;
     if (qi >= a.nq) return;
-    const int lane = lane_id();
-    WaveLds s = carve(smem, a);
-    const RowSource src = rows_of(ix, a, KIND);
-    const float *qrow = a.queries + static_cast<size_t>(qi) * ix.dim;
-
-    QueryRegs<G, F, KIND> Q;
-    load_query<G, F, KIND>(qrow, ix.dim, Q);
-
-    const uint32_t ht_slots = 1u << a.ht_log2;
-    for (uint32_t i = lane; i < ht_slots; i += 64) s.ht[i] = kNoLink;
-
-    uint32_t n_dist = 0, n_exp = 0, n_dist0 = 0, n_exp0 = 0;
-
-    // Entry point (Alg. 5): its distance seeds the descent.
-    if (lane == 0) s.ids[0] = ix.entry;
-    wave_sync();
-    score_ids<G, F, METRIC, KIND>(ix, src, Q, s.ids, 1, s.keys);
-    wave_sync();
-    uint64_t cur = s.keys[0];
-    n_dist += 1;
-
-    // Greedy descent through layers L..1 (SEARCH-LAYER with ef = 1).
-    for (int lc = static_cast<int>(ix.max_level); lc >= 1; --lc) {
-        for (;;) {
-            const uint32_t cid = key_id(cur);
-            const size_t row = static_cast<size_t>(ix.uoff[cid]) + static_cast<size_t>(lc - 1);
-            const uint32_t ld = ix.adjU[row * ix.Mmax + min(lane, static_cast<int>(ix.Mmax) - 1)];
-            const uint32_t e = lane < static_cast<int>(ix.Mmax) ? ld : kNoLink;
-            const bool valid = e != kNoLink;
-            const uint64_t vm = __ballot(valid);
-            const int m = __popcll(vm);
-            if (valid) s.ids[rank_in(vm)] = e;
-            wave_sync();
-            score_ids<G, F, METRIC, KIND>(ix, src, Q, s.ids, m, s.keys);
-            wave_sync();
-            uint64_t best = cur;
-            for (int i = lane; i < m; i += 64) best = s.keys[i] < best ? s.keys[i] : best;
-            best = wave_min_u64(best);
-            n_dist += m;
-            n_exp += 1;
-            wave_sync();
-            if (best == cur) break;
-            cur = best;
-        }
-    }
-
-    // SEARCH-LAYER on layer 0 with ef candidates, starting from the descent's result.
-    uint32_t ef = a.ef;
-    LearnState lst{0u, 0u, n_exp, key_dist(cur), 0.f, 0.f};
-    const uint32_t ht_shift = 32u - a.ht_log2, ht_mask = ht_slots - 1u;
-    if (lane == 0) {
-        s.W[0] = cur;
-        visit(s.ht, ht_shift, ht_mask, key_id(cur));
-    }
-    wave_sync();
-    uint32_t wsize = 1;
-    int cursor = 0;  // every position below it is expanded
-    n_dist0 = 1;
-    for (;;) {
-        int c = -1;
-        uint64_t ck = 0;
-        for (int cb = cursor; cb < static_cast<int>(wsize); cb += 64) {
-            const int i = cb + lane;
-            const uint64_t w = i < static_cast<int>(wsize) ? s.W[i] : 1ull;
-            const uint64_t um = __ballot(!(w & 1ull));
-            if (um) {
-                const int t = __ffsll(static_cast<unsigned long long>(um)) - 1;
-                c = cb + t;
-                ck = readlane64(w, t);
-                break;
-            }
-        }
-        if (c < 0) break;  // every element of W has been expanded
-        if (lane == 0) s.W[c] = ck | 1ull;
-        cursor = c + 1;
-        const uint32_t cid = key_id(ck);
-        const uint32_t ld = ix.adj0[static_cast<size_t>(cid) * ix.Mmax0 + min(lane, static_cast<int>(ix.Mmax0) - 1)];
-        const uint32_t e = lane < static_cast<int>(ix.Mmax0) ? ld : kNoLink;
-        const bool fresh = e != kNoLink && visit(s.ht, ht_shift, ht_mask, e);
-        const uint64_t fm = __ballot(fresh);
-        const int m = __popcll(fm);
-        if (fresh) s.ids[rank_in(fm)] = e;
-        wave_sync();
-        score_ids<G, F, METRIC, KIND>(ix, src, Q, s.ids, m, s.keys);
-        wave_sync();
-        n_dist0 += m;
-        n_exp0 += 1;
-        const int lbmin = merge_into_w(s, m, ef, wsize);
-        if (lbmin < cursor) cursor = lbmin;
-        if (LEARN && n_exp0 % a.mlp.period == 0 && lst.ckpt < a.mlp.max_ckpt &&
-            learned_checkpoint(s, a.mlp, lst, n_exp0, a.k, cursor, ef, wsize,
-                               a.ckpt_trace ? a.ckpt_trace + static_cast<size_t>(qi) * a.mlp.max_ckpt * (kMlpIn + 2)
-                                            : nullptr))
-            break;
-    }
-
-    uint32_t n_rerank = 0;
-    if (KIND != kF32) {
-        // Low-precision traversal: re-score every element of W exactly from the
-        // fp32 vectors and keep the K nearest by that distance.
-        for (uint32_t i = lane; i < wsize; i += 64) {
-            const uint32_t id = key_id(s.W[i]);
-            s.W[i] = make_key(exact_dist<METRIC>(ix, qrow, id), id);
-        }
-        wave_sync();
-        sort_w(s.W, wsize, a.wpow2);
-        n_rerank = wsize;
-    }
-
-    // The K nearest of W (Alg. 5, last line); W is sorted.
-    for (uint32_t i = lane; i < a.k; i += 64) {
-        const size_t o = static_cast<size_t>(qi) * a.k + i;
-        if (i < wsize) {
-            const uint64_t kk = s.W[i];
-            a.ids[o] = static_cast<int32_t>(key_id(kk));
-            a.dists[o] = key_dist(kk);
-        } else {
-            a.ids[o] = -1;
-            a.dists[o] = __int_as_float(0x7f800000);
-        }
-    }
-    if (a.counters && lane == 0) {
-        uint32_t *c4 = a.counters + static_cast<size_t>(qi) * 4;
-        c4[0] = n_dist + n_dist0 + n_rerank;
-        c4[1] = n_exp + n_exp0;
-        c4[2] = n_dist0;
-        c4[3] = n_exp0;
-    }
+    Job job;
+    job.q = a.queries + static_cast<size_t>(qi) * ix.dim;
+    job.k = a.k;
+    job.ef = a.ef;
+    job.ids = a.ids + static_cast<size_t>(qi) * a.k;
+    job.dists = a.dists + static_cast<size_t>(qi) * a.k;
+    job.counters = a.counters ? a.counters + static_cast<size_t>(qi) * 4 : nullptr;
+    job.trace = LEARN && a.ckpt_trace ? a.ckpt_trace + static_cast<size_t>(qi) * a.mlp.max_ckpt * (kMlpIn + 2)
+                                      : nullptr;
+    search_one<G, F, METRIC, KIND, LEARN>(ix, a, job, carve(smem, a));
 }
 
 template <int G, int F, int KIND>

@@ -37,7 +37,7 @@ WORKLOADS = {
     "deep_like": ("graphs/deep_like_1M.bin", 1_000_000, 10_000, 10),
     "uniform4": ("graphs/uniform4_1M.bin", 1_000_000, 10_000, 10),
 }
-EF_SWEEP = [10, 16, 24, 32, 48, 64, 96, 128, 192, 256, 384, 512, 800]
+EF_SWEEP = [10, 16, 24, 32, 40, 48, 56, 64, 80, 96, 112, 128, 160, 192, 256, 320, 384, 512, 640, 800]
 HBM_PEAK_GBS = 8000.0
 METRIC = "QPS at recall@10≥0.95, plain vs learned/low-precision; HBM GB/s"
 
@@ -217,7 +217,7 @@ def main():
     mlp = None
     forms = [f for f in a.forms.split(",") if f]
     if "learned" in forms:
-        mpath = os.path.join(ROOT, "graphs", f"{a.workload}.mlp.npz")
+        mpath = os.path.join(ROOT, "paper_1603_09320_amd", "nets", f"{a.workload}.mlp.npz")
         if os.path.exists(mpath) and hasattr(hnsw, "Mlp"):
             mlp = hnsw.Mlp.load(mpath)
         else:

@@ -163,6 +163,64 @@ class Runner:
         return wall * 1000.0 / steps, float(np.mean([s.elapsed_time(e) for s, e in evs]))
 
 
+# Each server's persistent grid: at ef_max = 512 a wave reserves about 22 KB of
+# LDS (7 waves per CU, 1792 on the chip), so two servers of 768 waves are
+# resident together.
+def serve_bench(hnsw, index, Q, mlp, rates=(50_000, 200_000, 500_000), n_req=20_000, seed=7):
+    """Continuous-batching serving: an open-loop Poisson replay over two live
+    servers, the main index and a 1M x 4 uniform index (built by the oracle,
+    file graphs/uniform4_1M.bin); per request K in {1, 10, 100}, ef uniform in
+    [K, 512], modes mixed over plain, BF16 and (K <= 64, when a net is loaded)
+    learned.  Returns p50/p99 latency (arrival to completion) and completed
+    requests per second for each arrival rate."""
+    import synthdata
+
+    upath = os.path.join(ROOT, WORKLOADS["uniform4"][0])
+    if not os.path.exists(upath):
+        log(f"[serve] missing {upath}: serving measured over the main index alone")
+        g4 = None
+    else:
+        g4 = hnsw.graphfile.read(upath)
+    idx4 = hnsw.Index(g4, synthdata.base("uniform4", g4["n"])) if g4 else None
+    Q4 = synthdata.queries("uniform4", 10_000) if g4 else None
+    for ix in (index, idx4):
+        if ix is not None:
+            ix.add_lowp(hnsw.MODE_BF16)
+    out = []
+    rng = np.random.default_rng(seed)
+    for rate in rates:
+        servers = [hnsw.Server(index, mlp=mlp, slots=4096, waves=768, ef_max=512, k_max=100, budget_s=120.0)]
+        if idx4 is not None:
+            servers.append(hnsw.Server(idx4, mlp=None, slots=4096, waves=768, ef_max=512, k_max=100, budget_s=120.0))
+        try:
+            arrival = np.cumsum(rng.exponential(1.0 / rate, n_req))
+            server_of = rng.integers(0, len(servers), n_req).astype(np.uint32)
+            qidx = rng.integers(0, len(Q), n_req).astype(np.uint32)
+            k = rng.choice([1, 10, 100], n_req).astype(np.uint32)
+            ef = np.array([rng.integers(kk, 513) for kk in k], dtype=np.uint32)
+            modes = [0, 1, 3] if mlp is not None else [0, 1]
+            mode = rng.choice(modes, n_req).astype(np.int32)
+            mode[(mode == 3) & ((k > 64) | (server_of == 1))] = 0
+            qs = [Q] + ([Q4] if idx4 is not None else [])
+            r = hnsw.replay(servers, qs, arrival, server_of, qidx, k, ef, mode, keep_results=False,
+                            timeout_s=60.0)
+        finally:
+            for sv in servers:
+                sv.stop()
+        lat = (r["t_done"] - arrival) * 1e3
+        span = float(r["t_done"].max() - arrival[0])
+        row = {"offered_rps": rate, "requests": n_req, "p50_ms": round(float(np.percentile(lat, 50)), 3),
+               "p99_ms": round(float(np.percentile(lat, 99)), 3), "completed_rps": round(n_req / span, 1)}
+        log(f"[serve] {row}")
+        out.append(row)
+    if idx4 is not None:
+        idx4.close()
+    return {"indices": ["main index", "uniform4 1M x 4"] if idx4 is not None else ["main index"],
+            "requests": "K in {1,10,100}, ef uniform in [K,512], modes plain/bf16" +
+                        ("/learned (K<=64, main index)" if mlp is not None else ""),
+            "rates": out}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -174,6 +232,7 @@ def main():
                     help="comma list of plain,bf16,fp8,learned (learned needs a trained net file)")
     ap.add_argument("--target-recall", type=float, default=0.95)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-serve", action="store_true", help="skip the serving-loop measurement")
     ap.add_argument("--copy-probe-bytes", type=int, default=0,
                     help="also run a plain device-to-device copy of this size (counter calibration)")
     a = ap.parse_args()
@@ -260,6 +319,10 @@ def main():
         log(f"[bench] copy probe: {a.copy_probe_bytes} bytes read and written, twice")
         del src, dst
 
+    serving = None
+    if not a.no_serve:
+        serving = serve_bench(hnsw, index, Q, mlp)
+
     head = results.get("plain") or next(iter(results.values()))
     cpu = None
     if not a.no_cpu_baseline:
@@ -294,6 +357,7 @@ def main():
         "bruteforce": {"ms": round(bf_ms, 3), "queries": nq,
                        "tflops": round(2.0 * nq * graph["n"] * graph["dim"] / (bf_ms / 1000.0) / 1e12, 2)},
         "cpu_baseline": cpu,
+        "serving": serving,
     }
     print(json.dumps(out), flush=True)
     index.close()

@@ -5,12 +5,57 @@
 #include <stdlib.h>
 #include <string.h>
 
+#include <mutex>
+#include <utility>
 #include <vector>
 
 #include "internal.h"
 
 
 namespace hnsw {
+
+namespace {
+std::mutex g_free_mu;
+int g_servers = 0;                            // resident server kernels
+std::vector<std::pair<void *, bool>> g_held;  // (pointer, host memory) held while servers run
+}  // namespace
+
+void device_free(void *p) {
+    if (!p) return;
+    std::lock_guard<std::mutex> lock(g_free_mu);
+    if (g_servers > 0) {
+        g_held.emplace_back(p, false);
+        return;
+    }
+    (void)hipFree(p);
+}
+
+void host_free(void *p) {
+    if (!p) return;
+    std::lock_guard<std::mutex> lock(g_free_mu);
+    if (g_servers > 0) {
+        g_held.emplace_back(p, true);
+        return;
+    }
+    (void)hipHostFree(p);
+}
+
+void server_started() {
+    std::lock_guard<std::mutex> lock(g_free_mu);
+    ++g_servers;
+}
+
+void server_stopped() {
+    std::vector<std::pair<void *, bool>> release;
+    {
+        std::lock_guard<std::mutex> lock(g_free_mu);
+        if (--g_servers == 0) release.swap(g_held);
+    }
+    for (const auto &h : release) {
+        if (h.second) (void)hipHostFree(h.first);
+        else (void)hipFree(h.first);
+    }
+}
 
 bool device_count_ok() {
     int n = 0;
@@ -107,7 +152,7 @@ struct Allocator {
         return p;
     }
     void release() {
-        for (void *p : got) (void)hipFree(p);
+        for (void *p : got) hnsw::device_free(p);
         got.clear();
     }
 };
@@ -194,7 +239,7 @@ hnsw_status hnsw_index_upload(const hnsw_graph_desc *g, void *stream, hnsw_index
 
 void hnsw_index_free(hnsw_index *index) {
     if (!index) return;
-    for (void *p : index->allocations) (void)hipFree(p);
+    for (void *p : index->allocations) hnsw::device_free(p);
     delete index;
 }
 
@@ -296,7 +341,7 @@ hnsw_status hnsw_index_add_lowp(hnsw_index *index, int kind, void *stream) {
     ok = ok && hipStreamSynchronize(st) == hipSuccess;
     if (!ok) {
         (void)hipGetLastError();
-        (void)hipFree(p);
+        hnsw::device_free(p);
         return HNSW_ERR_DEVICE;
     }
     if (kind == HNSW_MODE_BF16) {
@@ -392,7 +437,7 @@ hnsw_status hnsw_mlp_create(const float *params, float tau, int jmax, uint32_t p
     if (hipMemcpy(mem, w.data(), wbytes, hipMemcpyHostToDevice) != hipSuccess ||
         hipMemcpy(static_cast<uint8_t *>(mem) + wbytes, b.data(), b.size() * 4, hipMemcpyHostToDevice) != hipSuccess) {
         (void)hipGetLastError();
-        (void)hipFree(mem);
+        hnsw::device_free(mem);
         return HNSW_ERR_DEVICE;
     }
     hnsw_mlp *m = new hnsw_mlp();
@@ -406,7 +451,7 @@ hnsw_status hnsw_mlp_create(const float *params, float tau, int jmax, uint32_t p
 
 void hnsw_mlp_free(hnsw_mlp *mlp) {
     if (!mlp) return;
-    (void)hipFree(mlp->mem);
+    hnsw::device_free(mlp->mem);
     delete mlp;
 }
 

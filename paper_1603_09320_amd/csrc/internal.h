@@ -107,4 +107,15 @@ namespace hnsw {
 bool device_count_ok();
 bool is_device_ptr(const void *p);
 uint64_t mem_cap();
+
+// Frees while persistent server kernels are resident.  hipFree and
+// hipHostFree wait for the whole device to go idle, which a resident server
+// kernel does only once it is stopped: a free issued then (for example by a
+// garbage-collected index) would block its thread until the server's budget
+// ran out.  Frees requested while any server runs are therefore held and
+// released when the last server has stopped.
+void device_free(void *p);
+void host_free(void *p);
+void server_started();
+void server_stopped();
 }  // namespace hnsw

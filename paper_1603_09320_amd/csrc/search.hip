@@ -7,7 +7,7 @@ namespace hnsw {
 namespace {
 
 template <int G, int F, int METRIC, int KIND, bool LEARN>
-__global__ __launch_bounds__(64) void search_kernel(DevIndex ix, SearchArgs a) {
+__device__ __forceinline__ void search_query(const DevIndex &ix, const SearchArgs &a) {
     extern __shared__ __align__(16) uint8_t smem[];
     const uint32_t qi = blockIdx.x;
     if (qi >= a.nq) return;
@@ -23,23 +23,37 @@ __global__ __launch_bounds__(64) void search_kernel(DevIndex ix, SearchArgs a) {
     search_one<G, F, METRIC, KIND, LEARN>(ix, a, job, carve(smem, a));
 }
 
+// Waves per SIMD the register allocation is held to: six for the fp32 and
+// BF16 stores (80 registers, no spills), five for FP8 (its decode needs more).
+template <int G, int F, int METRIC, int KIND>
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(KIND == kFP8 ? 5 : 6))) void search_kernel(
+    DevIndex ix, SearchArgs a) {
+    search_query<G, F, METRIC, KIND, false>(ix, a);
+}
+
+// The learned stop rule raises register use; forcing five waves spills
+// inside the loop and is slower than four without spills.
+template <int G, int F, int METRIC>
+__global__ __launch_bounds__(64) void search_kernel_learned(DevIndex ix, SearchArgs a) {
+    search_query<G, F, METRIC, kF32, true>(ix, a);
+}
+
 template <int G, int F, int KIND>
 hipError_t launch_gfk(const DevIndex &ix, const SearchArgs &a, hipStream_t stream) {
     const size_t lds = search_lds_bytes(a);
     if constexpr (KIND == kF32) {
         if (a.mode == HNSW_MODE_LEARNED) {
             if (ix.metric == HNSW_IP)
-                hipLaunchKernelGGL((search_kernel<G, F, HNSW_IP, KIND, true>), dim3(a.nq), dim3(64), lds, stream, ix, a);
+                hipLaunchKernelGGL((search_kernel_learned<G, F, HNSW_IP>), dim3(a.nq), dim3(64), lds, stream, ix, a);
             else
-                hipLaunchKernelGGL((search_kernel<G, F, HNSW_L2SQ, KIND, true>), dim3(a.nq), dim3(64), lds, stream, ix,
-                                   a);
+                hipLaunchKernelGGL((search_kernel_learned<G, F, HNSW_L2SQ>), dim3(a.nq), dim3(64), lds, stream, ix, a);
             return hipGetLastError();
         }
     }
     if (ix.metric == HNSW_IP)
-        hipLaunchKernelGGL((search_kernel<G, F, HNSW_IP, KIND, false>), dim3(a.nq), dim3(64), lds, stream, ix, a);
+        hipLaunchKernelGGL((search_kernel<G, F, HNSW_IP, KIND>), dim3(a.nq), dim3(64), lds, stream, ix, a);
     else
-        hipLaunchKernelGGL((search_kernel<G, F, HNSW_L2SQ, KIND, false>), dim3(a.nq), dim3(64), lds, stream, ix, a);
+        hipLaunchKernelGGL((search_kernel<G, F, HNSW_L2SQ, KIND>), dim3(a.nq), dim3(64), lds, stream, ix, a);
     return hipGetLastError();
 }
 

@@ -92,13 +92,18 @@ __device__ __forceinline__ int rank_in(uint64_t mask) {
                                      __builtin_amdgcn_mbcnt_lo(static_cast<uint32_t>(mask), 0));
 }
 
+// Wave-wide minima.  Every lane ends with the same value; it is returned
+// through a scalar register so the compiler knows it is wave-uniform (loop
+// exits that depend on it then stay uniform control flow).
 __device__ __forceinline__ uint64_t wave_min_u64(uint64_t v) {
 #pragma unroll
     for (int o = 32; o > 0; o >>= 1) {
         const uint64_t w = __shfl_xor(v, o, 64);
         v = w < v ? w : v;
     }
-    return v;
+    const uint32_t lo = __builtin_amdgcn_readfirstlane(static_cast<uint32_t>(v));
+    const uint32_t hi = __builtin_amdgcn_readfirstlane(static_cast<uint32_t>(v >> 32));
+    return (static_cast<uint64_t>(hi) << 32) | lo;
 }
 
 __device__ __forceinline__ int wave_min_int(int v) {
@@ -107,7 +112,7 @@ __device__ __forceinline__ int wave_min_int(int v) {
         const int w = __shfl_xor(v, o, 64);
         v = w < v ? w : v;
     }
-    return v;
+    return __builtin_amdgcn_readfirstlane(v);
 }
 
 // Test-and-set of `id` in the visited table; true when the id was not seen.
@@ -123,13 +128,15 @@ __device__ __forceinline__ bool visit(uint32_t *ht, uint32_t shift, uint32_t mas
     return true;  // run full: forget, score again
 }
 
-// One DPP move of both halves of a double (gfx9 DPP controls, full rows/banks).
+// One DPP move of both halves of a double (gfx9 DPP controls, full rows and
+// banks).  Every lane has a source lane under the controls used here, so the
+// bound-control form is taken: it needs no "old" value to be materialised.
 template <int CTRL>
 __device__ __forceinline__ double dpp_f64(double v) {
     const uint64_t u = static_cast<uint64_t>(__double_as_longlong(v));
-    const uint32_t lo = static_cast<uint32_t>(__builtin_amdgcn_update_dpp(0, static_cast<int>(u), CTRL, 0xF, 0xF, false));
+    const uint32_t lo = static_cast<uint32_t>(__builtin_amdgcn_update_dpp(0, static_cast<int>(u), CTRL, 0xF, 0xF, true));
     const uint32_t hi =
-        static_cast<uint32_t>(__builtin_amdgcn_update_dpp(0, static_cast<int>(u >> 32), CTRL, 0xF, 0xF, false));
+        static_cast<uint32_t>(__builtin_amdgcn_update_dpp(0, static_cast<int>(u >> 32), CTRL, 0xF, 0xF, true));
     return __longlong_as_double(static_cast<long long>((static_cast<uint64_t>(hi) << 32) | lo));
 }
 
@@ -168,11 +175,15 @@ struct Store<kFP8> {
     using QT = float;
 };
 
-// E4M3 (OCP) code -> float: exponent bias 7, 3 mantissa bits, subnormals m * 2^-9.
-__device__ __forceinline__ float e4m3_to_float(uint32_t b) {
-    const uint32_t e = (b >> 3) & 15u, m = b & 7u;
-    const float mag = e ? __uint_as_float(((e + 120u) << 23) | (m << 20)) : static_cast<float>(m) * 0x1.0p-9f;
-    return (b & 0x80u) ? -mag : mag;
+// Byte k of w as an OCP FP8-E4M3 code, decoded by the hardware conversion
+// (exact: every code is a float; the store holds no NaN codes).
+__device__ __forceinline__ float fp8_byte(uint32_t w, int k) {
+    switch (k & 3) {
+        case 0: return __builtin_amdgcn_cvt_f32_fp8(static_cast<int>(w), 0);
+        case 1: return __builtin_amdgcn_cvt_f32_fp8(static_cast<int>(w), 1);
+        case 2: return __builtin_amdgcn_cvt_f32_fp8(static_cast<int>(w), 2);
+        default: return __builtin_amdgcn_cvt_f32_fp8(static_cast<int>(w), 3);
+    }
 }
 
 // Value j of a 16-byte piece.
@@ -181,7 +192,7 @@ __device__ __forceinline__ float piece_value(const uint4 &p, int j) {
     const uint32_t w = j < Store<KIND>::VPP / 4 ? p.x : (j < Store<KIND>::VPP / 2 ? p.y : (j < 3 * Store<KIND>::VPP / 4 ? p.z : p.w));
     if (KIND == kF32) return __uint_as_float(w);
     if (KIND == kBF16) return __uint_as_float((j & 1) ? (w & 0xFFFF0000u) : (w << 16));
-    return e4m3_to_float((w >> (8 * (j & 3))) & 0xFFu);
+    return fp8_byte(w, j);
 }
 
 template <int G, int F, int KIND>
@@ -228,12 +239,17 @@ template <int G, int F, int METRIC, int KIND>
 __device__ __forceinline__ void score_ids(const DevIndex &ix, const RowSource &src, const QueryRegs<G, F, KIND> &Q,
                                           const uint32_t *ids, int m, uint64_t *keys) {
     constexpr int P = 64 / G;
-    constexpr int B = (32 / P) < 1 ? 1 : ((32 / P) > 4 ? 4 : (32 / P));
+    // rows in flight per lane group: up to 4, fewer when each lane holds
+    // more than two pieces of a row (register budget)
+    constexpr int BP = (32 / P) < (8 / F) ? (32 / P) : (8 / F);
+    constexpr int B = BP < 1 ? 1 : (BP > 4 ? 4 : BP);
     constexpr int V = Store<KIND>::VPP;
     const int lane = lane_id();
     const int grp = lane / G, sub = lane % G;
     const size_t zero_row = static_cast<size_t>(ix.n) * src.stride;
     for (int base = 0; base < m; base += P * B) {
+        // sub-batches holding at least one id (wave-uniform: m and base are)
+        const int nb = min(B, (m - base + P - 1) / P);
         uint32_t idv[B];
 #pragma unroll
         for (int b = 0; b < B; ++b) idv[b] = ids[(base + b * P + grp) & 63];
@@ -243,6 +259,7 @@ __device__ __forceinline__ void score_ids(const DevIndex &ix, const RowSource &s
         float sc[B];
 #pragma unroll
         for (int b = 0; b < B; ++b) {
+            if (b >= nb) break;
             const size_t row = static_cast<size_t>(idv[b]) * src.stride;
 #pragma unroll
             for (int f = 0; f < F; ++f) {
@@ -255,6 +272,7 @@ __device__ __forceinline__ void score_ids(const DevIndex &ix, const RowSource &s
         }
 #pragma unroll
         for (int b = 0; b < B; ++b) {
+            if (b >= nb) break;
             double acc = 0.0;
             const double s = KIND == kFP8 ? static_cast<double>(sc[b]) : 1.0;
 #pragma unroll
@@ -279,41 +297,6 @@ __device__ __forceinline__ void score_ids(const DevIndex &ix, const RowSource &s
             }
         }
     }
-}
-
-// Exact fp32-input distance of one element, one lane alone (the re-rank of a
-// low-precision traversal): float4 pieces of the fp32 row, double accumulation.
-template <int METRIC>
-__device__ __forceinline__ float exact_dist(const DevIndex &ix, const float *qrow, uint32_t id) {
-    const float4 *row = reinterpret_cast<const float4 *>(ix.vec) + static_cast<size_t>(id) * ix.stride4;
-    const uint32_t full = ix.dim / 4;
-    double acc = 0.0;
-#pragma unroll 4
-    for (uint32_t c = 0; c < full; ++c) {
-        const float4 x = row[c];
-        const float xs[4] = {x.x, x.y, x.z, x.w};
-#pragma unroll
-        for (int j = 0; j < 4; ++j) {
-            const double qj = static_cast<double>(qrow[4 * c + j]);
-            if (METRIC == HNSW_L2SQ) {
-                const double t = qj - static_cast<double>(xs[j]);
-                acc = __fma_rn(t, t, acc);
-            } else {
-                acc = __fma_rn(qj, static_cast<double>(xs[j]), acc);
-            }
-        }
-    }
-    const float *rowf = reinterpret_cast<const float *>(row);
-    for (uint32_t e = 4 * full; e < ix.dim; ++e) {
-        const double qj = static_cast<double>(qrow[e]);
-        if (METRIC == HNSW_L2SQ) {
-            const double t = qj - static_cast<double>(rowf[e]);
-            acc = __fma_rn(t, t, acc);
-        } else {
-            acc = __fma_rn(qj, static_cast<double>(rowf[e]), acc);
-        }
-    }
-    return static_cast<float>(METRIC == HNSW_L2SQ ? acc : 1.0 - acc);
 }
 
 struct WaveLds {
@@ -428,6 +411,11 @@ __device__ __forceinline__ float lratio(float a, float b) {
     return r > 1e6f ? 1e6f : (r < -1e6f ? -1e6f : r);
 }
 
+// A wave-uniform float held in a scalar register.
+__device__ __forceinline__ float uniform_f(float v) {
+    return __uint_as_float(__builtin_amdgcn_readfirstlane(__float_as_uint(v)));
+}
+
 __device__ __forceinline__ float bf16_round(float f) {
     uint32_t u = __float_as_uint(f);
     u = (u + 0x7FFFu + ((u >> 16) & 1u)) & 0xFFFF0000u;
@@ -443,7 +431,8 @@ __device__ bool learned_checkpoint(const WaveLds &s, const DevMlp &net, LearnSta
     const uint32_t ck = ++st.ckpt;
     const uint32_t n = wsize;
     const uint32_t kk = n < K ? n : K;
-    const float d_best = key_dist(s.W[0]), d_k = key_dist(s.W[kk - 1]), d_f = key_dist(s.W[n - 1]);
+    const float d_best = uniform_f(key_dist(s.W[0])), d_k = uniform_f(key_dist(s.W[kk - 1])),
+                d_f = uniform_f(key_dist(s.W[n - 1]));
     uint32_t pos = n;
     for (int cb = cursor; cb < static_cast<int>(n); cb += 64) {
         const int i = cb + lane;
@@ -458,7 +447,7 @@ __device__ bool learned_checkpoint(const WaveLds &s, const DevMlp &net, LearnSta
         const int i = cb + lane;
         n_unexp += __popcll(__ballot(i < static_cast<int>(n) && !(s.W[i] & 1ull)));
     }
-    const float d_next = pos < n ? key_dist(s.W[pos]) : d_f;
+    const float d_next = pos < n ? uniform_f(key_dist(s.W[pos])) : d_f;
     bool fresh_top = false;
     uint32_t my_id = 0;
     if (lane < static_cast<int>(kk)) {
@@ -475,52 +464,62 @@ __device__ bool learned_checkpoint(const WaveLds &s, const DevMlp &net, LearnSta
         st.d_best_prev = d_best;
         st.d_k_prev = d_k;
     }
+    // features go to LDS as they are formed (hid[64..87]: layer 2 writes
+    // there only after layer 1 has read them), so few are live at once
     const float fe = static_cast<float>(ef);
-    float f[kMlpIn];
-    f[0] = static_cast<float>(n_exp0) / fe;
-    f[1] = static_cast<float>(n_exp0) / 256.0f;
-    f[2] = static_cast<float>(st.n_exp_upper) / 16.0f;
-    f[3] = static_cast<float>(n) / fe;
-    f[4] = static_cast<float>(pos) / fe;
-    f[5] = static_cast<float>(n_unexp) / fe;
-    f[6] = static_cast<float>(changed) / static_cast<float>(K);
-    f[7] = static_cast<float>(ck) / 32.0f;
-    f[8] = lratio(d_best, st.d_start);
-    f[9] = lratio(d_k, st.d_start);
-    f[10] = lratio(d_f, st.d_start);
-    f[11] = lratio(d_next, st.d_start);
-    f[12] = lratio(d_best, d_k);
-    f[13] = lratio(d_k, d_f);
-    f[14] = lratio(d_next, d_k);
-    f[15] = lratio(st.d_k_prev, d_k);
-    f[16] = lratio(st.d_best_prev, d_best);
-    f[17] = lratio(d_k - d_best, d_f - d_best);
-    f[18] = fe / 512.0f;
-    f[19] = static_cast<float>(K) / 100.0f;
-    f[20] = lratio(d_next - d_k, d_f - d_best);
-    f[21] = d_next < d_k ? 1.0f : 0.0f;
-    f[22] = pos < K ? 1.0f : 0.0f;
-    f[23] = 1.0f;
+    float *fs = s.hid + 64;
+    if (lane == 0) {
+        fs[0] = static_cast<float>(n_exp0) / fe;
+        fs[1] = static_cast<float>(n_exp0) / 256.0f;
+        fs[2] = static_cast<float>(st.n_exp_upper) / 16.0f;
+        fs[3] = static_cast<float>(n) / fe;
+        fs[4] = static_cast<float>(pos) / fe;
+        fs[5] = static_cast<float>(n_unexp) / fe;
+        fs[6] = static_cast<float>(changed) / static_cast<float>(K);
+        fs[7] = static_cast<float>(ck) / 32.0f;
+        fs[8] = lratio(d_best, st.d_start);
+        fs[9] = lratio(d_k, st.d_start);
+        fs[10] = lratio(d_f, st.d_start);
+        fs[11] = lratio(d_next, st.d_start);
+        fs[12] = lratio(d_best, d_k);
+        fs[13] = lratio(d_k, d_f);
+        fs[14] = lratio(d_next, d_k);
+        fs[15] = lratio(st.d_k_prev, d_k);
+        fs[16] = lratio(st.d_best_prev, d_best);
+        fs[17] = lratio(d_k - d_best, d_f - d_best);
+        fs[18] = fe / 512.0f;
+        fs[19] = static_cast<float>(K) / 100.0f;
+        fs[20] = lratio(d_next - d_k, d_f - d_best);
+        fs[21] = d_next < d_k ? 1.0f : 0.0f;
+        fs[22] = pos < K ? 1.0f : 0.0f;
+        fs[23] = 1.0f;
+    }
     st.d_best_prev = d_best;
     st.d_k_prev = d_k;
-    // layer 1 (lane = hidden unit)
+    wave_sync();
+    if (trace && lane < kMlpIn) trace[static_cast<size_t>(ck - 1) * (kMlpIn + 2) + lane] = fs[lane];
+    // layer 1 (lane = hidden unit), inputs in order
     float a = net.b1[lane];
-#pragma unroll
-    for (int i = 0; i < kMlpIn; ++i) a = fmaf(bf16_value(net.w1[lane * kMlpIn + i]), bf16_round(f[i]), a);
-    s.hid[lane] = bf16_round(a > 0.0f ? a : 0.0f);
+#pragma unroll 4
+    for (int i = 0; i < kMlpIn; ++i) a = fmaf(bf16_value(net.w1[lane * kMlpIn + i]), bf16_round(fs[i]), a);
+    const float h1 = bf16_round(a > 0.0f ? a : 0.0f);
+    wave_sync();
+    s.hid[lane] = h1;
     wave_sync();
     a = net.b2[lane];
+#pragma unroll 4
     for (int i = 0; i < kMlpHid; ++i) a = fmaf(bf16_value(net.w2[lane * kMlpHid + i]), s.hid[i], a);
     s.hid[64 + lane] = bf16_round(a > 0.0f ? a : 0.0f);
     wave_sync();
     const int o = lane < kMlpOut ? lane : 0;
     a = net.b3[o];
+#pragma unroll 4
     for (int i = 0; i < kMlpHid; ++i) a = fmaf(bf16_value(net.w3[o * kMlpHid + i]), s.hid[64 + i], a);
-    const float out0 = __shfl(a, 0, 64), out1 = __shfl(a, 1, 64);
+    const float out0 = __uint_as_float(__builtin_amdgcn_readlane(__float_as_uint(a), 0));
+    const float out1 = __uint_as_float(__builtin_amdgcn_readlane(__float_as_uint(a), 1));
     wave_sync();
     if (trace && lane == 0) {
         float *t = trace + static_cast<size_t>(ck - 1) * (kMlpIn + 2);
-        for (int i = 0; i < kMlpIn; ++i) t[i] = f[i];
         t[kMlpIn] = out0;
         t[kMlpIn + 1] = out1;
     }
@@ -609,7 +608,7 @@ __device__ void search_one(const DevIndex &ix, const SearchArgs &a, const Job &j
 
     // SEARCH-LAYER on layer 0 with ef candidates, starting from the descent's result.
     uint32_t ef = job.ef;
-    LearnState lst{0u, 0u, n_exp, key_dist(cur), 0.f, 0.f};
+    LearnState lst{0u, 0u, n_exp, uniform_f(key_dist(cur)), 0.f, 0.f};
     const uint32_t ht_shift = 32u - a.ht_log2, ht_mask = ht_slots - 1u;
     if (lane == 0) {
         s.W[0] = cur;
@@ -658,12 +657,22 @@ __device__ void search_one(const DevIndex &ix, const SearchArgs &a, const Job &j
     uint32_t n_rerank = 0;
     if (KIND != kF32) {
         // Low-precision traversal: re-score every element of W exactly from the
-        // fp32 vectors and keep the K nearest by that distance.
-        for (uint32_t i = lane; i < wsize; i += 64) {
-            const uint32_t id = key_id(s.W[i]);
-            s.W[i] = make_key(exact_dist<METRIC>(ix, qrow, id), id);
+        // fp32 vectors (the same grouped gather and arithmetic as the plain
+        // path, pieces of 4 floats, so each lane holds VPP/4 times as many)
+        // and keep the K nearest by that distance.
+        constexpr int FX = F * (Store<KIND>::VPP / 4);
+        QueryRegs<G, FX, kF32> QX;
+        load_query<G, FX, kF32>(qrow, ix.dim, QX);
+        const RowSource sx = rows_of(ix, a, kF32);
+        for (uint32_t c0 = 0; c0 < wsize; c0 += 64) {
+            const int cnt = static_cast<int>(min(64u, wsize - c0));
+            if (lane < cnt) s.ids[lane] = key_id(s.W[c0 + lane]);
+            wave_sync();
+            score_ids<G, FX, METRIC, kF32>(ix, sx, QX, s.ids, cnt, s.keys);
+            wave_sync();
+            if (lane < cnt) s.W[c0 + lane] = s.keys[lane];
+            wave_sync();
         }
-        wave_sync();
         sort_w(s.W, wsize, a.wpow2);
         n_rerank = wsize;
     }

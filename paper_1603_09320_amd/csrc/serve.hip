@@ -196,14 +196,16 @@ T *dev_view(T *host) {
     return static_cast<T *>(d);
 }
 
+// Releases a server whose kernel is not (or no longer) resident; frees go
+// through the holding path, since other servers may still be running.
 void free_server(hnsw_server *s) {
-    if (s->ring) (void)hipHostFree(s->ring);
-    if (s->qbuf) (void)hipHostFree(s->qbuf);
-    if (s->oids) (void)hipHostFree(s->oids);
-    if (s->od) (void)hipHostFree(s->od);
-    if (s->cnt) (void)hipHostFree(s->cnt);
-    if (s->stop) (void)hipHostFree(s->stop);
-    if (s->next_ticket_dev) (void)hipFree(s->next_ticket_dev);
+    hnsw::host_free(s->ring);
+    hnsw::host_free(s->qbuf);
+    hnsw::host_free(s->oids);
+    hnsw::host_free(s->od);
+    hnsw::host_free(s->cnt);
+    hnsw::host_free(s->stop);
+    hnsw::device_free(s->next_ticket_dev);
     if (s->stream) (void)hipStreamDestroy(s->stream);
     delete s;
 }
@@ -285,6 +287,7 @@ hnsw_status hnsw_server_start(const hnsw_index *index, const hnsw_mlp *mlp, uint
         free_server(s);
         return HNSW_ERR_DEVICE;
     }
+    hnsw::server_started();
     *out = s;
     return HNSW_OK;
 }
@@ -343,6 +346,7 @@ hnsw_status hnsw_server_stop(hnsw_server *srv) {
         std::this_thread::sleep_for(std::chrono::microseconds(200));
     }
     free_server(srv);
+    hnsw::server_stopped();
     return HNSW_OK;
 }
 

@@ -63,9 +63,10 @@ def train(feats, labels, epochs=6, batch=4096, lr=2e-3, lam=0.25, seed=0, log=pr
     return P.cpu().numpy()
 
 
-def calibrate(workload, params, taus, jmaxes=(0, 1, 2), K=10, ef=512, nq=2000, target=0.95, log=print):
-    """Recall and time of the learned search for each (tau, jmax) on held-out
-    queries; the fastest setting whose mean recall@K reaches the target wins."""
+def calibrate(workload, params, taus, jmaxes=(0, 1, 2), K=10, efs=(512,), nq=2000, target=0.95, log=print):
+    """Recall and time of the learned search for each (ef, tau, jmax) on
+    held-out queries; the fastest setting whose mean recall@K reaches the
+    target wins."""
     import torch
 
     import paper_1603_09320_amd as hnsw
@@ -82,25 +83,24 @@ def calibrate(workload, params, taus, jmaxes=(0, 1, 2), K=10, ef=512, nq=2000, t
     _, gt = hnsw.bruteforce(idx, q, K)
     gt = gt.cpu().numpy()
     rows = []
-    for jmax in jmaxes:
-        for tau in taus:
-            mlp = hnsw.Mlp(params, tau=tau, jmax=jmax)
-            ids, _ = idx.search(q, K, ef, mode=hnsw.MODE_LEARNED, mlp=mlp)
-            torch.cuda.synchronize()
-            t0 = time.perf_counter()
-            for _ in range(3):
-                idx.search(q, K, ef, mode=hnsw.MODE_LEARNED, mlp=mlp)
-            torch.cuda.synchronize()
-            ms = (time.perf_counter() - t0) * 1000 / 3
-            idn = ids.cpu().numpy()
-            x = X[np.clip(idn, 0, None)].astype(np.float64)
-            if g["metric"] == 1:
-                d = 1.0 - (x * Q[:, None, :].astype(np.float64)).sum(-1)
-            else:
-                d = ((x - Q[:, None, :].astype(np.float64)) ** 2).sum(-1)
-            rec = float(((d <= gt[:, K - 1:K]).sum(1) / K).mean())
-            rows.append((tau, jmax, rec, ms))
-            log(f"[calibrate] tau={tau:+.3f} jmax={jmax} recall={rec:.4f} ms={ms:.3f}")
+    for ef, jmax, tau in [(e, j, t) for e in efs for j in jmaxes for t in taus]:
+        mlp = hnsw.Mlp(params, tau=tau, jmax=jmax)
+        ids, _ = idx.search(q, K, ef, mode=hnsw.MODE_LEARNED, mlp=mlp)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(3):
+            idx.search(q, K, ef, mode=hnsw.MODE_LEARNED, mlp=mlp)
+        torch.cuda.synchronize()
+        ms = (time.perf_counter() - t0) * 1000 / 3
+        idn = ids.cpu().numpy()
+        x = X[np.clip(idn, 0, None)].astype(np.float64)
+        if g["metric"] == 1:
+            d = 1.0 - (x * Q[:, None, :].astype(np.float64)).sum(-1)
+        else:
+            d = ((x - Q[:, None, :].astype(np.float64)) ** 2).sum(-1)
+        rec = float(((d <= gt[:, K - 1:K]).sum(1) / K).mean())
+        rows.append((tau, jmax, rec, ms, ef))
+        log(f"[calibrate] ef={ef} tau={tau:+.3f} jmax={jmax} recall={rec:.4f} ms={ms:.3f}")
     ok = [r for r in rows if r[2] >= target]
     best = min(ok, key=lambda r: r[3]) if ok else max(rows, key=lambda r: r[2])
     return best, rows
@@ -116,7 +116,7 @@ def main():
     c = sub.add_parser("calibrate")
     c.add_argument("--workload", required=True)
     c.add_argument("--net", required=True)
-    c.add_argument("--ef", type=int, default=512)
+    c.add_argument("--ef", default="512", help="comma list of ef values to try")
     c.add_argument("--jmax", default="0,1,2", help="comma list of ef-halving limits to try")
     c.add_argument("--target", type=float, default=0.95)
     a = ap.parse_args()
@@ -131,10 +131,12 @@ def main():
         z = np.load(a.net)
         taus = [4.0, 3.0, 2.5, 2.0, 1.5, 1.0, 0.5, 0.0]
         jmaxes = [int(j) for j in a.jmax.split(",")]
-        best, rows = calibrate(a.workload, z["params"], taus, jmaxes, ef=a.ef, target=a.target)
+        efs = [int(e) for e in a.ef.split(",")]
+        best, rows = calibrate(a.workload, z["params"], taus, jmaxes, efs=efs, target=a.target)
         np.savez(a.net, params=z["params"], tau=best[0], jmax=best[1], period=int(z["period"]),
-                 max_ckpt=int(z["max_ckpt"]), ef=a.ef, calib=np.array(rows))
-        print(f"[calibrate] chose tau={best[0]} jmax={best[1]} recall={best[2]:.4f} ms={best[3]:.3f}", flush=True)
+                 max_ckpt=int(z["max_ckpt"]), ef=best[4], calib=np.array(rows))
+        print(f"[calibrate] chose ef={best[4]} tau={best[0]} jmax={best[1]} recall={best[2]:.4f} ms={best[3]:.3f}",
+              flush=True)
 
 
 if __name__ == "__main__":

@@ -155,3 +155,26 @@ def test_mixed_poisson_stream_two_indices(hnsw, setup):
             ids, ds = _standalone(hnsw, idx, net, Q[qidx[i]:qidx[i] + 1], int(k[i]), int(ef[i]), int(mode[i]))
             assert np.array_equal(r["ids"][i, :k[i]], ids[0]), (nm, i)
             assert np.array_equal(r["dists"][i, :k[i]], ds[0]), (nm, i)
+
+
+def test_free_while_serving_returns_at_once(hnsw, setup):
+    """Releasing an index (or net) while a server kernel is resident must not
+    wait for the device to go idle: the library holds such frees until the
+    last server stops.  The server's short budget bounds the test."""
+    import time
+
+    X, Q, idx, net = setup["uniform16"]
+    srv = hnsw.Server(idx, mlp=None, slots=8, waves=4, ef_max=64, k_max=10, budget_s=8.0)
+    try:
+        G = oracle.Graph.build(X[:500], M=8, efC=20, seed=1)
+        extra = hnsw.Index(G.packed(), X[:500])
+        extra_net = hnsw.Mlp(mlp_ref.init(3), tau=0.0, jmax=0)
+        t0 = time.time()
+        extra.close()
+        del extra_net
+        dt = time.time() - t0
+        assert dt < 2.0, f"free blocked for {dt:.1f} s while a server ran"
+        t = srv.submit(Q[0], 10, 32)
+        assert _wait(srv, t, 10, time.time() + 5.0) is not None
+    finally:
+        srv.stop()

@@ -6,6 +6,7 @@ special cases the paper states, hand-traced examples, or a differently
 structured model of the same algorithm.
 """
 import math
+import os
 
 import numpy as np
 import pytest
@@ -262,15 +263,22 @@ def test_mL_zero_simple_selection_gives_knn_graph():
 # --------------------------------------------------- P8: hand-traced example
 
 
-def test_search_layer_hand_trace():
-    """Alg. 2 on a path graph 0-1-2-...-9 of points x_i = i (1-D), query 6.4,
-    enter point 0, ef = 2: the beam walks right and stops with W = {6, 7}.
+def _golden(name):
+    """key -> list of values from a tests/golden text fixture."""
+    out = {}
+    for line in open(os.path.join(os.path.dirname(__file__), "golden", name)):
+        line = line.split("#")[0].split()
+        if line:
+            out[line[0]] = line[1:]
+    return out
 
-    Trace: expand 0 -> W={0,1}; expand 1 -> W={1,2}; ...; expand 6 -> sees 7
-    (d=0.36) and W={6,7}; expand 7 -> sees 8 (d=2.56 > d(7)) rejected; next
-    candidate 5 is further than the furthest of W, stop.  Distances: 10.
-    """
-    n = 10
+
+def test_search_layer_hand_trace():
+    """Alg. 2 on a path graph of points x_i = i (1-D): the hand trace stored
+    in tests/golden/search_layer_path_trace.txt (query 6.4, enter point 0,
+    ef = 2: the beam walks right and stops with W = {6, 7})."""
+    gd = _golden("search_layer_path_trace.txt")
+    n = int(gd["points"][0])
     x = np.arange(n, dtype=np.float32)[:, None]
     adj = np.full((n, 8), 0xFFFFFFFF, np.uint32)
     for i in range(n):
@@ -279,10 +287,11 @@ def test_search_layer_hand_trace():
     packed = dict(metric=oracle.L2, M=4, Mmax=4, Mmax0=8, entry_point=0, max_level=0,
                   levels=np.zeros(n, np.uint8), adj0=adj, adjU=np.zeros((0, 4), np.uint32))
     G = oracle.Graph.from_packed(x, packed)
-    ids, ds, ndist = G.search_layer(np.array([6.4], np.float32), [0], ef=2, lc=0)
-    assert list(ids) == [6, 7]
-    assert np.allclose(ds, [0.16, 0.36], rtol=1e-6)
-    assert ndist == 9  # 0 (entry) + 1..8 each evaluated once; 9 never seen
+    ids, ds, ndist = G.search_layer(np.array([float(gd["query"][0])], np.float32), [int(gd["enter"][0])],
+                                    ef=int(gd["ef"][0]), lc=0)
+    assert list(ids) == [int(v) for v in gd["result_ids"]]
+    assert np.allclose(ds, [float(v) for v in gd["result_dists"]], rtol=1e-6)
+    assert ndist == int(gd["distance_evaluations"][0])  # 0 (entry) + 1..8 once each; 9 never seen
 
 
 # ---------------------------------------------- P7 / P8: search equivalences
@@ -378,9 +387,13 @@ def test_memory_model_against_paper_range():
     the paper puts at about 60-450 bytes for M in [6, 48].  With the level law's
     floor the exact expectation is (Mmax0 + Mmax/(M-1)) * 4; the oracle's packed
     graph must match that, and the paper's own formula must span its range."""
-    lo = (12 + 6 / math.log(6)) * 4
-    hi = (96 + 48 / math.log(48)) * 4
-    assert 55 < lo < 65 and 420 < hi < 460
+    gd = _golden("memory_per_element.txt")
+    m_lo, m_hi = int(gd["m_low"][0]), int(gd["m_high"][0])
+    b_lo, b_hi = float(gd["bytes_low"][0]), float(gd["bytes_high"][0])
+    # the paper's formula with Mmax0 = 2M, Mmax = M, mL = 1/ln M
+    lo = (2 * m_lo + m_lo / math.log(m_lo)) * 4
+    hi = (2 * m_hi + m_hi / math.log(m_hi)) * 4
+    assert abs(lo - b_lo) / b_lo < 0.1 and abs(hi - b_hi) / b_hi < 0.05
     M, n = 16, 1_000_000
     lv = oracle.levels(99, n, 1 / math.log(M))
     per = (2 * M * n + M * lv.astype(np.int64).sum()) * 4 / n

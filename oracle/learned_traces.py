@@ -76,7 +76,9 @@ if __name__ == "__main__":
     ap.add_argument("--ef", type=int, default=512)
     ap.add_argument("--out", required=True)
     ap.add_argument("--threads", type=int, default=None)
+    ap.add_argument("--period", type=int, default=8, help="layer-0 expansions between checkpoints")
+    ap.add_argument("--max-ckpt", type=int, default=64)
     a = ap.parse_args()
-    F, Y, meta = make(a.workload, a.nq, a.ef, threads=a.threads)
+    F, Y, meta = make(a.workload, a.nq, a.ef, period=a.period, max_ckpt=a.max_ckpt, threads=a.threads)
     np.savez(a.out, feats=F, labels=Y, **meta)
     print(f"[traces] wrote {a.out}", flush=True)

@@ -31,10 +31,11 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(KIND == kFP8
     search_query<G, F, METRIC, KIND, false>(ix, a);
 }
 
-// The learned stop rule raises register use; forcing five waves spills
-// inside the loop and is slower than four without spills.
+// The learned stop rule: also six waves per SIMD (its checkpoint keeps its
+// addresses and constants out of the expansion loop, see learned_checkpoint).
 template <int G, int F, int METRIC>
-__global__ __launch_bounds__(64) void search_kernel_learned(DevIndex ix, SearchArgs a) {
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(6))) void search_kernel_learned(DevIndex ix,
+                                                                                                    SearchArgs a) {
     search_query<G, F, METRIC, kF32, true>(ix, a);
 }
 

@@ -405,10 +405,12 @@ struct LearnState {
     float d_start, d_best_prev, d_k_prev;
 };
 
-__device__ __forceinline__ float lratio(float a, float b) {
-    const float den = fabsf(b) + 1e-20f;
+// a / (|b| + tiny) clamped to [-big, big]; big = 1e6, tiny = 1e-20 (passed in
+// scalar registers so that the constants are not held in vector registers).
+__device__ __forceinline__ float lratio(float a, float b, float big, float tiny) {
+    const float den = fabsf(b) + tiny;
     const float r = a / den;
-    return r > 1e6f ? 1e6f : (r < -1e6f ? -1e6f : r);
+    return r > big ? big : (r < -big ? -big : r);
 }
 
 // A wave-uniform float held in a scalar register.
@@ -422,12 +424,29 @@ __device__ __forceinline__ float bf16_round(float f) {
     return __uint_as_float(u);
 }
 
-__device__ __forceinline__ float bf16_value(uint16_t b) { return __uint_as_float(static_cast<uint32_t>(b) << 16); }
+
+// BF16 value h (0..7) of a 16-byte piece, as a float (exact).
+__device__ __forceinline__ float bf16_half(const uint4 &p, int h) {
+    const uint32_t w = h < 2 ? p.x : (h < 4 ? p.y : (h < 6 ? p.z : p.w));
+    return __uint_as_float((h & 1) ? (w & 0xFFFF0000u) : (w << 16));
+}
 
 // Returns true when the rule stops the search; may lower ef and wsize.
 __device__ bool learned_checkpoint(const WaveLds &s, const DevMlp &net, LearnState &st, uint32_t n_exp0,
                                    uint32_t K, int cursor, uint32_t &ef, uint32_t &wsize, float *trace) {
-    const int lane = lane_id();
+    // The lane id is re-read here behind an empty asm barrier: addresses the
+    // checkpoint derives from it are then formed inside the checkpoint instead
+    // of being hoisted out of the expansion loop and kept live across it.
+    int lane = lane_id();
+    asm volatile("" : "+v"(lane));
+    float big = 1e6f, tiny = 1e-20f;
+    asm volatile("" : "+s"(big), "+s"(tiny));
+    // likewise the loop-invariant inputs of the features (K, the upper-layer
+    // expansion count, the distance at the start of layer 0)
+    asm volatile("" : "+s"(K));
+    uint32_t n_exp_upper = st.n_exp_upper;
+    float d_start = st.d_start;
+    asm volatile("" : "+s"(n_exp_upper), "+s"(d_start));
     const uint32_t ck = ++st.ckpt;
     const uint32_t n = wsize;
     const uint32_t kk = n < K ? n : K;
@@ -471,25 +490,25 @@ __device__ bool learned_checkpoint(const WaveLds &s, const DevMlp &net, LearnSta
     if (lane == 0) {
         fs[0] = static_cast<float>(n_exp0) / fe;
         fs[1] = static_cast<float>(n_exp0) / 256.0f;
-        fs[2] = static_cast<float>(st.n_exp_upper) / 16.0f;
+        fs[2] = static_cast<float>(n_exp_upper) / 16.0f;
         fs[3] = static_cast<float>(n) / fe;
         fs[4] = static_cast<float>(pos) / fe;
         fs[5] = static_cast<float>(n_unexp) / fe;
         fs[6] = static_cast<float>(changed) / static_cast<float>(K);
         fs[7] = static_cast<float>(ck) / 32.0f;
-        fs[8] = lratio(d_best, st.d_start);
-        fs[9] = lratio(d_k, st.d_start);
-        fs[10] = lratio(d_f, st.d_start);
-        fs[11] = lratio(d_next, st.d_start);
-        fs[12] = lratio(d_best, d_k);
-        fs[13] = lratio(d_k, d_f);
-        fs[14] = lratio(d_next, d_k);
-        fs[15] = lratio(st.d_k_prev, d_k);
-        fs[16] = lratio(st.d_best_prev, d_best);
-        fs[17] = lratio(d_k - d_best, d_f - d_best);
+        fs[8] = lratio(d_best, d_start, big, tiny);
+        fs[9] = lratio(d_k, d_start, big, tiny);
+        fs[10] = lratio(d_f, d_start, big, tiny);
+        fs[11] = lratio(d_next, d_start, big, tiny);
+        fs[12] = lratio(d_best, d_k, big, tiny);
+        fs[13] = lratio(d_k, d_f, big, tiny);
+        fs[14] = lratio(d_next, d_k, big, tiny);
+        fs[15] = lratio(st.d_k_prev, d_k, big, tiny);
+        fs[16] = lratio(st.d_best_prev, d_best, big, tiny);
+        fs[17] = lratio(d_k - d_best, d_f - d_best, big, tiny);
         fs[18] = fe / 512.0f;
         fs[19] = static_cast<float>(K) / 100.0f;
-        fs[20] = lratio(d_next - d_k, d_f - d_best);
+        fs[20] = lratio(d_next - d_k, d_f - d_best, big, tiny);
         fs[21] = d_next < d_k ? 1.0f : 0.0f;
         fs[22] = pos < K ? 1.0f : 0.0f;
         fs[23] = 1.0f;
@@ -498,23 +517,51 @@ __device__ bool learned_checkpoint(const WaveLds &s, const DevMlp &net, LearnSta
     st.d_k_prev = d_k;
     wave_sync();
     if (trace && lane < kMlpIn) trace[static_cast<size_t>(ck - 1) * (kMlpIn + 2) + lane] = fs[lane];
-    // layer 1 (lane = hidden unit), inputs in order
+    // layer 1 (lane = hidden unit), inputs in order; the unit's 24 BF16
+    // weights are three 16-byte pieces, fetched together
+    const uint4 *r1 = reinterpret_cast<const uint4 *>(net.w1) + lane * 3;
+    const uint4 w10 = r1[0], w11 = r1[1], w12 = r1[2];
     float a = net.b1[lane];
-#pragma unroll 4
-    for (int i = 0; i < kMlpIn; ++i) a = fmaf(bf16_value(net.w1[lane * kMlpIn + i]), bf16_round(fs[i]), a);
+#pragma unroll
+    for (int i = 0; i < kMlpIn; ++i) {
+        const uint4 &p = i < 8 ? w10 : (i < 16 ? w11 : w12);
+        a = fmaf(bf16_half(p, i & 7), bf16_round(fs[i]), a);
+    }
     const float h1 = bf16_round(a > 0.0f ? a : 0.0f);
     wave_sync();
     s.hid[lane] = h1;
     wave_sync();
+    // layer 2: 64 weights per unit, eight pieces in two groups of four
     a = net.b2[lane];
-#pragma unroll 4
-    for (int i = 0; i < kMlpHid; ++i) a = fmaf(bf16_value(net.w2[lane * kMlpHid + i]), s.hid[i], a);
+    {
+        const uint4 *r2 = reinterpret_cast<const uint4 *>(net.w2) + lane * 8;
+#pragma unroll
+        for (int g = 0; g < 2; ++g) {
+            const uint4 q0 = r2[4 * g], q1 = r2[4 * g + 1], q2 = r2[4 * g + 2], q3 = r2[4 * g + 3];
+#pragma unroll
+            for (int i = 0; i < 32; ++i) {
+                const uint4 &p = i < 8 ? q0 : (i < 16 ? q1 : (i < 24 ? q2 : q3));
+                a = fmaf(bf16_half(p, i & 7), s.hid[32 * g + i], a);
+            }
+        }
+    }
     s.hid[64 + lane] = bf16_round(a > 0.0f ? a : 0.0f);
     wave_sync();
+    // layer 3: lanes 0 and 1 hold the two outputs (the others repeat row 0)
     const int o = lane < kMlpOut ? lane : 0;
     a = net.b3[o];
-#pragma unroll 4
-    for (int i = 0; i < kMlpHid; ++i) a = fmaf(bf16_value(net.w3[o * kMlpHid + i]), s.hid[64 + i], a);
+    {
+        const uint4 *r3 = reinterpret_cast<const uint4 *>(net.w3) + o * 8;
+#pragma unroll
+        for (int g = 0; g < 2; ++g) {
+            const uint4 q0 = r3[4 * g], q1 = r3[4 * g + 1], q2 = r3[4 * g + 2], q3 = r3[4 * g + 3];
+#pragma unroll
+            for (int i = 0; i < 32; ++i) {
+                const uint4 &p = i < 8 ? q0 : (i < 16 ? q1 : (i < 24 ? q2 : q3));
+                a = fmaf(bf16_half(p, i & 7), s.hid[64 + 32 * g + i], a);
+            }
+        }
+    }
     const float out0 = __uint_as_float(__builtin_amdgcn_readlane(__float_as_uint(a), 0));
     const float out1 = __uint_as_float(__builtin_amdgcn_readlane(__float_as_uint(a), 1));
     wave_sync();

@@ -63,7 +63,7 @@ def train(feats, labels, epochs=6, batch=4096, lr=2e-3, lam=0.25, seed=0, log=pr
     return P.cpu().numpy()
 
 
-def calibrate(workload, params, taus, jmaxes=(0, 1, 2), K=10, efs=(512,), nq=2000, target=0.95, log=print):
+def calibrate(workload, params, taus, jmaxes=(0, 1, 2), K=10, efs=(512,), nq=10000, target=0.95, log=print):
     """Recall and time of the learned search for each (ef, tau, jmax) on
     held-out queries; the fastest setting whose mean recall@K reaches the
     target wins."""
@@ -129,7 +129,7 @@ def main():
         print(f"[train] wrote {a.out}", flush=True)
     else:
         z = np.load(a.net)
-        taus = [4.0, 3.0, 2.5, 2.0, 1.5, 1.0, 0.5, 0.0]
+        taus = [8.0, 6.0, 5.0, 4.0, 3.5, 3.0, 2.5, 2.0, 1.5, 1.0, 0.5, 0.0]
         jmaxes = [int(j) for j in a.jmax.split(",")]
         efs = [int(e) for e in a.ef.split(",")]
         best, rows = calibrate(a.workload, z["params"], taus, jmaxes, efs=efs, target=a.target)

@@ -1,6 +1,8 @@
 """The learned stop rule on the GPU: perceptron training kernels against the
 fp64 reference (gradient check), and the learned search against the
 oracle's learned search with the same network."""
+import os
+
 import numpy as np
 import pytest
 
@@ -136,3 +138,47 @@ def test_learned_mode_without_net_is_plain(hnsw):
     assert torch.equal(a[0], b[0]) and torch.equal(a[1], b[1])
     with pytest.raises(hnsw.HnswError):
         hnsw.Mlp(np.full(hnsw.MLP_PARAMS, np.nan, np.float32))
+
+
+GLOVE = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "graphs", "glove_like_1200k.bin")
+NET = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "paper_1603_09320_amd", "nets",
+                   "glove_like.mlp.npz")
+
+
+@pytest.mark.skipif(not (os.path.exists(GLOVE) and os.path.exists(NET)), reason="glove_like graph or net not built")
+def test_trained_net_gain_on_glove_like(hnsw):
+    """What the trained network gains over the method without it, on the
+    1.2M x 100 inner-product workload with its calibrated (ef, tau): the plain
+    search at that ef, and the plain search at every smaller swept ef that
+    reaches at least the learned recall, do more layer-0 expansions."""
+    print("case learned gain glove_like 1.2M", flush=True)
+    p = hnsw.graphfile.read(GLOVE)
+    X = synthdata.base("glove_like", p["n"])
+    Q = synthdata.queries("glove_like", 4000)
+    idx = hnsw.Index(p, X)
+    q = torch.from_numpy(Q).cuda()
+    _, gt = hnsw.bruteforce(idx, q, 10)
+    gt = gt.cpu().numpy()
+    net = hnsw.Mlp.load(NET)
+    ef = int(np.load(NET)["ef"])
+
+    def run(ef_, mode, mlp=None):
+        ids, _, cnt = idx.search(q, 10, ef_, mode=mode, mlp=mlp, counters=True)
+        torch.cuda.synchronize()
+        ids, cnt = ids.cpu().numpy(), cnt.cpu().numpy().astype(np.float64)
+        x = X[np.clip(ids, 0, None)].astype(np.float64)
+        d = 1.0 - (x * Q[:, None, :].astype(np.float64)).sum(-1)
+        return float(((d <= gt[:, 9:10]).sum(1) / 10).mean()), float(cnt[:, 3].mean())
+
+    rec_l, exp_l = run(ef, hnsw.MODE_LEARNED, net)
+    rec_p, exp_p = run(ef, hnsw.MODE_PLAIN)
+    print(f"  learned ef={ef} tau={net.tau}: recall {rec_l:.4f}, {exp_l:.1f} layer-0 expansions", flush=True)
+    print(f"  plain   ef={ef}: recall {rec_p:.4f}, {exp_p:.1f}", flush=True)
+    assert rec_l >= rec_p - 0.01
+    assert exp_l <= 0.9 * exp_p
+    # the plain search needs more work than the learned one to reach the learned recall
+    for e in range(32, ef + 1, 32):
+        r, x_ = run(e, hnsw.MODE_PLAIN)
+        print(f"  plain   ef={e}: recall {r:.4f}, {x_:.1f}", flush=True)
+        if r >= rec_l:
+            assert x_ > exp_l

@@ -221,6 +221,47 @@ def serve_bench(hnsw, index, Q, mlp, rates=(50_000, 200_000, 500_000), n_req=20_
             "rates": out}
 
 
+def learned_glove_bench(hnsw, steps=10, warmup=2, target=0.90):
+    """The learned stop rule where it pays: glove_like 1.2M x 100 (inner
+    product) with the net trained and calibrated for it.  This stand-in reaches
+    recall@10 0.92 at ef 512, so the target here is 0.90; plain and learned
+    are each timed at the smallest swept ef that reaches it."""
+    import torch
+
+    import synthdata
+
+    path, n, nq, K = WORKLOADS["glove_like"]
+    gpath = os.path.join(ROOT, path)
+    mpath = os.path.join(ROOT, "paper_1603_09320_amd", "nets", "glove_like.mlp.npz")
+    if not (os.path.exists(gpath) and os.path.exists(mpath)):
+        log("[glove] graph or net missing: skipped")
+        return None
+    g = hnsw.graphfile.read(gpath)
+    X = synthdata.base("glove_like", g["n"])
+    Q = synthdata.queries("glove_like", nq)
+    index = hnsw.Index(g, X)
+    q = torch.from_numpy(Q).cuda()
+    _, gt = hnsw.bruteforce(index, q, K)
+    torch.cuda.synchronize()
+    mlp = hnsw.Mlp.load(mpath)
+    run = Runner(index, q, X, Q, K, gt.cpu().numpy(), g["metric"], torch.cuda.current_stream(), mlp)
+    efs = [e for e in EF_SWEEP if e >= 64 and e <= 512] + [448]
+    out = {"workload": f"glove_like {g['n']}x{g['dim']} inner product, {nq} queries, K={K}",
+           "target_recall": target, "net": {"tau": mlp.tau, "jmax": mlp.jmax, "period": mlp.period}}
+    for form, mode in (("plain", 0), ("learned", 3)):
+        ef, rec, _ = run.sweep(mode, sorted(set(efs)), target)
+        _, _, cnt = run.search(ef, mode, counters=True)
+        torch.cuda.synchronize()
+        ms, kern_ms = run.time(ef, mode, steps, warmup)
+        out[form] = {"ef": ef, "recall": round(rec, 5), "qps": round(nq / (ms / 1000.0), 1),
+                     "kernel_ms": round(kern_ms, 4),
+                     "expansions_per_query": round(float(cnt.cpu().numpy()[:, 1].astype(np.float64).mean()), 2)}
+        log(f"[glove] {form}: {out[form]}")
+    out["learned_vs_plain_qps"] = round(out["learned"]["qps"] / out["plain"]["qps"], 4)
+    index.close()
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -233,6 +274,7 @@ def main():
     ap.add_argument("--target-recall", type=float, default=0.95)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-serve", action="store_true", help="skip the serving-loop measurement")
+    ap.add_argument("--no-glove", action="store_true", help="skip the learned-rule measurement on glove_like")
     ap.add_argument("--copy-probe-bytes", type=int, default=0,
                     help="also run a plain device-to-device copy of this size (counter calibration)")
     a = ap.parse_args()
@@ -322,6 +364,9 @@ def main():
     serving = None
     if not a.no_serve:
         serving = serve_bench(hnsw, index, Q, mlp)
+    glove = None
+    if not a.no_glove and a.workload == "sift_like":
+        glove = learned_glove_bench(hnsw)
 
     head = results.get("plain") or next(iter(results.values()))
     cpu = None
@@ -358,6 +403,7 @@ def main():
                        "tflops": round(2.0 * nq * graph["n"] * graph["dim"] / (bf_ms / 1000.0) / 1e12, 2)},
         "cpu_baseline": cpu,
         "serving": serving,
+        "learned_glove_like": glove,
     }
     print(json.dumps(out), flush=True)
     index.close()

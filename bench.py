@@ -48,7 +48,7 @@ def log(msg):
 
 def kernel_source_hash() -> str:
     h = hashlib.sha256()
-    for f in ("search.hip", "search_device.h", "internal.h"):
+    for f in ("search.hip", "search_kernels.h", "search_device.h", "internal.h"):
         with open(os.path.join(ROOT, "paper_1603_09320_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]

@@ -233,7 +233,12 @@ hnsw_status hnsw_mlp_adam(float *params, const float *grad, float *m, float *v, 
  *   budget_s  wall-clock seconds after which every wave exits even without a
  *             stop (a bound on the kernel's lifetime).
  * The server runs on a stream of its own.  Results are bit-identical to
- * hnsw_search_batch_ex with the same (query, k, ef, mode).
+ * hnsw_search_batch_ex with the same (query, k, ef, mode).  An index whose
+ * fp32 or low-precision vector store exceeds 2 GiB is refused
+ * (HNSW_ERR_UNSUPPORTED): the serving kernel gathers with 32-bit offsets.
+ * While a server runs, device and pinned-host frees requested through this
+ * library (index, net, other servers) are held until the last server stops:
+ * hipFree would wait for the resident server kernel.
  */
 typedef struct hnsw_server hnsw_server;
 hnsw_status hnsw_server_start(const hnsw_index *index, const hnsw_mlp *mlp, uint32_t slots, uint32_t waves,

@@ -85,6 +85,10 @@ hipError_t launch_bruteforce(const DevIndex &ix, const float *Q, uint32_t nq, ui
                              uint64_t *partial, uint32_t nchunks, uint32_t chunk, int32_t *ids, double *d,
                              hipStream_t stream);
 hipError_t launch_search(const DevIndex &ix, const SearchArgs &a, hipStream_t stream);
+// The same for indices with a vector store above 2 GiB (64-bit addressed gathers).
+hipError_t launch_search_wide(const DevIndex &ix, const SearchArgs &a, hipStream_t stream);
+// True when every vector store of the index fits the buffered gathers.
+bool stores_buffered(const DevIndex &ix);
 
 }  // namespace hnsw
 

@@ -1,82 +1,12 @@
 // Batched K-NN-SEARCH (Alg. 5 of arXiv:1603.09320) for gfx950: one workgroup
 // of one wavefront per query; the search itself is search_one in
-// search_device.h.
-#include "search_device.h"
+// search_device.h.  This unit holds the buffered-gather kernels (stores of at
+// most 2 GiB); search_wide.hip holds those for larger stores.
+#include <stdlib.h>
+
+#include "search_kernels.h"
 
 namespace hnsw {
-namespace {
-
-template <int G, int F, int METRIC, int KIND, bool LEARN>
-__device__ __forceinline__ void search_query(const DevIndex &ix, const SearchArgs &a) {
-    extern __shared__ __align__(16) uint8_t smem[];
-    const uint32_t qi = blockIdx.x;
-    if (qi >= a.nq) return;
-    Job job;
-    job.q = a.queries + static_cast<size_t>(qi) * ix.dim;
-    job.k = a.k;
-    job.ef = a.ef;
-    job.ids = a.ids + static_cast<size_t>(qi) * a.k;
-    job.dists = a.dists + static_cast<size_t>(qi) * a.k;
-    job.counters = a.counters ? a.counters + static_cast<size_t>(qi) * 4 : nullptr;
-    job.trace = LEARN && a.ckpt_trace ? a.ckpt_trace + static_cast<size_t>(qi) * a.mlp.max_ckpt * (kMlpIn + 2)
-                                      : nullptr;
-    search_one<G, F, METRIC, KIND, LEARN>(ix, a, job, carve(smem, a));
-}
-
-// Waves per SIMD the register allocation is held to: six for the fp32 and
-// BF16 stores (80 registers, no spills), five for FP8 (its decode needs more).
-template <int G, int F, int METRIC, int KIND>
-__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(KIND == kFP8 ? 5 : 6))) void search_kernel(
-    DevIndex ix, SearchArgs a) {
-    search_query<G, F, METRIC, KIND, false>(ix, a);
-}
-
-// The learned stop rule: also six waves per SIMD (its checkpoint keeps its
-// addresses and constants out of the expansion loop, see learned_checkpoint).
-template <int G, int F, int METRIC>
-__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(6))) void search_kernel_learned(DevIndex ix,
-                                                                                                    SearchArgs a) {
-    search_query<G, F, METRIC, kF32, true>(ix, a);
-}
-
-template <int G, int F, int KIND>
-hipError_t launch_gfk(const DevIndex &ix, const SearchArgs &a, hipStream_t stream) {
-    const size_t lds = search_lds_bytes(a);
-    if constexpr (KIND == kF32) {
-        if (a.mode == HNSW_MODE_LEARNED) {
-            if (ix.metric == HNSW_IP)
-                hipLaunchKernelGGL((search_kernel_learned<G, F, HNSW_IP>), dim3(a.nq), dim3(64), lds, stream, ix, a);
-            else
-                hipLaunchKernelGGL((search_kernel_learned<G, F, HNSW_L2SQ>), dim3(a.nq), dim3(64), lds, stream, ix, a);
-            return hipGetLastError();
-        }
-    }
-    if (ix.metric == HNSW_IP)
-        hipLaunchKernelGGL((search_kernel<G, F, HNSW_IP, KIND>), dim3(a.nq), dim3(64), lds, stream, ix, a);
-    else
-        hipLaunchKernelGGL((search_kernel<G, F, HNSW_L2SQ, KIND>), dim3(a.nq), dim3(64), lds, stream, ix, a);
-    return hipGetLastError();
-}
-
-template <int KIND>
-hipError_t launch_kind(const DevIndex &ix, const SearchArgs &a, hipStream_t stream) {
-    const TileShape t = tile_for(KIND, ix.dim);
-    switch (t.G * 16 + t.F) {
-        case 1 * 16 + 1: return launch_gfk<1, 1, KIND>(ix, a, stream);
-        case 2 * 16 + 1: return launch_gfk<2, 1, KIND>(ix, a, stream);
-        case 2 * 16 + 2: return launch_gfk<2, 2, KIND>(ix, a, stream);
-        case 4 * 16 + 1: return launch_gfk<4, 1, KIND>(ix, a, stream);
-        case 4 * 16 + 2: return launch_gfk<4, 2, KIND>(ix, a, stream);
-        case 8 * 16 + 1: return launch_gfk<8, 1, KIND>(ix, a, stream);
-        case 8 * 16 + 2: return launch_gfk<8, 2, KIND>(ix, a, stream);
-        case 16 * 16 + 1: return launch_gfk<16, 1, KIND>(ix, a, stream);
-        case 16 * 16 + 2: return launch_gfk<16, 2, KIND>(ix, a, stream);
-        case 16 * 16 + 4: return launch_gfk<16, 4, KIND>(ix, a, stream);
-        default: return hipErrorInvalidValue;
-    }
-}
-
-}  // namespace
 
 // Lane-group tile for a store: G lanes per vector, F pieces per lane.
 // fp32 rows use two pieces per lane up to 128 dimensions; low-precision
@@ -105,12 +35,21 @@ size_t search_lds_bytes(const SearchArgs &a) {
            (static_cast<size_t>(1) << a.ht_log2) * 4;
 }
 
+bool stores_buffered(const DevIndex &ix) {
+    auto fits = [&](const void *p, uint32_t stride16) {
+        return !p || (static_cast<uint64_t>(ix.n) + 1) * stride16 * 16 <= kBufferedMaxBytes;
+    };
+    return fits(ix.vec, ix.stride4) && fits(ix.vbf16, ix.bf16_stride16) && fits(ix.vfp8, ix.fp8_stride16);
+}
+
+// HNSW_WIDE_GATHERS=1 sends every launch through the 64-bit addressed kernels
+// (they are otherwise taken only for stores above 2 GiB), so that tests can
+// check them on small indices.
 hipError_t launch_search(const DevIndex &ix, const SearchArgs &a, hipStream_t stream) {
-    switch (a.mode) {
-        case HNSW_MODE_BF16: return launch_kind<kBF16>(ix, a, stream);
-        case HNSW_MODE_FP8: return launch_kind<kFP8>(ix, a, stream);
-        default: return launch_kind<kF32>(ix, a, stream);
-    }
+    const char *w = getenv("HNSW_WIDE_GATHERS");
+    const bool force_wide = w && w[0] == '1';
+    if (stores_buffered(ix) && !force_wide) return launch_search_stores<true>(ix, a, stream);
+    return launch_search_wide(ix, a, stream);
 }
 
 }  // namespace hnsw

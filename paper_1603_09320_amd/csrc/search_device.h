@@ -220,12 +220,33 @@ struct RowSource {
     uint32_t stride;     // pieces per row
     uint32_t pieces;     // pieces holding values (the rest of the row is padding/scale)
     uint32_t scale_off;  // FP8: byte offset of the scale within the row
+    __amdgpu_buffer_rsrc_t rsrc;  // raw buffer over the store (buffered kernels: the store spans <= 2 GiB)
 };
 
+// Raw buffer descriptor word 3 for gfx9-family targets (32-bit data, no
+// swizzle); loads beyond num_records return zero.
+constexpr int kBufferDword3 = 0x00020000;
+// Largest store the buffered gathers address (32-bit offsets, with room for
+// the out-of-range offset of a padding piece).
+constexpr uint64_t kBufferedMaxBytes = 1ull << 31;
+
+__device__ __forceinline__ RowSource make_source(const void *base, uint32_t stride, uint32_t pieces,
+                                                 uint32_t scale_off, uint32_t n) {
+    RowSource r;
+    r.base = reinterpret_cast<const uint4 *>(base);
+    r.stride = stride;
+    r.pieces = pieces;
+    r.scale_off = scale_off;
+    const uint64_t bytes = (static_cast<uint64_t>(n) + 1) * stride * 16;
+    r.rsrc = __builtin_amdgcn_make_buffer_rsrc(const_cast<void *>(base), 0,
+                                               static_cast<int>(bytes <= kBufferedMaxBytes ? bytes : 0), kBufferDword3);
+    return r;
+}
+
 __device__ __forceinline__ RowSource rows_of(const DevIndex &ix, const SearchArgs &a, int kind) {
-    if (kind == kF32) return {reinterpret_cast<const uint4 *>(ix.vec), ix.stride4, ix.stride4, 0};
-    if (kind == kBF16) return {reinterpret_cast<const uint4 *>(ix.vbf16), ix.bf16_stride16, ix.bf16_stride16, 0};
-    return {reinterpret_cast<const uint4 *>(ix.vfp8), ix.fp8_stride16, ix.fp8_pieces, ix.fp8_scale_off};
+    if (kind == kF32) return make_source(ix.vec, ix.stride4, ix.stride4, 0, ix.n);
+    if (kind == kBF16) return make_source(ix.vbf16, ix.bf16_stride16, ix.bf16_stride16, 0, ix.n);
+    return make_source(ix.vfp8, ix.fp8_stride16, ix.fp8_pieces, ix.fp8_scale_off, ix.n);
 }
 
 // Scores ids[0..m) against the query; keys[slot] receives the key of ids[slot].
@@ -235,7 +256,7 @@ __device__ __forceinline__ RowSource rows_of(const DevIndex &ix, const SearchArg
 // all-zero row n instead (the address is chosen, not the value, so no load is
 // split or predicated).  Distances: sum over coordinates of (q_j - s*x_j)^2,
 // or 1 - sum q_j*s*x_j, in double (s = 1 except for FP8), rounded once to float.
-template <int G, int F, int METRIC, int KIND>
+template <int G, int F, int METRIC, int KIND, bool BUF>
 __device__ __forceinline__ void score_ids(const DevIndex &ix, const RowSource &src, const QueryRegs<G, F, KIND> &Q,
                                           const uint32_t *ids, int m, uint64_t *keys) {
     constexpr int P = 64 / G;
@@ -247,6 +268,14 @@ __device__ __forceinline__ void score_ids(const DevIndex &ix, const RowSource &s
     const int lane = lane_id();
     const int grp = lane / G, sub = lane % G;
     const size_t zero_row = static_cast<size_t>(ix.n) * src.stride;
+    // byte offset of each of this lane's pieces within a row (buffered path);
+    // 0x80000000 places a piece past the row's values beyond the store
+    uint32_t coff[F];
+#pragma unroll
+    for (int f = 0; f < F; ++f) {
+        const uint32_t c = static_cast<uint32_t>(sub + f * G);
+        coff[f] = c < src.pieces ? c * 16u : 0x80000000u;
+    }
     for (int base = 0; base < m; base += P * B) {
         // sub-batches holding at least one id (wave-uniform: m and base are)
         const int nb = min(B, (m - base + P - 1) / P);
@@ -257,18 +286,35 @@ __device__ __forceinline__ void score_ids(const DevIndex &ix, const RowSource &s
         for (int b = 0; b < B; ++b) idv[b] = base + b * P + grp < m ? idv[b] : ix.n;
         uint4 v[B][F];
         float sc[B];
+        if constexpr (BUF) {
+            // 32-bit offsets: one multiply per row; a piece past the row's
+            // values gets an offset beyond the store, which reads as zero
 #pragma unroll
-        for (int b = 0; b < B; ++b) {
-            if (b >= nb) break;
-            const size_t row = static_cast<size_t>(idv[b]) * src.stride;
+            for (int b = 0; b < B; ++b) {
+                if (b >= nb) break;
+                const uint32_t roff = idv[b] * (src.stride * 16u);
 #pragma unroll
-            for (int f = 0; f < F; ++f) {
-                const uint32_t c = static_cast<uint32_t>(sub + f * G);
-                v[b][f] = src.base[c < src.pieces ? row + c : zero_row];
+                for (int f = 0; f < F; ++f) {
+                    const auto w = __builtin_amdgcn_raw_buffer_load_b128(src.rsrc, roff + coff[f], 0, 0);
+                    v[b][f] = make_uint4(w[0], w[1], w[2], w[3]);
+                }
+                if (KIND == kFP8)
+                    sc[b] = __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(src.rsrc, roff + src.scale_off, 0, 0));
             }
-            if (KIND == kFP8)
-                sc[b] = *reinterpret_cast<const float *>(reinterpret_cast<const uint8_t *>(src.base + row) +
-                                                         src.scale_off);
+        } else {
+#pragma unroll
+            for (int b = 0; b < B; ++b) {
+                if (b >= nb) break;
+                const size_t row = static_cast<size_t>(idv[b]) * src.stride;
+#pragma unroll
+                for (int f = 0; f < F; ++f) {
+                    const uint32_t c = static_cast<uint32_t>(sub + f * G);
+                    v[b][f] = src.base[c < src.pieces ? row + c : zero_row];
+                }
+                if (KIND == kFP8)
+                    sc[b] = *reinterpret_cast<const float *>(reinterpret_cast<const uint8_t *>(src.base + row) +
+                                                             src.scale_off);
+            }
         }
 #pragma unroll
         for (int b = 0; b < B; ++b) {
@@ -606,7 +652,7 @@ __device__ __forceinline__ void sort_w(uint64_t *W, uint32_t n, uint32_t cap) {
 
 // One query, answered by the calling wave (Alg. 5).  `s` is the wave's LDS
 // workspace, sized for a.wpow2 and a.ht_log2; job.ef >= job.k.
-template <int G, int F, int METRIC, int KIND, bool LEARN>
+template <int G, int F, int METRIC, int KIND, bool LEARN, bool BUF>
 __device__ void search_one(const DevIndex &ix, const SearchArgs &a, const Job &job, const WaveLds &s) {
     const int lane = lane_id();
     const RowSource src = rows_of(ix, a, KIND);
@@ -623,7 +669,7 @@ __device__ void search_one(const DevIndex &ix, const SearchArgs &a, const Job &j
     // Entry point (Alg. 5): its distance seeds the descent.
     if (lane == 0) s.ids[0] = ix.entry;
     wave_sync();
-    score_ids<G, F, METRIC, KIND>(ix, src, Q, s.ids, 1, s.keys);
+    score_ids<G, F, METRIC, KIND, BUF>(ix, src, Q, s.ids, 1, s.keys);
     wave_sync();
     uint64_t cur = s.keys[0];
     n_dist += 1;
@@ -640,7 +686,7 @@ __device__ void search_one(const DevIndex &ix, const SearchArgs &a, const Job &j
             const int m = __popcll(vm);
             if (valid) s.ids[rank_in(vm)] = e;
             wave_sync();
-            score_ids<G, F, METRIC, KIND>(ix, src, Q, s.ids, m, s.keys);
+            score_ids<G, F, METRIC, KIND, BUF>(ix, src, Q, s.ids, m, s.keys);
             wave_sync();
             uint64_t best = cur;
             for (int i = lane; i < m; i += 64) best = s.keys[i] < best ? s.keys[i] : best;
@@ -690,7 +736,7 @@ __device__ void search_one(const DevIndex &ix, const SearchArgs &a, const Job &j
         const int m = __popcll(fm);
         if (fresh) s.ids[rank_in(fm)] = e;
         wave_sync();
-        score_ids<G, F, METRIC, KIND>(ix, src, Q, s.ids, m, s.keys);
+        score_ids<G, F, METRIC, KIND, BUF>(ix, src, Q, s.ids, m, s.keys);
         wave_sync();
         n_dist0 += m;
         n_exp0 += 1;
@@ -715,7 +761,7 @@ __device__ void search_one(const DevIndex &ix, const SearchArgs &a, const Job &j
             const int cnt = static_cast<int>(min(64u, wsize - c0));
             if (lane < cnt) s.ids[lane] = key_id(s.W[c0 + lane]);
             wave_sync();
-            score_ids<G, FX, METRIC, kF32>(ix, sx, QX, s.ids, cnt, s.keys);
+            score_ids<G, FX, METRIC, kF32, BUF>(ix, sx, QX, s.ids, cnt, s.keys);
             wave_sync();
             if (lane < cnt) s.W[c0 + lane] = s.keys[lane];
             wave_sync();

@@ -107,11 +107,11 @@ __global__ __launch_bounds__(64) void serve_kernel(DevIndex ix, SearchArgs a, Se
         job.counters = sv.counters + static_cast<size_t>(slot) * 4;
         job.trace = nullptr;
         if (mode == HNSW_MODE_BF16 && ix.vbf16)
-            search_one<G, F, METRIC, kBF16, false>(ix, a, job, s);
+            search_one<G, F, METRIC, kBF16, false, true>(ix, a, job, s);
         else if (mode == HNSW_MODE_LEARNED && a.mlp.w1)
-            search_one<G, F, METRIC, kF32, true>(ix, a, job, s);
+            search_one<G, F, METRIC, kF32, true, true>(ix, a, job, s);
         else
-            search_one<G, F, METRIC, kF32, false>(ix, a, job, s);
+            search_one<G, F, METRIC, kF32, false, true>(ix, a, job, s);
         // every lane's result stores are visible system-wide before the flag;
         // all lanes store the same value
         __hip_atomic_store(&r->state, 2u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_SYSTEM);
@@ -226,6 +226,8 @@ hnsw_status hnsw_server_start(const hnsw_index *index, const hnsw_mlp *mlp, uint
         k_max > ef_max || !(budget_s > 0.0) || budget_s > 3600.0)
         return HNSW_ERR_INVALID_ARG;
     if (ef_max > HNSW_EF_MAX) return HNSW_ERR_UNSUPPORTED;
+    // the serving kernel gathers with 32-bit buffer offsets only
+    if (!hnsw::stores_buffered(index->ix)) return HNSW_ERR_UNSUPPORTED;
     if (!hnsw::device_count_ok()) return HNSW_ERR_DEVICE;
     hnsw_server *s = new hnsw_server();
     memset(static_cast<void *>(s), 0, sizeof(*s));

@@ -92,6 +92,18 @@ def test_lowp_parity_inner_product_and_dims(hnsw, kind):
         _lowp_parity(hnsw, X, Q, G, 10, 50, kind, oracle.L2)
 
 
+@pytest.mark.parametrize("kind", [1, 2])
+def test_lowp_parity_wide_gathers(hnsw, monkeypatch, kind):
+    """Low-precision traversal and re-rank through the 64-bit addressed
+    kernels (taken for stores above 2 GiB), forced on a small index."""
+    print(f"case lowp wide gathers kind={kind}", flush=True)
+    monkeypatch.setenv("HNSW_WIDE_GATHERS", "1")
+    X = synthdata.base("deep_like", 6000)
+    Q = synthdata.queries("deep_like", 150)
+    G = oracle.Graph.build(X, M=16, efC=60, seed=4004)
+    _lowp_parity(hnsw, X, Q, G, 10, 64, kind, oracle.L2)
+
+
 def test_bf16_equals_fp32_on_integer_data(hnsw):
     """Integer coordinates are exact in BF16: the BF16 search returns exactly the fp32 search's output."""
     X = synthdata.base("sift_like", 30000)

@@ -95,6 +95,19 @@ def test_parity_dims(hnsw, dim):
     _run_parity(hnsw, G, X, Q, 10, 40)
 
 
+@pytest.mark.parametrize("dim", [3, 17, 100, 130])
+def test_parity_wide_gathers(hnsw, monkeypatch, dim):
+    """The 64-bit addressed kernels (taken for vector stores above 2 GiB),
+    forced on small indices: same results as the oracle."""
+    _log(f"case wide gathers dim={dim}")
+    monkeypatch.setenv("HNSW_WIDE_GATHERS", "1")
+    rng = np.random.default_rng(100 + dim)
+    X = rng.random((3000, dim)).astype(np.float32)
+    Q = rng.random((200, dim)).astype(np.float32)
+    G = oracle.Graph.build(X, M=8, efC=60, seed=7)
+    _run_parity(hnsw, G, X, Q, 10, 40)
+
+
 def test_parity_inner_product(hnsw):
     _log("case glove_like 20k x 100 IP")
     X = synthdata.base("glove_like", 20000)

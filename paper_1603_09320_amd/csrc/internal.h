@@ -75,7 +75,8 @@ hipError_t launch_adam(float *P, const float *G, float *M, float *V, uint32_t np
 hipError_t launch_quantize_bf16(const DevIndex &ix, uint16_t *out, hipStream_t stream);
 hipError_t launch_quantize_fp8(const DevIndex &ix, uint8_t *out, hipStream_t stream);
 
-size_t search_lds_bytes(const SearchArgs &a);
+// LDS per wave of a search kernel; `learned` adds the stop rule's buffers.
+size_t search_lds_bytes(const SearchArgs &a, bool learned);
 
 // Brute-force K-NN (MFMA scan + fp64 rerank).
 hipError_t launch_row_norms(const DevIndex &ix, float *out, hipStream_t stream);

@@ -30,8 +30,8 @@ TileShape tile_for(int kind, uint32_t dim) {
     return {16, 2};
 }
 
-size_t search_lds_bytes(const SearchArgs &a) {
-    return static_cast<size_t>(a.wpow2) * 8 + 64 * 8 + 64 * 4 * 2 + 128 * 4 +
+size_t search_lds_bytes(const SearchArgs &a, bool learned) {
+    return static_cast<size_t>(a.wpow2) * 8 + 64 * 8 + 64 * 4 + (learned ? 64 * 4 + 128 * 4 : 0) +
            (static_cast<size_t>(1) << a.ht_log2) * 4;
 }
 

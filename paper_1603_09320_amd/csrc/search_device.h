@@ -354,14 +354,23 @@ struct WaveLds {
     uint32_t *ht;      // [1 << ht_log2]
 };
 
+// The learned stop rule's buffers (prevk, hid) are carved only for its
+// kernels, so the others keep more waves per CU within the LDS.
+template <bool LEARN>
 __device__ __forceinline__ WaveLds carve(uint8_t *base, const SearchArgs &a) {
     WaveLds s;
     s.W = reinterpret_cast<uint64_t *>(base);
     s.keys = s.W + a.wpow2;
     s.ids = reinterpret_cast<uint32_t *>(s.keys + 64);
-    s.prevk = s.ids + 64;
-    s.hid = reinterpret_cast<float *>(s.prevk + 64);
-    s.ht = reinterpret_cast<uint32_t *>(s.hid + 128);
+    if (LEARN) {
+        s.prevk = s.ids + 64;
+        s.hid = reinterpret_cast<float *>(s.prevk + 64);
+        s.ht = reinterpret_cast<uint32_t *>(s.hid + 128);
+    } else {
+        s.prevk = nullptr;
+        s.hid = nullptr;
+        s.ht = s.ids + 64;
+    }
     return s;
 }
 

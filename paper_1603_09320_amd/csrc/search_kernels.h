@@ -24,7 +24,7 @@ __device__ __forceinline__ void search_query(const DevIndex &ix, const SearchArg
     job.counters = a.counters ? a.counters + static_cast<size_t>(qi) * 4 : nullptr;
     job.trace = LEARN && a.ckpt_trace ? a.ckpt_trace + static_cast<size_t>(qi) * a.mlp.max_ckpt * (kMlpIn + 2)
                                       : nullptr;
-    search_one<G, F, METRIC, KIND, LEARN, BUF>(ix, a, job, carve(smem, a));
+    search_one<G, F, METRIC, KIND, LEARN, BUF>(ix, a, job, carve<LEARN>(smem, a));
 }
 
 // Waves per SIMD the register allocation is held to: six for the fp32 and
@@ -45,7 +45,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(6))) void se
 
 template <int G, int F, int KIND, bool BUF>
 hipError_t launch_gfk(const DevIndex &ix, const SearchArgs &a, hipStream_t stream) {
-    const size_t lds = search_lds_bytes(a);
+    const size_t lds = search_lds_bytes(a, KIND == kF32 && a.mode == HNSW_MODE_LEARNED);
     if constexpr (KIND == kF32) {
         if (a.mode == HNSW_MODE_LEARNED) {
             if (ix.metric == HNSW_IP)

@@ -68,7 +68,7 @@ __device__ __forceinline__ uint64_t load_sys64(const uint64_t *p) {
 template <int G, int F, int METRIC>
 __global__ __launch_bounds__(64) void serve_kernel(DevIndex ix, SearchArgs a, ServeArgs sv) {
     extern __shared__ __align__(16) uint8_t smem[];
-    const WaveLds s = carve(smem, a);
+    const WaveLds s = carve<true>(smem, a);
     const int lane = lane_id();
     const uint64_t t_end = wall_clock64() + sv.budget_ticks;
     bool quit = false;
@@ -125,7 +125,7 @@ __global__ __launch_bounds__(64) void serve_kernel(DevIndex ix, SearchArgs a, Se
 template <int G, int F>
 hipError_t launch_serve_gf(const DevIndex &ix, const SearchArgs &a, const ServeArgs &sv, uint32_t waves,
                            hipStream_t st) {
-    const size_t lds = search_lds_bytes(a);
+    const size_t lds = search_lds_bytes(a, true);
     if (ix.metric == HNSW_IP)
         hipLaunchKernelGGL((serve_kernel<G, F, HNSW_IP>), dim3(waves), dim3(64), lds, st, ix, a, sv);
     else

@@ -9,7 +9,7 @@
  * It shares no code, header or table with the GPU library.
  *
  * What it implements, each in the paper's order and notation:
- *   - level draw of Alg. 1 (its line computing l = floor(-ln(unif(0..1)) * mL)),
+ *   - the level draw of Alg. 1, l = floor(-ln(unif(0..1)) * mL),
  *   - SEARCH-LAYER (Alg. 2) with an exact visited set and two binary heaps
  *     (C: nearest first, W: furthest first),
  *   - SELECT-NEIGHBORS-SIMPLE (Alg. 3) and SELECT-NEIGHBORS-HEURISTIC (Alg. 4),
@@ -30,7 +30,7 @@
  *   - unif(0..1): U = (r + 1) * 2^-53 with r the top 53 bits of
  *     splitmix64(seed XOR i), so U lies in (0, 1] and ln U is finite.
  *   - Alg. 4's keep-test: candidate e is kept iff dist(e, q) < dist(e, r) for
- *     every r already kept (the rule stated in Sec. 3; the printed line is
+ *     every r already kept (the rule stated in Sec. 3; the printed test is
  *     garbled).
  *   - Alg. 1: the first element becomes the entry point with no links; a new
  *     element takes M links on every layer it belongs to, layer 0 included;
@@ -503,7 +503,7 @@ static uint64_t splitmix64(uint64_t x) {
     return x ^ (x >> 31);
 }
 
-/* The level line of Alg. 1: l = floor(-ln(unif(0..1)) * mL). */
+/* The level draw of Alg. 1: l = floor(-ln(unif(0..1)) * mL). */
 OR_EXPORT void or_levels(uint64_t seed, uint32_t n, double mL, uint8_t *out) {
     for (uint32_t i = 0; i < n; ++i) {
         uint64_t r = splitmix64(seed ^ (uint64_t)i) >> 11;

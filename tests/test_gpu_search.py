@@ -108,6 +108,35 @@ def test_parity_wide_gathers(hnsw, monkeypatch, dim):
     _run_parity(hnsw, G, X, Q, 10, 40)
 
 
+@pytest.mark.parametrize("ef", [10, 64])
+def test_parity_ties_and_duplicates(hnsw, ef):
+    """Integer grid coordinates: most distances tie, and many points are exact
+    duplicates of others; every decision falls to the id order of the key."""
+    _log(f"case ties and duplicates ef={ef}")
+    rng = np.random.default_rng(5)
+    X = rng.integers(0, 6, size=(3000, 4)).astype(np.float32)
+    Q = rng.integers(0, 6, size=(300, 4)).astype(np.float32)
+    G = oracle.Graph.build(X, M=8, efC=40, seed=11)
+    _run_parity(hnsw, G, X, Q, 10, ef)
+
+
+@pytest.mark.parametrize("seed", [1, 2, 3])
+def test_parity_random_graphs_with_ties(hnsw, seed):
+    """Arbitrary single-layer graphs (random out-lists of 1..16 links) on
+    points of a small integer grid, uploaded as they are: the search follows
+    the graph it is given, not one with HNSW's structure."""
+    _log(f"case random graph seed={seed}")
+    X, adj = synthdata.random_graph(2000, 16, seed, dim=3, tie_grid=5)
+    n = len(X)
+    packed = dict(metric=oracle.L2, M=8, Mmax=8, Mmax0=16, entry_point=0, max_level=0,
+                  levels=np.zeros(n, np.uint8), adj0=adj, upper_off=np.full(n, -1, np.int32),
+                  adjU=np.zeros((0, 8), np.uint32))
+    G = oracle.Graph.from_packed(X, packed)
+    Q = np.random.default_rng(seed).integers(0, 5, size=(200, 3)).astype(np.float32)
+    for ef in (5, 40):
+        _run_parity(hnsw, G, X, Q, 10, ef)
+
+
 def test_parity_inner_product(hnsw):
     _log("case glove_like 20k x 100 IP")
     X = synthdata.base("glove_like", 20000)

@@ -92,27 +92,49 @@ __device__ __forceinline__ int rank_in(uint64_t mask) {
                                      __builtin_amdgcn_mbcnt_lo(static_cast<uint32_t>(mask), 0));
 }
 
-// Wave-wide minima.  Every lane ends with the same value; it is returned
-// through a scalar register so the compiler knows it is wave-uniform (loop
-// exits that depend on it then stay uniform control flow).
-__device__ __forceinline__ uint64_t wave_min_u64(uint64_t v) {
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) {
-        const uint64_t w = __shfl_xor(v, o, 64);
-        v = w < v ? w : v;
-    }
-    const uint32_t lo = __builtin_amdgcn_readfirstlane(static_cast<uint32_t>(v));
-    const uint32_t hi = __builtin_amdgcn_readfirstlane(static_cast<uint32_t>(v >> 32));
+// Wave-wide minima.  Four DPP steps leave every lane with the minimum of its
+// row of 16 (xor-1 and xor-2 swaps inside a quad, then the mirrored half-row
+// and the mirrored row); the four row minima are then read into scalar
+// registers, so the result is wave-uniform and known to the compiler as such
+// (loop exits that depend on it stay uniform control flow).  No LDS traffic.
+template <int CTRL>
+__device__ __forceinline__ uint32_t dpp_u32(uint32_t v) {
+    return static_cast<uint32_t>(__builtin_amdgcn_update_dpp(0, static_cast<int>(v), CTRL, 0xF, 0xF, true));
+}
+
+template <int CTRL>
+__device__ __forceinline__ uint64_t dpp_u64(uint64_t v) {
+    const uint32_t lo = dpp_u32<CTRL>(static_cast<uint32_t>(v)), hi = dpp_u32<CTRL>(static_cast<uint32_t>(v >> 32));
     return (static_cast<uint64_t>(hi) << 32) | lo;
 }
 
-__device__ __forceinline__ int wave_min_int(int v) {
+__device__ __forceinline__ uint64_t wave_min_u64(uint64_t v) {
+    uint64_t w;
+    w = dpp_u64<0xB1>(v);   // quad_perm [1,0,3,2]
+    v = w < v ? w : v;
+    w = dpp_u64<0x4E>(v);   // quad_perm [2,3,0,1]
+    v = w < v ? w : v;
+    w = dpp_u64<0x141>(v);  // row_half_mirror
+    v = w < v ? w : v;
+    w = dpp_u64<0x140>(v);  // row_mirror
+    v = w < v ? w : v;
+    uint64_t m = readlane64(v, 0);
 #pragma unroll
-    for (int o = 32; o > 0; o >>= 1) {
-        const int w = __shfl_xor(v, o, 64);
-        v = w < v ? w : v;
+    for (int r = 16; r < 64; r += 16) {
+        const uint64_t x = readlane64(v, r);
+        m = x < m ? x : m;
     }
-    return __builtin_amdgcn_readfirstlane(v);
+    return m;
+}
+
+__device__ __forceinline__ int wave_min_int(int v) {
+    v = min(v, static_cast<int>(dpp_u32<0xB1>(static_cast<uint32_t>(v))));
+    v = min(v, static_cast<int>(dpp_u32<0x4E>(static_cast<uint32_t>(v))));
+    v = min(v, static_cast<int>(dpp_u32<0x141>(static_cast<uint32_t>(v))));
+    v = min(v, static_cast<int>(dpp_u32<0x140>(static_cast<uint32_t>(v))));
+    const int a = min(__builtin_amdgcn_readlane(v, 0), __builtin_amdgcn_readlane(v, 16));
+    const int b = min(__builtin_amdgcn_readlane(v, 32), __builtin_amdgcn_readlane(v, 48));
+    return min(a, b);
 }
 
 // Test-and-set of `id` in the visited table; true when the id was not seen.
@@ -384,6 +406,42 @@ __device__ __forceinline__ WaveLds carve(uint8_t *base, const SearchArgs &a) {
 __device__ __forceinline__ int merge_into_w(const WaveLds &s, int m, uint32_t ef, uint32_t &wsize) {
     const int lane = lane_id();
     const int ws = static_cast<int>(wsize);
+    if (ws <= 64) {
+        // W fits one chunk: lane i holds W[i] in registers (read together with
+        // the new keys), the threshold W[ef-1] comes from a lane of it, and one
+        // pass over the admitted keys yields every count: the W entries below
+        // each key (scalar, from a ballot), whether W already holds it, the
+        // admitted keys below each W entry and below each admitted key.
+        const uint64_t wf = lane < ws ? s.W[lane] : ~0ull;
+        const uint64_t a = lane < m ? s.keys[lane] : ~0ull;
+        const uint64_t wk = lane < ws ? (wf >> 1) : ~0ull;
+        const uint64_t thr = wsize < ef ? ~0ull : readlane64(wf, static_cast<int>(ef) - 1);
+        uint64_t cm = __ballot(lane < m && a < thr);
+        if (cm == 0) return INT_MAX;
+        uint64_t km = 0;
+        int lbmin = INT_MAX, lb = 0, r = 0, shift = 0;
+        while (cm) {
+            const int t = __ffsll(static_cast<unsigned long long>(cm)) - 1;
+            cm &= cm - 1;
+            const uint64_t at = readlane64(a, t);
+            if (__ballot(wk == (at >> 1))) continue;  // (distance, id) already in W
+            const int below = __popcll(__ballot(wk < (at >> 1)));
+            km |= 1ull << t;
+            lbmin = min(lbmin, below);
+            lb = lane == t ? below : lb;
+            shift += at < wf;
+            r += (at < a) || (at == a && t < lane);
+        }
+        if (km == 0) return INT_MAX;
+        const bool keep = (km >> lane) & 1ull;
+        const int np = lane + shift;
+        wave_sync();
+        if (lane < ws && lane >= lbmin && np < static_cast<int>(ef)) s.W[np] = wf;
+        if (keep && lb + r < static_cast<int>(ef)) s.W[lb + r] = a;
+        wave_sync();
+        wsize = min(ef, wsize + static_cast<uint32_t>(__popcll(km)));
+        return lbmin;
+    }
     const uint64_t thr = wsize < ef ? ~0ull : s.W[ef - 1];
     const uint64_t a = lane < m ? s.keys[lane] : ~0ull;
     const bool cand = lane < m && a < thr;

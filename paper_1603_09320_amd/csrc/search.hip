@@ -1,8 +1,13 @@
 // Batched K-NN-SEARCH (Alg. 5 of arXiv:1603.09320) for gfx950: one workgroup
 // of one wavefront per query; the search itself is search_one in
-// search_device.h.  This unit holds the buffered-gather kernels (stores of at
-// most 2 GiB); search_wide.hip holds those for larger stores.
+// search_device.h (or, for batches larger than the chip holds at once, its
+// descent and layer-0 parts as separate launches with the queries reordered
+// between them, see search_kernels.h).  This unit holds the buffered-gather
+// kernels (stores of at most 2 GiB); search_wide.hip holds those for larger
+// stores.
 #include <stdlib.h>
+
+#include <mutex>
 
 #include "search_kernels.h"
 
@@ -42,12 +47,80 @@ bool stores_buffered(const DevIndex &ix) {
     return fits(ix.vec, ix.stride4) && fits(ix.vbf16, ix.bf16_stride16) && fits(ix.vfp8, ix.fp8_stride16);
 }
 
+namespace {
+
+// Workspace of the scheduled launches, one per (device, stream): 20 bytes
+// per query (layer-0 entry key, the upper layers' counters, the order).  It
+// grows to the largest batch seen on that stream and is kept until the
+// process ends.  Launches on one stream run in order, so a buffer is reused
+// only after the previous batch's kernels have read it; the mutex is held
+// while a batch's kernels are enqueued, so that batches submitted to one
+// stream from several threads do not interleave their launches.
+struct SchedBuf {
+    int device;
+    hipStream_t stream;
+    uint8_t *p;
+    size_t cap;
+};
+std::mutex g_sched_mu;
+std::vector<SchedBuf> g_sched;
+
+uint8_t *sched_buffer(hipStream_t stream, size_t need) {
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return nullptr;
+    SchedBuf *b = nullptr;
+    for (SchedBuf &x : g_sched)
+        if (x.device == dev && x.stream == stream) b = &x;
+    if (!b) {
+        g_sched.push_back(SchedBuf{dev, stream, nullptr, 0});
+        b = &g_sched.back();
+    }
+    if (b->cap < need) {
+        if (b->p) device_free(b->p);
+        b->p = nullptr;
+        b->cap = 0;
+        size_t cap = 1u << 20;
+        while (cap < need) cap <<= 1;
+        void *p = nullptr;
+        if (hipMalloc(&p, cap) != hipSuccess) {
+            (void)hipGetLastError();
+            return nullptr;
+        }
+        b->p = static_cast<uint8_t *>(p);
+        b->cap = cap;
+    }
+    return b->p;
+}
+
+}  // namespace
+
 // HNSW_WIDE_GATHERS=1 sends every launch through the 64-bit addressed kernels
 // (they are otherwise taken only for stores above 2 GiB), so that tests can
-// check them on small indices.
-hipError_t launch_search(const DevIndex &ix, const SearchArgs &a, hipStream_t stream) {
+// check them on small indices.  HNSW_SCHEDULE=0 keeps every batch in one
+// kernel, HNSW_SCHEDULE=2 schedules every batch (both for tests); by default
+// a batch is scheduled when it holds more queries than waves resident at once.
+hipError_t launch_search(const DevIndex &ix, const SearchArgs &a0, hipStream_t stream) {
     const char *w = getenv("HNSW_WIDE_GATHERS");
     const bool force_wide = w && w[0] == '1';
+    const char *sv = getenv("HNSW_SCHEDULE");
+    SearchArgs a = a0;
+    a.sched = sv && sv[0] == '0' ? 0 : (sv && sv[0] == '2' ? 2 : 1);
+    a.sched_start = nullptr;
+    a.sched_up = nullptr;
+    a.sched_order = nullptr;
+    std::unique_lock<std::mutex> lk(g_sched_mu, std::defer_lock);
+    if (a.sched == 2 || (a.sched == 1 && a.nq > 256)) {
+        lk.lock();
+        const size_t n = a.nq;
+        uint8_t *p = sched_buffer(stream, n * 20);
+        if (p) {
+            a.sched_start = reinterpret_cast<uint64_t *>(p);
+            a.sched_up = reinterpret_cast<uint32_t *>(p + n * 8);
+            a.sched_order = reinterpret_cast<uint32_t *>(p + n * 16);
+        } else {
+            a.sched = 0;
+        }
+    }
     if (stores_buffered(ix) && !force_wide) return launch_search_stores<true>(ix, a, stream);
     return launch_search_wide(ix, a, stream);
 }

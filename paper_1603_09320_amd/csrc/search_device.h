@@ -717,31 +717,27 @@ __device__ __forceinline__ void sort_w(uint64_t *W, uint32_t n, uint32_t cap) {
         }
 }
 
-// One query, answered by the calling wave (Alg. 5).  `s` is the wave's LDS
-// workspace, sized for a.wpow2 and a.ht_log2; job.ef >= job.k.
-template <int G, int F, int METRIC, int KIND, bool LEARN, bool BUF>
-__device__ void search_one(const DevIndex &ix, const SearchArgs &a, const Job &job, const WaveLds &s) {
+// Where the greedy descent of one query ends (the layer-0 entry, with its
+// key) and the work it took.
+struct Descent {
+    uint64_t cur;
+    uint32_t n_dist, n_exp;
+};
+
+// The first part of K-NN-SEARCH (Alg. 5): the entry point's distance, then a
+// greedy walk (SEARCH-LAYER with ef = 1) through layers L..1.  Uses s.ids and
+// s.keys only.
+template <int G, int F, int METRIC, int KIND, bool BUF>
+__device__ Descent descend(const DevIndex &ix, const RowSource &src, const QueryRegs<G, F, KIND> &Q,
+                           const WaveLds &s) {
     const int lane = lane_id();
-    const RowSource src = rows_of(ix, a, KIND);
-    const float *qrow = job.q;
-
-    QueryRegs<G, F, KIND> Q;
-    load_query<G, F, KIND>(qrow, ix.dim, Q);
-
-    const uint32_t ht_slots = 1u << a.ht_log2;
-    for (uint32_t i = lane; i < ht_slots; i += 64) s.ht[i] = kNoLink;
-
-    uint32_t n_dist = 0, n_exp = 0, n_dist0 = 0, n_exp0 = 0;
-
-    // Entry point (Alg. 5): its distance seeds the descent.
+    Descent d{0ull, 0u, 0u};
     if (lane == 0) s.ids[0] = ix.entry;
     wave_sync();
     score_ids<G, F, METRIC, KIND, BUF>(ix, src, Q, s.ids, 1, s.keys);
     wave_sync();
     uint64_t cur = s.keys[0];
-    n_dist += 1;
-
-    // Greedy descent through layers L..1 (SEARCH-LAYER with ef = 1).
+    d.n_dist = 1;
     for (int lc = static_cast<int>(ix.max_level); lc >= 1; --lc) {
         for (;;) {
             const uint32_t cid = key_id(cur);
@@ -758,13 +754,31 @@ __device__ void search_one(const DevIndex &ix, const SearchArgs &a, const Job &j
             uint64_t best = cur;
             for (int i = lane; i < m; i += 64) best = s.keys[i] < best ? s.keys[i] : best;
             best = wave_min_u64(best);
-            n_dist += m;
-            n_exp += 1;
+            d.n_dist += m;
+            d.n_exp += 1;
             wave_sync();
             if (best == cur) break;
             cur = best;
         }
     }
+    d.cur = cur;
+    return d;
+}
+
+// The rest of K-NN-SEARCH (Alg. 5) from the descent's result: SEARCH-LAYER on
+// layer 0 with ef (Alg. 2), the exact rerank of low-precision traversals, and
+// the K nearest of W written to the job's outputs.  `s` is the wave's LDS
+// workspace, sized for a.wpow2 and a.ht_log2; job.ef >= job.k.
+template <int G, int F, int METRIC, int KIND, bool LEARN, bool BUF>
+__device__ void search_layer0(const DevIndex &ix, const SearchArgs &a, const Job &job, const WaveLds &s,
+                              const RowSource &src, const QueryRegs<G, F, KIND> &Q, const Descent &dsc) {
+    const int lane = lane_id();
+    const float *qrow = job.q;
+    const uint32_t ht_slots = 1u << a.ht_log2;
+    for (uint32_t i = lane; i < ht_slots; i += 64) s.ht[i] = kNoLink;
+    const uint64_t cur = dsc.cur;
+    const uint32_t n_dist = dsc.n_dist, n_exp = dsc.n_exp;
+    uint32_t n_dist0 = 0, n_exp0 = 0;
 
     // SEARCH-LAYER on layer 0 with ef candidates, starting from the descent's result.
     uint32_t ef = job.ef;
@@ -855,6 +869,16 @@ __device__ void search_one(const DevIndex &ix, const SearchArgs &a, const Job &j
         c4[2] = n_dist0;
         c4[3] = n_exp0;
     }
+}
+
+// One query, answered by the calling wave (Alg. 5): descent, then layer 0.
+template <int G, int F, int METRIC, int KIND, bool LEARN, bool BUF>
+__device__ void search_one(const DevIndex &ix, const SearchArgs &a, const Job &job, const WaveLds &s) {
+    const RowSource src = rows_of(ix, a, KIND);
+    QueryRegs<G, F, KIND> Q;
+    load_query<G, F, KIND>(job.q, ix.dim, Q);
+    const Descent d = descend<G, F, METRIC, KIND, BUF>(ix, src, Q, s);
+    search_layer0<G, F, METRIC, KIND, LEARN, BUF>(ix, a, job, s, src, Q, d);
 }
 
 

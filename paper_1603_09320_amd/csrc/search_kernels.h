@@ -10,11 +10,7 @@ namespace hnsw {
 namespace {
 
 
-template <int G, int F, int METRIC, int KIND, bool LEARN, bool BUF>
-__device__ __forceinline__ void search_query(const DevIndex &ix, const SearchArgs &a) {
-    extern __shared__ __align__(16) uint8_t smem[];
-    const uint32_t qi = blockIdx.x;
-    if (qi >= a.nq) return;
+__device__ __forceinline__ Job job_of(const DevIndex &ix, const SearchArgs &a, uint32_t qi, bool learn) {
     Job job;
     job.q = a.queries + static_cast<size_t>(qi) * ix.dim;
     job.k = a.k;
@@ -22,9 +18,17 @@ __device__ __forceinline__ void search_query(const DevIndex &ix, const SearchArg
     job.ids = a.ids + static_cast<size_t>(qi) * a.k;
     job.dists = a.dists + static_cast<size_t>(qi) * a.k;
     job.counters = a.counters ? a.counters + static_cast<size_t>(qi) * 4 : nullptr;
-    job.trace = LEARN && a.ckpt_trace ? a.ckpt_trace + static_cast<size_t>(qi) * a.mlp.max_ckpt * (kMlpIn + 2)
+    job.trace = learn && a.ckpt_trace ? a.ckpt_trace + static_cast<size_t>(qi) * a.mlp.max_ckpt * (kMlpIn + 2)
                                       : nullptr;
-    search_one<G, F, METRIC, KIND, LEARN, BUF>(ix, a, job, carve<LEARN>(smem, a));
+    return job;
+}
+
+template <int G, int F, int METRIC, int KIND, bool LEARN, bool BUF>
+__device__ __forceinline__ void search_query(const DevIndex &ix, const SearchArgs &a) {
+    extern __shared__ __align__(16) uint8_t smem[];
+    const uint32_t qi = blockIdx.x;
+    if (qi >= a.nq) return;
+    search_one<G, F, METRIC, KIND, LEARN, BUF>(ix, a, job_of(ix, a, qi, LEARN), carve<LEARN>(smem, a));
 }
 
 // Waves per SIMD the register allocation is held to: six for the fp32 and
@@ -43,23 +47,158 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(6))) void se
     search_query<G, F, METRIC, kF32, true, BUF>(ix, a);
 }
 
+// ------------------------------------------------ scheduled launches
+//
+// A batch larger than the waves the chip holds at once finishes when its
+// slowest queries do, and a query started late that needs many layer-0
+// expansions decides the end.  The scheduled form runs every query's descent
+// first (descent_kernel), then starts the layer-0 searches of the quarter of
+// queries whose descent ended farthest from them (their layer-0 searches tend
+// to be the longest) before the others (order_kernel, layer0_kernel).  Each
+// query's arithmetic is that of the one-kernel path; only the order in which
+// queries occupy the chip changes.
+
+template <int G, int F, int METRIC, int KIND, bool BUF>
+__global__ __launch_bounds__(64) void descent_kernel(DevIndex ix, SearchArgs a) {
+    __shared__ uint64_t keys[64];
+    __shared__ uint32_t ids[64];
+    const uint32_t qi = blockIdx.x;
+    if (qi >= a.nq) return;
+    WaveLds s{};
+    s.keys = keys;
+    s.ids = ids;
+    const RowSource src = rows_of(ix, a, KIND);
+    QueryRegs<G, F, KIND> Q;
+    load_query<G, F, KIND>(a.queries + static_cast<size_t>(qi) * ix.dim, ix.dim, Q);
+    const Descent d = descend<G, F, METRIC, KIND, BUF>(ix, src, Q, s);
+    if (lane_id() == 0) {
+        a.sched_start[qi] = d.cur;
+        a.sched_up[2 * static_cast<size_t>(qi)] = d.n_dist;
+        a.sched_up[2 * static_cast<size_t>(qi) + 1] = d.n_exp;
+    }
+}
+
+// One workgroup of 1024 threads.  The threshold is the distance ranked at a
+// quarter of a sample of at most 4096 descents (every nq/ns-th query,
+// bitonic-sorted in LDS, largest first); queries at or above it go first, in
+// batch order, then the others, in batch order (a stable partition: each
+// thread takes a contiguous chunk, and the chunks' counts are scanned).
+constexpr uint32_t kOrderThreads = 1024, kOrderSample = 4096;
+
+__global__ __launch_bounds__(1024) void order_kernel(const uint64_t *start, uint32_t nq, uint32_t *order) {
+    __shared__ uint32_t samp[kOrderSample];
+    __shared__ uint32_t cnt[kOrderThreads];
+    const uint32_t t = threadIdx.x;
+    const uint32_t ns = nq < kOrderSample ? nq : kOrderSample;
+    for (uint32_t i = t; i < kOrderSample; i += kOrderThreads)
+        samp[i] = i < ns ? static_cast<uint32_t>(start[static_cast<uint64_t>(i) * nq / ns] >> 32) : 0u;
+    __syncthreads();
+    for (uint32_t k = 2; k <= kOrderSample; k <<= 1)
+        for (uint32_t j = k >> 1; j > 0; j >>= 1) {
+            for (uint32_t p = t; p < kOrderSample / 2; p += kOrderThreads) {
+                const uint32_t i = 2 * j * (p / j) + (p % j), l = i + j;
+                const bool down = (i & k) == 0;  // largest first
+                const uint32_t x = samp[i], y = samp[l];
+                if ((x < y) == down) {
+                    samp[i] = y;
+                    samp[l] = x;
+                }
+            }
+            __syncthreads();
+        }
+    const uint32_t thr = samp[ns / 4];
+    const uint32_t chunk = (nq + kOrderThreads - 1) / kOrderThreads;
+    const uint32_t lo = min(nq, t * chunk), hi = min(nq, lo + chunk);
+    uint32_t c = 0;
+    for (uint32_t q = lo; q < hi; ++q) c += static_cast<uint32_t>(start[q] >> 32) >= thr;
+    cnt[t] = c;
+    __syncthreads();
+    // inclusive scan of the counts (Hillis-Steele, in place with a barrier
+    // between the read and the write of each step)
+    for (uint32_t o = 1; o < kOrderThreads; o <<= 1) {
+        const uint32_t v = t >= o ? cnt[t - o] : 0u;
+        __syncthreads();
+        cnt[t] += v;
+        __syncthreads();
+    }
+    const uint32_t total = cnt[kOrderThreads - 1];
+    uint32_t front = cnt[t] - c;          // flagged queries before this chunk
+    uint32_t back = total + (lo - front); // then the others before this chunk
+    for (uint32_t q = lo; q < hi; ++q) {
+        if (static_cast<uint32_t>(start[q] >> 32) >= thr)
+            order[front++] = q;
+        else
+            order[back++] = q;
+    }
+}
+
+template <int G, int F, int METRIC, int KIND, bool LEARN, bool BUF>
+__device__ __forceinline__ void layer0_query(const DevIndex &ix, const SearchArgs &a) {
+    extern __shared__ __align__(16) uint8_t smem[];
+    if (blockIdx.x >= a.nq) return;
+    const uint32_t qi = __builtin_amdgcn_readfirstlane(a.sched_order[blockIdx.x]);
+    const Job job = job_of(ix, a, qi, LEARN);
+    const RowSource src = rows_of(ix, a, KIND);
+    QueryRegs<G, F, KIND> Q;
+    load_query<G, F, KIND>(job.q, ix.dim, Q);
+    const uint64_t cur = a.sched_start[qi];
+    Descent d;
+    d.cur = (static_cast<uint64_t>(__builtin_amdgcn_readfirstlane(static_cast<uint32_t>(cur >> 32))) << 32) |
+            __builtin_amdgcn_readfirstlane(static_cast<uint32_t>(cur));
+    d.n_dist = __builtin_amdgcn_readfirstlane(a.sched_up[2 * static_cast<size_t>(qi)]);
+    d.n_exp = __builtin_amdgcn_readfirstlane(a.sched_up[2 * static_cast<size_t>(qi) + 1]);
+    search_layer0<G, F, METRIC, KIND, LEARN, BUF>(ix, a, job, carve<LEARN>(smem, a), src, Q, d);
+}
+
+template <int G, int F, int METRIC, int KIND, bool BUF>
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(KIND == kFP8 ? 5 : 6))) void layer0_kernel(
+    DevIndex ix, SearchArgs a) {
+    layer0_query<G, F, METRIC, KIND, false, BUF>(ix, a);
+}
+
+template <int G, int F, int METRIC, bool BUF>
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(6))) void layer0_kernel_learned(DevIndex ix,
+                                                                                                    SearchArgs a) {
+    layer0_query<G, F, METRIC, kF32, true, BUF>(ix, a);
+}
+
+// One metric: the one-kernel launch, or (a.sched and a batch above what the
+// chip holds at once) the scheduled three.
+template <int G, int F, int METRIC, int KIND, bool BUF>
+hipError_t launch_gfkm(const DevIndex &ix, const SearchArgs &a, hipStream_t stream) {
+    const bool learned = KIND == kF32 && a.mode == HNSW_MODE_LEARNED;
+    const size_t lds = search_lds_bytes(a, learned);
+    const void *fused = learned ? reinterpret_cast<const void *>(&search_kernel_learned<G, F, METRIC, BUF>)
+                                : reinterpret_cast<const void *>(&search_kernel<G, F, METRIC, KIND, BUF>);
+    bool sched = a.sched_order && a.sched == 2;
+    if (a.sched_order && a.sched == 1) {
+        int per_cu = 0, dev = 0, cus = 0;
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fused, 64, lds) == hipSuccess &&
+            hipGetDevice(&dev) == hipSuccess &&
+            hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess)
+            sched = static_cast<uint64_t>(a.nq) > static_cast<uint64_t>(per_cu) * static_cast<uint64_t>(cus);
+        (void)hipGetLastError();
+    }
+    if (!sched) {
+        if (learned)
+            hipLaunchKernelGGL((search_kernel_learned<G, F, METRIC, BUF>), dim3(a.nq), dim3(64), lds, stream, ix, a);
+        else
+            hipLaunchKernelGGL((search_kernel<G, F, METRIC, KIND, BUF>), dim3(a.nq), dim3(64), lds, stream, ix, a);
+        return hipGetLastError();
+    }
+    hipLaunchKernelGGL((descent_kernel<G, F, METRIC, KIND, BUF>), dim3(a.nq), dim3(64), 0, stream, ix, a);
+    hipLaunchKernelGGL(order_kernel, dim3(1), dim3(kOrderThreads), 0, stream, a.sched_start, a.nq, a.sched_order);
+    if (learned)
+        hipLaunchKernelGGL((layer0_kernel_learned<G, F, METRIC, BUF>), dim3(a.nq), dim3(64), lds, stream, ix, a);
+    else
+        hipLaunchKernelGGL((layer0_kernel<G, F, METRIC, KIND, BUF>), dim3(a.nq), dim3(64), lds, stream, ix, a);
+    return hipGetLastError();
+}
+
 template <int G, int F, int KIND, bool BUF>
 hipError_t launch_gfk(const DevIndex &ix, const SearchArgs &a, hipStream_t stream) {
-    const size_t lds = search_lds_bytes(a, KIND == kF32 && a.mode == HNSW_MODE_LEARNED);
-    if constexpr (KIND == kF32) {
-        if (a.mode == HNSW_MODE_LEARNED) {
-            if (ix.metric == HNSW_IP)
-                hipLaunchKernelGGL((search_kernel_learned<G, F, HNSW_IP, BUF>), dim3(a.nq), dim3(64), lds, stream, ix, a);
-            else
-                hipLaunchKernelGGL((search_kernel_learned<G, F, HNSW_L2SQ, BUF>), dim3(a.nq), dim3(64), lds, stream, ix, a);
-            return hipGetLastError();
-        }
-    }
-    if (ix.metric == HNSW_IP)
-        hipLaunchKernelGGL((search_kernel<G, F, HNSW_IP, KIND, BUF>), dim3(a.nq), dim3(64), lds, stream, ix, a);
-    else
-        hipLaunchKernelGGL((search_kernel<G, F, HNSW_L2SQ, KIND, BUF>), dim3(a.nq), dim3(64), lds, stream, ix, a);
-    return hipGetLastError();
+    if (ix.metric == HNSW_IP) return launch_gfkm<G, F, HNSW_IP, KIND, BUF>(ix, a, stream);
+    return launch_gfkm<G, F, HNSW_L2SQ, KIND, BUF>(ix, a, stream);
 }
 
 template <int KIND, bool BUF>

@@ -100,11 +100,14 @@ def test_checkpoint_features_and_outputs_equal_oracle(hnsw, workload, metric, n)
         assert np.array_equal(tr[i, :k, 24:], out), i
 
 
-@pytest.mark.parametrize("workload,metric,n,dim_ef", [("uniform16", oracle.L2, 10000, 200),
-                                                      ("glove_like", oracle.IP, 20000, 256),
-                                                      ("sift_like", oracle.L2, 20000, 128)])
-def test_learned_search_parity(hnsw, workload, metric, n, dim_ef):
-    print(f"case learned parity {workload} n={n}", flush=True)
+@pytest.mark.parametrize("workload,metric,n,dim_ef,sched", [("uniform16", oracle.L2, 10000, 200, "1"),
+                                                            ("glove_like", oracle.IP, 20000, 256, "1"),
+                                                            ("sift_like", oracle.L2, 20000, 128, "1"),
+                                                            ("sift_like", oracle.L2, 20000, 128, "2")])
+def test_learned_search_parity(hnsw, monkeypatch, workload, metric, n, dim_ef, sched):
+    """sched "2" forces the scheduled form (descents first, layer 0 reordered)."""
+    print(f"case learned parity {workload} n={n} sched={sched}", flush=True)
+    monkeypatch.setenv("HNSW_SCHEDULE", sched)
     X = synthdata.base(workload, n)
     Q = synthdata.queries(workload, 400)
     G = oracle.Graph.build(X, metric=metric, M=16, efC=100, seed=7)

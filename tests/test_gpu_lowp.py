@@ -126,3 +126,16 @@ def test_lowp_requires_copy(hnsw):
     with pytest.raises(hnsw.HnswError) as e:
         idx.search(torch.from_numpy(X[:3]).cuda(), 5, 10, mode=hnsw.MODE_FP8)
     assert e.value.code == 1
+
+
+@pytest.mark.parametrize("kind", [1, 2])
+def test_lowp_parity_scheduled(hnsw, monkeypatch, kind):
+    """Low-precision traversal and re-rank in the scheduled form (descents
+    first, layer 0 reordered), forced on a small batch."""
+    print(f"case lowp scheduled kind={kind}", flush=True)
+    monkeypatch.setenv("HNSW_SCHEDULE", "2")
+    X = synthdata.base("deep_like", 6000)
+    Q = synthdata.queries("deep_like", 700)
+    G = oracle.Graph.build(X, M=16, efC=60, seed=4005)
+    for ef in (10, 64):
+        _lowp_parity(hnsw, X, Q, G, 10, ef, kind, oracle.L2)

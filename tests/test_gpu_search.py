@@ -108,6 +108,38 @@ def test_parity_wide_gathers(hnsw, monkeypatch, dim):
     _run_parity(hnsw, G, X, Q, 10, 40)
 
 
+@pytest.mark.parametrize("K,ef", [(10, 50), (1, 1), (64, 200), (200, 1024)])
+def test_parity_scheduled_launches(hnsw, cfg0, monkeypatch, K, ef):
+    """The scheduled form (every descent first, then layer 0 with the queries
+    reordered), forced on a small batch: the oracle's results and counters,
+    and the one-kernel path's outputs bit for bit."""
+    _log(f"case scheduled launches K={K} ef={ef}")
+    X, Q, G = cfg0
+    monkeypatch.setenv("HNSW_SCHEDULE", "2")
+    ids, ds, cnt, _ = _run_parity(hnsw, G, X, Q, K, ef)
+    monkeypatch.setenv("HNSW_SCHEDULE", "0")
+    idx = _index(hnsw, G, X)
+    i1, d1, c1 = idx.search(torch.from_numpy(Q).cuda(), K, ef, counters=True)
+    torch.cuda.synchronize()
+    assert np.array_equal(ids, i1.cpu().numpy()) and np.array_equal(ds, d1.cpu().numpy())
+    assert np.array_equal(cnt, c1.cpu().numpy().astype(np.uint32))
+
+
+@pytest.mark.parametrize("nq", [1, 2, 257, 4097])
+def test_scheduled_batch_sizes_and_wide_ip(hnsw, monkeypatch, nq):
+    """Scheduled launches at batch sizes around the order kernel's sample
+    (4096) and one-query batches, inner product, through the 64-bit
+    addressed kernels."""
+    _log(f"case scheduled nq={nq} IP wide")
+    monkeypatch.setenv("HNSW_SCHEDULE", "2")
+    monkeypatch.setenv("HNSW_WIDE_GATHERS", "1")
+    rng = np.random.default_rng(nq)
+    X = rng.normal(size=(4000, 24)).astype(np.float32)
+    Q = rng.normal(size=(nq, 24)).astype(np.float32)
+    G = oracle.Graph.build(X, metric=oracle.IP, M=8, efC=40, seed=5)
+    _run_parity(hnsw, G, X, Q, 10, 32, metric=oracle.IP)
+
+
 @pytest.mark.parametrize("ef", [10, 64])
 def test_parity_ties_and_duplicates(hnsw, ef):
     """Integer grid coordinates: most distances tie, and many points are exact

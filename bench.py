@@ -3,7 +3,11 @@
 Workload (default): the 1M x 128 SIFT-like Gaussian mixture (1,000 centres,
 sigma 20, integer coordinates 0..255), graph built by the oracle's INSERT
 with M = 16, Mmax0 = 32, efConstruction = 200; 10,000 seeded queries, K = 10.
-A step is one batched search of all 10,000 queries (one kernel launch).
+A step is one batched search call over all 10,000 queries.  A batch larger
+than the waves resident at once runs as three launches on one stream
+(descent_kernel, order_kernel, layer0_kernel: every descent first, then
+layer 0 with the queries whose descent ended farthest started first); the
+HIP events bracket the whole call.
 
 For every form of the search (plain fp32 traversal, BF16 and FP8-E4M3
 traversal with an exact fp32 re-rank, and the learned early-termination
@@ -88,7 +92,7 @@ def algorithmic_bytes(cnt, graph, K, mode, ef):
 
 def load_traffic(kernel_hash: str, workload: str, ef: int):
     """HBM bytes per launch measured by rocprofv3 counters, if taken on this exact kernel."""
-    p = os.path.join(ROOT, "profiles", f"search_kernel_{workload}_traffic.json")
+    p = os.path.join(ROOT, "profiles", f"search_{workload}_traffic.json")
     if not os.path.exists(p):
         return None
     try:
@@ -349,6 +353,7 @@ def main():
                          "bytes_per_query": round(alg / nq, 1),
                          "dist_evals_per_query": round(float(c[:, 0].mean()), 2),
                          "expansions_per_query": round(float(c[:, 1].mean()), 2),
+                         "layer0_expansions_per_query": round(float(c[:, 3].mean()), 2),
                          "sweep": curve}
         log(f"[bench] {form}: {results[form]}")
 
@@ -396,7 +401,8 @@ def main():
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(achieved / HBM_PEAK_GBS, 4),
                      "traffic": load_traffic(khash, a.workload, head["ef"]),
-                     "kernel": "search_kernel", "kernel_ms": head["kernel_ms"],
+                     "kernel": "search call: descent_kernel + order_kernel + layer0_kernel (one stream, "
+                               "event-timed together)", "kernel_ms": head["kernel_ms"],
                      "algorithmic_bytes_per_launch": alg_launch, "kernel_hash": khash},
         "forms": results,
         "bruteforce": {"ms": round(bf_ms, 3), "queries": nq,

@@ -54,8 +54,8 @@ struct SearchArgs {
     int mode;              // hnsw_mode
     DevMlp mlp;            // learned stop rule (mode HNSW_MODE_LEARNED)
     float *ckpt_trace;     // learned mode: [nq][max_ckpt][26] features + outputs per checkpoint, or null
-    // Scheduled launches (descents first, then layer 0 in a chosen order):
-    // workspace of the batch, or null for the one-kernel path.
+    // Scheduled launches (descents first, then layer 0 in a chosen order, see
+    // search_kernels.h): workspace of the batch, or null for the one-kernel path.
     uint64_t *sched_start;   // [nq] key of each query's layer-0 entry
     uint32_t *sched_up;      // [nq][2] distance evaluations and expansions above layer 0
     uint32_t *sched_order;   // [nq] query of each layer-0 wave

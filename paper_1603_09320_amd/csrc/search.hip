@@ -104,7 +104,7 @@ hipError_t launch_search(const DevIndex &ix, const SearchArgs &a0, hipStream_t s
     const bool force_wide = w && w[0] == '1';
     const char *sv = getenv("HNSW_SCHEDULE");
     SearchArgs a = a0;
-    a.sched = sv && sv[0] == '0' ? 0 : (sv && sv[0] == '2' ? 2 : 1);
+    a.sched = !sv ? 1 : (sv[0] == '0' ? 0 : (sv[0] == '2' ? 2 : 1));
     a.sched_start = nullptr;
     a.sched_up = nullptr;
     a.sched_order = nullptr;

@@ -78,25 +78,30 @@ __global__ __launch_bounds__(64) void descent_kernel(DevIndex ix, SearchArgs a) 
     }
 }
 
-// One workgroup of 1024 threads.  The threshold is the distance ranked at a
-// quarter of a sample of at most 4096 descents (every nq/ns-th query,
-// bitonic-sorted in LDS, largest first); queries at or above it go first, in
-// batch order, then the others, in batch order (a stable partition: each
-// thread takes a contiguous chunk, and the chunks' counts are scanned).
-constexpr uint32_t kOrderThreads = 1024, kOrderSample = 4096;
+// One workgroup of 1024 threads (16 waves).  The threshold is the distance
+// ranked at a quarter of a sample of at most 1024 descents (every nq/ns-th
+// query, bitonic-sorted in LDS, largest first).  Queries at or above it go
+// first, in batch order, then the others, in batch order: a stable partition,
+// computed over rounds of 16 tiles of 1024 consecutive queries (thread t reads
+// query tile*1024 + t of each tile, so every load is coalesced and up to 16
+// are in flight per thread); a ballot per (tile, wave) counts the queries that
+// go first, an exclusive scan of those 256 counts gives each wave its base, and
+// a lane adds the flagged lanes below it.
+constexpr uint32_t kOrderThreads = 1024, kOrderSample = 1024, kOrderTiles = 16;
 
 __global__ __launch_bounds__(1024) void order_kernel(const uint64_t *start, uint32_t nq, uint32_t *order) {
     __shared__ uint32_t samp[kOrderSample];
-    __shared__ uint32_t cnt[kOrderThreads];
-    const uint32_t t = threadIdx.x;
+    __shared__ uint32_t cnt[kOrderTiles * 16];
+    __shared__ uint32_t total_s, round_s;
+    const uint32_t t = threadIdx.x, lane = t & 63u, wv = t >> 6;
     const uint32_t ns = nq < kOrderSample ? nq : kOrderSample;
-    for (uint32_t i = t; i < kOrderSample; i += kOrderThreads)
-        samp[i] = i < ns ? static_cast<uint32_t>(start[static_cast<uint64_t>(i) * nq / ns] >> 32) : 0u;
+    samp[t] = t < ns ? static_cast<uint32_t>(start[static_cast<uint64_t>(t) * nq / ns] >> 32) : 0u;
+    if (t == 0) total_s = 0u;
     __syncthreads();
     for (uint32_t k = 2; k <= kOrderSample; k <<= 1)
         for (uint32_t j = k >> 1; j > 0; j >>= 1) {
-            for (uint32_t p = t; p < kOrderSample / 2; p += kOrderThreads) {
-                const uint32_t i = 2 * j * (p / j) + (p % j), l = i + j;
+            if (t < kOrderSample / 2) {
+                const uint32_t i = 2 * j * (t / j) + (t % j), l = i + j;
                 const bool down = (i & k) == 0;  // largest first
                 const uint32_t x = samp[i], y = samp[l];
                 if ((x < y) == down) {
@@ -107,28 +112,66 @@ __global__ __launch_bounds__(1024) void order_kernel(const uint64_t *start, uint
             __syncthreads();
         }
     const uint32_t thr = samp[ns / 4];
-    const uint32_t chunk = (nq + kOrderThreads - 1) / kOrderThreads;
-    const uint32_t lo = min(nq, t * chunk), hi = min(nq, lo + chunk);
-    uint32_t c = 0;
-    for (uint32_t q = lo; q < hi; ++q) c += static_cast<uint32_t>(start[q] >> 32) >= thr;
-    cnt[t] = c;
+    // Bit i of the result: query r0 + i*1024 + t exists and goes first.  The
+    // loads read a clamped index unconditionally, so all 16 are in flight
+    // before the first comparison.
+    auto flags = [&](uint32_t r0) {
+        const uint32_t *dist_bits = reinterpret_cast<const uint32_t *>(start) + 1;  // high word of each key
+        uint32_t hi[kOrderTiles];
+#pragma unroll
+        for (uint32_t i = 0; i < kOrderTiles; ++i) hi[i] = dist_bits[2 * min(r0 + i * kOrderThreads + t, nq - 1u)];
+        uint32_t fb = 0;
+#pragma unroll
+        for (uint32_t i = 0; i < kOrderTiles; ++i)
+            fb |= static_cast<uint32_t>(r0 + i * kOrderThreads + t < nq && hi[i] >= thr) << i;
+        return fb;
+    };
+    // the number of queries that go first (the others start after them)
+    uint32_t mine = 0;
+    for (uint32_t r0 = 0; r0 < nq; r0 += kOrderTiles * kOrderThreads) mine += __popc(flags(r0));
+    atomicAdd(&total_s, mine);
     __syncthreads();
-    // inclusive scan of the counts (Hillis-Steele, in place with a barrier
-    // between the read and the write of each step)
-    for (uint32_t o = 1; o < kOrderThreads; o <<= 1) {
-        const uint32_t v = t >= o ? cnt[t - o] : 0u;
+    const uint32_t total = total_s;
+    uint32_t fbase = 0;  // queries that go first among those before this round
+    for (uint32_t r0 = 0; r0 < nq; r0 += kOrderTiles * kOrderThreads) {
+        const uint32_t fb = flags(r0);
+#pragma unroll
+        for (uint32_t i = 0; i < kOrderTiles; ++i) {
+            const uint64_t bm = __ballot((fb >> i) & 1u);
+            if (lane == 0) cnt[i * 16 + wv] = static_cast<uint32_t>(__popcll(bm));
+        }
         __syncthreads();
-        cnt[t] += v;
+        if (wv == 0) {
+            // exclusive scan of cnt[0..256) in (tile, wave) order: 4 per lane
+            uint32_t v[4], run = 0;
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                v[e] = run;
+                run += cnt[4 * lane + e];
+            }
+            uint32_t incl = run;
+#pragma unroll
+            for (int o = 1; o < 64; o <<= 1) {
+                const uint32_t y = __shfl_up(incl, o, 64);
+                if (lane >= static_cast<uint32_t>(o)) incl += y;
+            }
+            const uint32_t excl = incl - run;
+#pragma unroll
+            for (int e = 0; e < 4; ++e) cnt[4 * lane + e] = excl + v[e];
+            if (lane == 63) round_s = incl;
+        }
         __syncthreads();
-    }
-    const uint32_t total = cnt[kOrderThreads - 1];
-    uint32_t front = cnt[t] - c;          // flagged queries before this chunk
-    uint32_t back = total + (lo - front); // then the others before this chunk
-    for (uint32_t q = lo; q < hi; ++q) {
-        if (static_cast<uint32_t>(start[q] >> 32) >= thr)
-            order[front++] = q;
-        else
-            order[back++] = q;
+#pragma unroll
+        for (uint32_t i = 0; i < kOrderTiles; ++i) {
+            const uint32_t q = r0 + i * kOrderThreads + t;
+            const bool f = (fb >> i) & 1u;
+            const uint64_t bm = __ballot(f);
+            const uint32_t below = static_cast<uint32_t>(__popcll(bm & ((1ull << lane) - 1ull)));
+            const uint32_t fr = fbase + cnt[i * 16 + wv] + below;  // queries going first before q
+            if (q < nq) order[f ? fr : total + q - fr] = q;
+        }
+        fbase += round_s;
+        __syncthreads();  // cnt and round_s are rewritten by the next round
     }
 }
 
@@ -162,8 +205,9 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(6))) void la
     layer0_query<G, F, METRIC, kF32, true, BUF>(ix, a);
 }
 
-// One metric: the one-kernel launch, or (a.sched and a batch above what the
-// chip holds at once) the scheduled three.
+// One metric: the one-kernel launch or, for a batch larger than the waves of
+// the one-kernel form resident at once (a.sched 1) or always (a.sched 2), the
+// scheduled three.
 template <int G, int F, int METRIC, int KIND, bool BUF>
 hipError_t launch_gfkm(const DevIndex &ix, const SearchArgs &a, hipStream_t stream) {
     const bool learned = KIND == kF32 && a.mode == HNSW_MODE_LEARNED;

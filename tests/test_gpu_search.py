@@ -125,11 +125,11 @@ def test_parity_scheduled_launches(hnsw, cfg0, monkeypatch, K, ef):
     assert np.array_equal(cnt, c1.cpu().numpy().astype(np.uint32))
 
 
-@pytest.mark.parametrize("nq", [1, 2, 257, 4097])
+@pytest.mark.parametrize("nq", [1, 2, 3, 257, 4097, 20000])
 def test_scheduled_batch_sizes_and_wide_ip(hnsw, monkeypatch, nq):
-    """Scheduled launches at batch sizes around the order kernel's sample
-    (4096) and one-query batches, inner product, through the 64-bit
-    addressed kernels."""
+    """Scheduled launches: tiny batches, sizes around the order kernel's
+    1024-query tiles, and a batch spanning two of its 16,384-query rounds;
+    inner product, through the 64-bit addressed kernels."""
     _log(f"case scheduled nq={nq} IP wide")
     monkeypatch.setenv("HNSW_SCHEDULE", "2")
     monkeypatch.setenv("HNSW_WIDE_GATHERS", "1")

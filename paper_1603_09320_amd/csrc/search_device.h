@@ -137,17 +137,24 @@ __device__ __forceinline__ int wave_min_int(int v) {
     return min(a, b);
 }
 
-// Test-and-set of `id` in the visited table; true when the id was not seen.
-__device__ __forceinline__ bool visit(uint32_t *ht, uint32_t shift, uint32_t mask, uint32_t id) {
+// Test-and-set of `id` in the visited table.  Returns kSeen when the id was
+// already there, kInserted when this call put it there, and kForgot when all
+// kProbes slots were taken by other ids: the id is then treated as unseen
+// (scored again).  Slots are never cleared during a query, so an id that was
+// once forgotten is forgotten at every later test, and an id that is inserted
+// has never been scored before.
+constexpr int kSeen = 0, kInserted = 1, kForgot = 2;
+
+__device__ __forceinline__ int visit(uint32_t *ht, uint32_t shift, uint32_t mask, uint32_t id) {
     const uint32_t h = (id * 0x9E3779B1u) >> shift;
 #pragma unroll
     for (int p = 0; p < kProbes; ++p) {
         const uint32_t slot = (h + p) & mask;
         const uint32_t old = atomicCAS(&ht[slot], kNoLink, id);
-        if (old == kNoLink) return true;
-        if (old == id) return false;
+        if (old == kNoLink) return kInserted;
+        if (old == id) return kSeen;
     }
-    return true;  // run full: forget, score again
+    return kForgot;
 }
 
 // One DPP move of both halves of a double (gfx9 DPP controls, full rows and
@@ -403,7 +410,11 @@ __device__ __forceinline__ WaveLds carve(uint8_t *base, const SearchArgs &a) {
 // Positions come from wave-wide comparisons: for each admitted key (broadcast
 // with readlane) a ballot over each 64-entry chunk of W counts the smaller
 // entries and detects an equal one; no LDS access depends on another.
-__device__ __forceinline__ int merge_into_w(const WaveLds &s, int m, uint32_t ef, uint32_t &wsize) {
+// `forgot`: some id of this batch was forgotten by the visited table.  Only
+// then can a new key already be in W (the id was scored before without being
+// recorded) or equal another new key (the same id twice); otherwise both
+// checks are skipped.
+__device__ __forceinline__ int merge_into_w(const WaveLds &s, int m, uint32_t ef, uint32_t &wsize, bool forgot) {
     const int lane = lane_id();
     const int ws = static_cast<int>(wsize);
     if (ws <= 64) {
@@ -420,17 +431,34 @@ __device__ __forceinline__ int merge_into_w(const WaveLds &s, int m, uint32_t ef
         if (cm == 0) return INT_MAX;
         uint64_t km = 0;
         int lbmin = INT_MAX, lb = 0, r = 0, shift = 0;
-        while (cm) {
-            const int t = __ffsll(static_cast<unsigned long long>(cm)) - 1;
-            cm &= cm - 1;
-            const uint64_t at = readlane64(a, t);
-            if (__ballot(wk == (at >> 1))) continue;  // (distance, id) already in W
-            const int below = __popcll(__ballot(wk < (at >> 1)));
-            km |= 1ull << t;
-            lbmin = min(lbmin, below);
-            lb = lane == t ? below : lb;
-            shift += at < wf;
-            r += (at < a) || (at == a && t < lane);
+        if (!forgot) {
+            // every new key is distinct and absent from W: all are admitted
+            km = cm;
+            while (cm) {
+                const int t = __ffsll(static_cast<unsigned long long>(cm)) - 1;
+                cm &= cm - 1;
+                const uint64_t at = readlane64(a, t);
+                const int below = __popcll(__ballot(wk < (at >> 1)));
+                lbmin = min(lbmin, below);
+                // lane t takes `below`; with a scalar value the lane select
+                // must come from M0 (one scalar operand per vector instruction)
+                asm("s_mov_b32 m0, %2\n\ts_nop 0\n\tv_writelane_b32 %0, %1, m0" : "+v"(lb) : "s"(below), "s"(t) : "m0");
+                shift += at < wf;
+                r += at < a;
+            }
+        } else {
+            while (cm) {
+                const int t = __ffsll(static_cast<unsigned long long>(cm)) - 1;
+                cm &= cm - 1;
+                const uint64_t at = readlane64(a, t);
+                if (__ballot(wk == (at >> 1))) continue;  // (distance, id) already in W
+                const int below = __popcll(__ballot(wk < (at >> 1)));
+                km |= 1ull << t;
+                lbmin = min(lbmin, below);
+                lb = lane == t ? below : lb;
+                shift += at < wf;
+                r += (at < a) || (at == a && t < lane);
+            }
         }
         if (km == 0) return INT_MAX;
         const bool keep = (km >> lane) & 1ull;
@@ -458,7 +486,7 @@ __device__ __forceinline__ int merge_into_w(const WaveLds &s, int m, uint32_t ef
             mm &= mm - 1;
             const uint64_t at = readlane64(a, t) >> 1;
             const int below = __popcll(__ballot(w < at));
-            const bool eq = __ballot(w == at) != 0;
+            const bool eq = forgot && __ballot(w == at) != 0;
             if (lane == t) {
                 lb += below;
                 dup = dup || eq;
@@ -812,7 +840,9 @@ __device__ void search_layer0(const DevIndex &ix, const SearchArgs &a, const Job
         const uint32_t cid = key_id(ck);
         const uint32_t ld = ix.adj0[static_cast<size_t>(cid) * ix.Mmax0 + min(lane, static_cast<int>(ix.Mmax0) - 1)];
         const uint32_t e = lane < static_cast<int>(ix.Mmax0) ? ld : kNoLink;
-        const bool fresh = e != kNoLink && visit(s.ht, ht_shift, ht_mask, e);
+        const int vs = e != kNoLink ? visit(s.ht, ht_shift, ht_mask, e) : kSeen;
+        const bool fresh = vs != kSeen;
+        const bool forgot = __ballot(vs == kForgot) != 0;
         const uint64_t fm = __ballot(fresh);
         const int m = __popcll(fm);
         if (fresh) s.ids[rank_in(fm)] = e;
@@ -821,7 +851,7 @@ __device__ void search_layer0(const DevIndex &ix, const SearchArgs &a, const Job
         wave_sync();
         n_dist0 += m;
         n_exp0 += 1;
-        const int lbmin = merge_into_w(s, m, ef, wsize);
+        const int lbmin = merge_into_w(s, m, ef, wsize, forgot);
         if (lbmin < cursor) cursor = lbmin;
         if (LEARN && n_exp0 % a.mlp.period == 0 && lst.ckpt < a.mlp.max_ckpt &&
             learned_checkpoint(s, a.mlp, lst, n_exp0, job.k, cursor, ef, wsize, job.trace))

@@ -79,23 +79,34 @@ __global__ __launch_bounds__(64) void descent_kernel(DevIndex ix, SearchArgs a) 
 }
 
 // One workgroup of 1024 threads (16 waves).  The threshold is the distance
-// ranked at a quarter of a sample of at most 1024 descents (every nq/ns-th
+// ranked at a quarter of a sample of at most 512 descents (every nq/ns-th
 // query, bitonic-sorted in LDS, largest first).  Queries at or above it go
 // first, in batch order, then the others, in batch order: a stable partition,
 // computed over rounds of 16 tiles of 1024 consecutive queries (thread t reads
-// query tile*1024 + t of each tile, so every load is coalesced and up to 16
-// are in flight per thread); a ballot per (tile, wave) counts the queries that
-// go first, an exclusive scan of those 256 counts gives each wave its base, and
-// a lane adds the flagged lanes below it.
-constexpr uint32_t kOrderThreads = 1024, kOrderSample = 1024, kOrderTiles = 16;
+// query tile*1024 + t of each tile, so every load is coalesced and all 16 are
+// in flight together); a ballot per (tile, wave) counts the queries that go
+// first, an exclusive scan of those 256 counts gives each wave its base, and a
+// lane adds the flagged lanes below it.  A batch of one round keeps its flags
+// from the counting pass.
+constexpr uint32_t kOrderThreads = 1024, kOrderSample = 512, kOrderTiles = 16;
+
+__device__ __forceinline__ uint32_t wave_sum_u32(uint32_t v) {
+    v += dpp_u32<0xB1>(v);   // quad_perm [1,0,3,2]
+    v += dpp_u32<0x4E>(v);   // quad_perm [2,3,0,1]
+    v += dpp_u32<0x141>(v);  // row_half_mirror
+    v += dpp_u32<0x140>(v);  // row_mirror
+    return __builtin_amdgcn_readlane(v, 0) + __builtin_amdgcn_readlane(v, 16) + __builtin_amdgcn_readlane(v, 32) +
+           __builtin_amdgcn_readlane(v, 48);
+}
 
 __global__ __launch_bounds__(1024) void order_kernel(const uint64_t *start, uint32_t nq, uint32_t *order) {
     __shared__ uint32_t samp[kOrderSample];
     __shared__ uint32_t cnt[kOrderTiles * 16];
     __shared__ uint32_t total_s, round_s;
     const uint32_t t = threadIdx.x, lane = t & 63u, wv = t >> 6;
+    const uint32_t *dist_bits = reinterpret_cast<const uint32_t *>(start) + 1;  // high word of each key
     const uint32_t ns = nq < kOrderSample ? nq : kOrderSample;
-    samp[t] = t < ns ? static_cast<uint32_t>(start[static_cast<uint64_t>(t) * nq / ns] >> 32) : 0u;
+    if (t < kOrderSample) samp[t] = t < ns ? dist_bits[2 * (static_cast<uint64_t>(t) * nq / ns)] : 0u;
     if (t == 0) total_s = 0u;
     __syncthreads();
     for (uint32_t k = 2; k <= kOrderSample; k <<= 1)
@@ -116,7 +127,6 @@ __global__ __launch_bounds__(1024) void order_kernel(const uint64_t *start, uint
     // loads read a clamped index unconditionally, so all 16 are in flight
     // before the first comparison.
     auto flags = [&](uint32_t r0) {
-        const uint32_t *dist_bits = reinterpret_cast<const uint32_t *>(start) + 1;  // high word of each key
         uint32_t hi[kOrderTiles];
 #pragma unroll
         for (uint32_t i = 0; i < kOrderTiles; ++i) hi[i] = dist_bits[2 * min(r0 + i * kOrderThreads + t, nq - 1u)];
@@ -126,15 +136,18 @@ __global__ __launch_bounds__(1024) void order_kernel(const uint64_t *start, uint
             fb |= static_cast<uint32_t>(r0 + i * kOrderThreads + t < nq && hi[i] >= thr) << i;
         return fb;
     };
+    constexpr uint32_t kRound = kOrderTiles * kOrderThreads;
     // the number of queries that go first (the others start after them)
-    uint32_t mine = 0;
-    for (uint32_t r0 = 0; r0 < nq; r0 += kOrderTiles * kOrderThreads) mine += __popc(flags(r0));
-    atomicAdd(&total_s, mine);
+    const uint32_t fb0 = flags(0);
+    uint32_t mine = __popc(fb0);
+    for (uint32_t r0 = kRound; r0 < nq; r0 += kRound) mine += __popc(flags(r0));
+    mine = wave_sum_u32(mine);
+    if (lane == 0) atomicAdd(&total_s, mine);
     __syncthreads();
     const uint32_t total = total_s;
     uint32_t fbase = 0;  // queries that go first among those before this round
-    for (uint32_t r0 = 0; r0 < nq; r0 += kOrderTiles * kOrderThreads) {
-        const uint32_t fb = flags(r0);
+    for (uint32_t r0 = 0; r0 < nq; r0 += kRound) {
+        const uint32_t fb = r0 == 0 ? fb0 : flags(r0);
 #pragma unroll
         for (uint32_t i = 0; i < kOrderTiles; ++i) {
             const uint64_t bm = __ballot((fb >> i) & 1u);

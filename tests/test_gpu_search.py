@@ -140,6 +140,54 @@ def test_scheduled_batch_sizes_and_wide_ip(hnsw, monkeypatch, nq):
     _run_parity(hnsw, G, X, Q, 10, 32, metric=oracle.IP)
 
 
+def test_scheduled_concurrent_threads_and_streams(hnsw, cfg0, monkeypatch):
+    """Scheduled launches submitted by four host threads, two per stream: each
+    stream has its own workspace (grown while other batches run, by a 60,000-
+    query batch), and batches sharing a stream never interleave their three
+    launches.  Every result equals the serial one."""
+    import threading
+
+    _log("case scheduled launches from threads and streams")
+    monkeypatch.setenv("HNSW_SCHEDULE", "2")
+    X, Q, G = cfg0
+    idx = _index(hnsw, G, X)
+    q = torch.from_numpy(Q).cuda()
+    ref_i, ref_d = idx.search(q, 10, 50)
+    torch.cuda.synchronize()
+    ref_i, ref_d = ref_i.cpu().numpy(), ref_d.cpu().numpy()
+    big = q.repeat(60, 1).contiguous()
+    streams = [torch.cuda.Stream(), torch.cuda.Stream()]
+    results, errors = {}, []
+
+    def worker(j, stream):
+        try:
+            outs = []
+            for r in range(6):
+                qq = big if (j, r) in ((1, 2), (2, 3)) else q[:[1000, 300, 700][r % 3]]
+                with torch.cuda.stream(stream):
+                    ids, ds = idx.search(qq, 10, 50, stream=stream)
+                outs.append((ids, ds))
+            stream.synchronize()
+            results[j] = [(i.cpu().numpy(), d.cpu().numpy()) for i, d in outs]
+        except Exception as e:  # reported below
+            errors.append(repr(e))
+
+    threads = [threading.Thread(target=worker, args=(j, streams[j % 2])) for j in range(4)]
+    for t in threads:
+        t.start()
+    for t in threads:
+        t.join(timeout=120)
+    assert not errors, errors
+    assert sorted(results) == [0, 1, 2, 3]
+    for j, outs in results.items():
+        for ids, ds in outs:
+            n = ids.shape[0]
+            reps = max(1, n // len(Q))
+            ei = np.tile(ref_i, (reps, 1))[:n] if n > len(Q) else ref_i[:n]
+            ed = np.tile(ref_d, (reps, 1))[:n] if n > len(Q) else ref_d[:n]
+            assert np.array_equal(ids, ei) and np.array_equal(ds, ed), (j, n)
+
+
 @pytest.mark.parametrize("ef", [10, 64])
 def test_parity_ties_and_duplicates(hnsw, ef):
     """Integer grid coordinates: most distances tie, and many points are exact

@@ -823,9 +823,23 @@ __device__ void search_layer0(const DevIndex &ix, const SearchArgs &a, const Job
     uint32_t wsize = 1;
     int cursor = 0;  // every position below it is expanded
     n_dist0 = 1;
+    // FP8 store: the links of the element most likely expanded next (the
+    // second unexpanded element of W when the current one is taken; it comes
+    // next unless a key admitted meanwhile is smaller, about 2 times in 3 on
+    // sift_like) are loaded while the current element's neighbours are
+    // gathered: when it does come next, its links are already in registers
+    // and the expansion skips one dependent memory round trip.  pid: the
+    // element whose row pl holds (kNoLink: none).  Alternating runs on one GPU
+    // (10,000-query sift_like batch): FP8 3.5% faster; fp32 1.5% and BF16 2.3%
+    // slower (their traversal moves 2-4 times the bytes and is limited by
+    // bandwidth, not by the chain of round trips), so only FP8 does it.
+    constexpr bool kPrefetch = KIND == kFP8;
+    const int lsel = min(lane, static_cast<int>(ix.Mmax0) - 1);
+    uint32_t pid = kNoLink, pl = 0;
     for (;;) {
         int c = -1;
         uint64_t ck = 0;
+        uint32_t nid = kNoLink;  // the second unexpanded element, if in the same 64-entry chunk
         for (int cb = cursor; cb < static_cast<int>(wsize); cb += 64) {
             const int i = cb + lane;
             const uint64_t w = i < static_cast<int>(wsize) ? s.W[i] : 1ull;
@@ -834,6 +848,8 @@ __device__ void search_layer0(const DevIndex &ix, const SearchArgs &a, const Job
                 const int t = __ffsll(static_cast<unsigned long long>(um)) - 1;
                 c = cb + t;
                 ck = readlane64(w, t);
+                const uint64_t um2 = um & (um - 1);
+                if (kPrefetch && um2) nid = key_id(readlane64(w, __ffsll(static_cast<unsigned long long>(um2)) - 1));
                 break;
             }
         }
@@ -841,7 +857,11 @@ __device__ void search_layer0(const DevIndex &ix, const SearchArgs &a, const Job
         if (lane == 0) s.W[c] = ck | 1ull;
         cursor = c + 1;
         const uint32_t cid = key_id(ck);
-        const uint32_t ld = ix.adj0[static_cast<size_t>(cid) * ix.Mmax0 + min(lane, static_cast<int>(ix.Mmax0) - 1)];
+        uint32_t ld;
+        if (kPrefetch && cid == pid)
+            ld = pl;
+        else
+            ld = ix.adj0[static_cast<size_t>(cid) * ix.Mmax0 + lsel];
         const uint32_t e = lane < static_cast<int>(ix.Mmax0) ? ld : kNoLink;
         const int vs = e != kNoLink ? visit(s.ht, ht_shift, ht_mask, e) : kSeen;
         const bool fresh = vs != kSeen;
@@ -850,6 +870,10 @@ __device__ void search_layer0(const DevIndex &ix, const SearchArgs &a, const Job
         const int m = __popcll(fm);
         if (fresh) s.ids[rank_in(fm)] = e;
         wave_sync();
+        // issued here, after the links above are used, so that no wait for them
+        // also waits for it: it is in flight with the gathers below
+        if (kPrefetch && nid != kNoLink) pl = ix.adj0[static_cast<size_t>(nid) * ix.Mmax0 + lsel];
+        pid = nid;
         score_ids<G, F, METRIC, KIND, BUF>(ix, src, Q, s.ids, m, s.keys);
         wave_sync();
         n_dist0 += m;

@@ -108,6 +108,15 @@ hnsw_status hnsw_index_info(const hnsw_index *index, uint64_t out[9]);
  *   ef        size of the dynamic list W (Alg. 2); raised to k when smaller;
  *             above HNSW_EF_MAX returns HNSW_ERR_UNSUPPORTED.
  *   ids_out   device i32 [n][k];  dists_out  device fp32 [n][k].
+ * A batch of more than 256 queries uses a device workspace of 20 bytes per
+ * query (at least 1 MiB), one per (device, stream), allocated on first use,
+ * grown to the largest batch seen on that stream and kept until the process
+ * ends.  A batch larger than the waves the GPU holds at once runs as three
+ * launches on `stream` (every descent, an ordering step, then layer 0 with the
+ * queries whose descent ended farthest started first); results and counters
+ * are those of the one-launch form.  Calls on one stream from several threads
+ * are serialised while their launches are enqueued.  If the workspace cannot
+ * be allocated the batch runs as one launch.
  */
 hnsw_status hnsw_search_batch(const hnsw_index *index, const float *queries, uint32_t n, uint32_t k, uint32_t ef,
                               int32_t *ids_out, float *dists_out, void *stream);

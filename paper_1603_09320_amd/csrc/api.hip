@@ -279,19 +279,11 @@ static hnsw_status search_impl(const hnsw_index *index, const float *queries, ui
     a.wcap = (efe + 63) & ~63u;
     a.wpow2 = 64;
     while (a.wpow2 < a.wcap) a.wpow2 <<= 1;
-    // visited table: about 8 slots per unit of ef, 1024..4096 slots
-    // (HNSW_VISITED_LOG2 = 8..14 overrides the size, for tuning)
-    uint32_t lg = 10;
-    while (lg < 12 && (1u << lg) < 8u * efe) ++lg;
-    if (const char *v = getenv("HNSW_VISITED_LOG2")) {
-        const long x = strtol(v, nullptr, 10);
-        if (x >= 8 && x <= 14) lg = static_cast<uint32_t>(x);
-    }
-    a.ht_log2 = lg;
     a.mode = mode;
     a.mlp = hnsw::DevMlp{};
     if (mode == HNSW_MODE_LEARNED) a.mlp = static_cast<const hnsw_mlp *>(mlp)->net;
     a.ckpt_trace = mode == HNSW_MODE_LEARNED ? trace : nullptr;
+    a.ht_slots = hnsw::visited_slots(a, mode == HNSW_MODE_LEARNED);
     if (hnsw::launch_search(index->ix, a, static_cast<hipStream_t>(stream)) != hipSuccess) {
         (void)hipGetLastError();
         return HNSW_ERR_DEVICE;

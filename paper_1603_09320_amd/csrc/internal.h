@@ -50,7 +50,7 @@ struct SearchArgs {
     uint32_t *counters;    // [nq][4] or null
     uint32_t wcap;         // capacity of W in LDS, multiple of 64, >= ef
     uint32_t wpow2;        // power of two >= wcap (LDS reserved for W)
-    uint32_t ht_log2;      // visited-table slots = 1 << ht_log2
+    uint32_t ht_slots;     // visited-table slots (any count >= 64)
     int mode;              // hnsw_mode
     DevMlp mlp;            // learned stop rule (mode HNSW_MODE_LEARNED)
     float *ckpt_trace;     // learned mode: [nq][max_ckpt][26] features + outputs per checkpoint, or null
@@ -83,6 +83,10 @@ hipError_t launch_quantize_fp8(const DevIndex &ix, uint8_t *out, hipStream_t str
 
 // LDS per wave of a search kernel; `learned` adds the stop rule's buffers.
 size_t search_lds_bytes(const SearchArgs &a, bool learned);
+// Visited-table slots for a batch search: at least the power of two of the
+// 8-slots-per-ef rule (1024..4096), more while the kernel's LDS share at its
+// target occupancy leaves room.
+uint32_t visited_slots(const SearchArgs &a, bool learned);
 
 // Brute-force K-NN (MFMA scan + fp64 rerank).
 hipError_t launch_row_norms(const DevIndex &ix, float *out, hipStream_t stream);

@@ -37,7 +37,30 @@ TileShape tile_for(int kind, uint32_t dim) {
 
 size_t search_lds_bytes(const SearchArgs &a, bool learned) {
     return static_cast<size_t>(a.wpow2) * 8 + 64 * 8 + 64 * 4 + (learned ? 64 * 4 + 128 * 4 : 0) +
-           (static_cast<size_t>(1) << a.ht_log2) * 4;
+           static_cast<size_t>(a.ht_slots) * 4;
+}
+
+// The batch kernels keep six waves per SIMD (five for FP8), at most 24 per
+// CU sharing 160 KiB of LDS.  The table takes what is left of a 24th of it,
+// rounded down to whole KiB (the share itself, so that no allocation rounding
+// can cost a wave); a fuller table forgets fewer ids (a forgotten id is
+// scored again).  FP8 is sized like the others: a table filling a 20th of
+// the LDS (all of it at five waves per SIMD) measured 2% slower.
+// HNSW_VISITED_LOG2 = 8..14 fixes a power of two instead.
+uint32_t visited_slots(const SearchArgs &a, bool learned) {
+    if (const char *v = getenv("HNSW_VISITED_LOG2")) {
+        const long x = strtol(v, nullptr, 10);
+        if (x >= 8 && x <= 14) return 1u << x;
+    }
+    uint32_t lg = 10;
+    while (lg < 12 && (1u << lg) < 8u * a.ef) ++lg;
+    const uint32_t base = 1u << lg;
+    const uint32_t share = (160u * 1024u / 24u) & ~1023u;
+    SearchArgs t = a;
+    t.ht_slots = 0;
+    const uint32_t fixed = static_cast<uint32_t>(search_lds_bytes(t, learned));
+    const uint32_t fit = share > fixed ? ((share - fixed) / 4) & ~63u : 0u;
+    return fit > base ? fit : base;
 }
 
 bool stores_buffered(const DevIndex &ix) {

@@ -145,11 +145,14 @@ __device__ __forceinline__ int wave_min_int(int v) {
 // has never been scored before.
 constexpr int kSeen = 0, kInserted = 1, kForgot = 2;
 
-__device__ __forceinline__ int visit(uint32_t *ht, uint32_t shift, uint32_t mask, uint32_t id) {
-    const uint32_t h = (id * 0x9E3779B1u) >> shift;
+// The home slot is the multiplicative hash of the id scaled onto [0, slots)
+// (multiply-shift, so any slot count works); probes continue linearly, wrapping.
+__device__ __forceinline__ int visit(uint32_t *ht, uint32_t slots, uint32_t id) {
+    const uint32_t h = static_cast<uint32_t>((static_cast<uint64_t>(id * 0x9E3779B1u) * slots) >> 32);
 #pragma unroll
     for (int p = 0; p < kProbes; ++p) {
-        const uint32_t slot = (h + p) & mask;
+        uint32_t slot = h + p;
+        slot = slot >= slots ? slot - slots : slot;
         const uint32_t old = atomicCAS(&ht[slot], kNoLink, id);
         if (old == kNoLink) return kInserted;
         if (old == id) return kSeen;
@@ -380,7 +383,7 @@ struct WaveLds {
     uint32_t *ids;     // [64] ids of the current batch
     uint32_t *prevk;   // [64] top-K ids at the previous checkpoint (learned mode)
     float *hid;        // [2][64] hidden layers of the stop-rule network
-    uint32_t *ht;      // [1 << ht_log2]
+    uint32_t *ht;      // [ht_slots]
 };
 
 // The learned stop rule's buffers (prevk, hid) are carved only for its
@@ -799,13 +802,13 @@ __device__ Descent descend(const DevIndex &ix, const RowSource &src, const Query
 // The rest of K-NN-SEARCH (Alg. 5) from the descent's result: SEARCH-LAYER on
 // layer 0 with ef (Alg. 2), the exact rerank of low-precision traversals, and
 // the K nearest of W written to the job's outputs.  `s` is the wave's LDS
-// workspace, sized for a.wpow2 and a.ht_log2; job.ef >= job.k.
+// workspace, sized for a.wpow2 and a.ht_slots; job.ef >= job.k.
 template <int G, int F, int METRIC, int KIND, bool LEARN, bool BUF>
 __device__ void search_layer0(const DevIndex &ix, const SearchArgs &a, const Job &job, const WaveLds &s,
                               const RowSource &src, const QueryRegs<G, F, KIND> &Q, const Descent &dsc) {
     const int lane = lane_id();
     const float *qrow = job.q;
-    const uint32_t ht_slots = 1u << a.ht_log2;
+    const uint32_t ht_slots = a.ht_slots;
     for (uint32_t i = lane; i < ht_slots; i += 64) s.ht[i] = kNoLink;
     const uint64_t cur = dsc.cur;
     const uint32_t n_dist = dsc.n_dist, n_exp = dsc.n_exp;
@@ -814,10 +817,9 @@ __device__ void search_layer0(const DevIndex &ix, const SearchArgs &a, const Job
     // SEARCH-LAYER on layer 0 with ef candidates, starting from the descent's result.
     uint32_t ef = job.ef;
     LearnState lst{0u, 0u, n_exp, uniform_f(key_dist(cur)), 0.f, 0.f};
-    const uint32_t ht_shift = 32u - a.ht_log2, ht_mask = ht_slots - 1u;
     if (lane == 0) {
         s.W[0] = cur;
-        visit(s.ht, ht_shift, ht_mask, key_id(cur));
+        visit(s.ht, ht_slots, key_id(cur));
     }
     wave_sync();
     uint32_t wsize = 1;
@@ -863,7 +865,7 @@ __device__ void search_layer0(const DevIndex &ix, const SearchArgs &a, const Job
         else
             ld = ix.adj0[static_cast<size_t>(cid) * ix.Mmax0 + lsel];
         const uint32_t e = lane < static_cast<int>(ix.Mmax0) ? ld : kNoLink;
-        const int vs = e != kNoLink ? visit(s.ht, ht_shift, ht_mask, e) : kSeen;
+        const int vs = e != kNoLink ? visit(s.ht, ht_slots, e) : kSeen;
         const bool fresh = vs != kSeen;
         const bool forgot = __ballot(vs == kForgot) != 0;
         const uint64_t fm = __ballot(fresh);

@@ -285,7 +285,7 @@ hnsw_status hnsw_server_start(const hnsw_index *index, const hnsw_mlp *mlp, uint
     while (a.wpow2 < a.wcap) a.wpow2 <<= 1;
     uint32_t lg = 10;
     while (lg < 12 && (1u << lg) < 8u * ef_max) ++lg;
-    a.ht_log2 = lg;
+    a.ht_slots = 1u << lg;
     a.mode = HNSW_MODE_PLAIN;
     a.mlp = mlp ? mlp->net : hnsw::DevMlp{};
     if (hnsw::launch_serve(index->ix, a, sv, waves, s->stream) != hipSuccess) {

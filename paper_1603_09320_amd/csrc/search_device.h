@@ -146,13 +146,21 @@ __device__ __forceinline__ int wave_min_int(int v) {
 constexpr int kSeen = 0, kInserted = 1, kForgot = 2;
 
 // The home slot is the multiplicative hash of the id scaled onto [0, slots)
-// (multiply-shift, so any slot count works); probes continue linearly, wrapping.
+// (multiply-shift, so any slot count works); later probes step by a second
+// hash of the id, 1..128 slots (below the smallest table, 256 slots), so that
+// they do not fall in the runs that linear probing builds: at ef = 56 on
+// sift_like this forgets fewer ids than linear steps (738 against 746
+// distance evaluations per query, 1,216 slots).
 __device__ __forceinline__ int visit(uint32_t *ht, uint32_t slots, uint32_t id) {
     const uint32_t h = static_cast<uint32_t>((static_cast<uint64_t>(id * 0x9E3779B1u) * slots) >> 32);
+    const uint32_t step = 1u + ((id * 0x85EBCA6Bu) >> 25);
+    uint32_t slot = h;
 #pragma unroll
     for (int p = 0; p < kProbes; ++p) {
-        uint32_t slot = h + p;
-        slot = slot >= slots ? slot - slots : slot;
+        if (p) {
+            slot += step;
+            slot = slot >= slots ? slot - slots : slot;
+        }
         const uint32_t old = atomicCAS(&ht[slot], kNoLink, id);
         if (old == kNoLink) return kInserted;
         if (old == id) return kSeen;

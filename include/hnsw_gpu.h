@@ -111,12 +111,16 @@ hnsw_status hnsw_index_info(const hnsw_index *index, uint64_t out[9]);
  * A batch of more than 256 queries uses a device workspace of 20 bytes per
  * query (at least 1 MiB), one per (device, stream), allocated on first use,
  * grown to the largest batch seen on that stream and kept until the process
- * ends.  A batch larger than the waves the GPU holds at once runs as three
+ * ends.  A batch larger than the waves the GPU holds at once can run as three
  * launches on `stream` (every descent, an ordering step, then layer 0 with the
  * queries whose descent ended farthest started first); results and counters
- * are those of the one-launch form.  Calls on one stream from several threads
- * are serialised while their launches are enqueued.  If the workspace cannot
- * be allocated the batch runs as one launch.
+ * are those of the one-launch form.  Which form is faster depends on the data
+ * (per-query cost spread), so for each (index, mode, ef, batch-size octave)
+ * the library times one call of each form, reading events back without
+ * blocking, and then keeps the faster; until then it uses the three launches.
+ * Calls on one stream from several threads are serialised while their
+ * launches are enqueued.  If the workspace cannot be allocated the batch runs
+ * as one launch.
  */
 hnsw_status hnsw_search_batch(const hnsw_index *index, const float *queries, uint32_t n, uint32_t k, uint32_t ef,
                               int32_t *ids_out, float *dists_out, void *stream);

@@ -83,6 +83,15 @@ hipError_t launch_quantize_fp8(const DevIndex &ix, uint8_t *out, hipStream_t str
 
 // LDS per wave of a search kernel; `learned` adds the stop rule's buffers.
 size_t search_lds_bytes(const SearchArgs &a, bool learned);
+// Form of a batch larger than the resident waves (true: the scheduled
+// launches).  Per (index, mode, ef, batch-size octave) it times one call of
+// each form with events read back without blocking, then keeps the faster;
+// until then it answers true.  *ev_start / *ev_end, when set, are to be
+// recorded on the stream around the batch's launches.  Called with the
+// workspace mutex held.
+bool tuned_form(const DevIndex &ix, const SearchArgs &a, hipStream_t stream, hipEvent_t *ev_start,
+                hipEvent_t *ev_end);
+
 // Visited-table slots for a batch search: at least the power of two of the
 // 8-slots-per-ef rule (1024..4096), more while the kernel's LDS share at its
 // target occupancy leaves room.

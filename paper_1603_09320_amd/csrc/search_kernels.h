@@ -218,24 +218,10 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(6))) void la
     layer0_query<G, F, METRIC, kF32, true, BUF>(ix, a);
 }
 
-// One metric: the one-kernel launch or, for a batch larger than the waves of
-// the one-kernel form resident at once (a.sched 1) or always (a.sched 2), the
-// scheduled three.
+// The launches of one form (the one-kernel form, or the scheduled three).
 template <int G, int F, int METRIC, int KIND, bool BUF>
-hipError_t launch_gfkm(const DevIndex &ix, const SearchArgs &a, hipStream_t stream) {
-    const bool learned = KIND == kF32 && a.mode == HNSW_MODE_LEARNED;
-    const size_t lds = search_lds_bytes(a, learned);
-    const void *fused = learned ? reinterpret_cast<const void *>(&search_kernel_learned<G, F, METRIC, BUF>)
-                                : reinterpret_cast<const void *>(&search_kernel<G, F, METRIC, KIND, BUF>);
-    bool sched = a.sched_order && a.sched == 2;
-    if (a.sched_order && a.sched == 1) {
-        int per_cu = 0, dev = 0, cus = 0;
-        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fused, 64, lds) == hipSuccess &&
-            hipGetDevice(&dev) == hipSuccess &&
-            hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess)
-            sched = static_cast<uint64_t>(a.nq) > static_cast<uint64_t>(per_cu) * static_cast<uint64_t>(cus);
-        (void)hipGetLastError();
-    }
+hipError_t launch_form(const DevIndex &ix, const SearchArgs &a, hipStream_t stream, bool sched, bool learned,
+                       size_t lds) {
     if (!sched) {
         if (learned)
             hipLaunchKernelGGL((search_kernel_learned<G, F, METRIC, BUF>), dim3(a.nq), dim3(64), lds, stream, ix, a);
@@ -250,6 +236,32 @@ hipError_t launch_gfkm(const DevIndex &ix, const SearchArgs &a, hipStream_t stre
     else
         hipLaunchKernelGGL((layer0_kernel<G, F, METRIC, KIND, BUF>), dim3(a.nq), dim3(64), lds, stream, ix, a);
     return hipGetLastError();
+}
+
+// One metric: the one-kernel launch or the scheduled three.  A batch larger
+// than the waves of the one-kernel form resident at once takes the form
+// tuned_form picks for it (a.sched 1); a.sched 2 forces the scheduled form.
+template <int G, int F, int METRIC, int KIND, bool BUF>
+hipError_t launch_gfkm(const DevIndex &ix, const SearchArgs &a, hipStream_t stream) {
+    const bool learned = KIND == kF32 && a.mode == HNSW_MODE_LEARNED;
+    const size_t lds = search_lds_bytes(a, learned);
+    const void *fused = learned ? reinterpret_cast<const void *>(&search_kernel_learned<G, F, METRIC, BUF>)
+                                : reinterpret_cast<const void *>(&search_kernel<G, F, METRIC, KIND, BUF>);
+    bool sched = a.sched_order && a.sched == 2;
+    hipEvent_t ev0 = nullptr, ev1 = nullptr;  // set while tuned_form times this call
+    if (a.sched_order && a.sched == 1) {
+        int per_cu = 0, dev = 0, cus = 0;
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fused, 64, lds) == hipSuccess &&
+            hipGetDevice(&dev) == hipSuccess &&
+            hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess &&
+            static_cast<uint64_t>(a.nq) > static_cast<uint64_t>(per_cu) * static_cast<uint64_t>(cus))
+            sched = tuned_form(ix, a, stream, &ev0, &ev1);
+        (void)hipGetLastError();
+    }
+    if (ev0) (void)hipEventRecord(ev0, stream);
+    hipError_t err = launch_form<G, F, METRIC, KIND, BUF>(ix, a, stream, sched, learned, lds);
+    if (ev1) (void)hipEventRecord(ev1, stream);
+    return err;
 }
 
 template <int G, int F, int KIND, bool BUF>

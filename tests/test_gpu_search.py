@@ -188,6 +188,34 @@ def test_scheduled_concurrent_threads_and_streams(hnsw, cfg0, monkeypatch):
             assert np.array_equal(ids, ei) and np.array_equal(ds, ed), (j, n)
 
 
+def test_default_form_choice_repeated_calls(hnsw, cfg0, monkeypatch):
+    """A batch above the resident capacity with the default form choice: the
+    first calls time the scheduled and the one-kernel forms (events read back
+    later, without blocking), later ones use the faster.  Every call, with or
+    without a synchronisation before the next, returns the same results, and
+    those equal the oracle's on a sample."""
+    _log("case default form choice, repeated 12,000-query calls")
+    monkeypatch.delenv("HNSW_SCHEDULE", raising=False)
+    X, _, G = cfg0
+    Q = synthdata.queries("uniform16", 12000)
+    idx = _index(hnsw, G, X)
+    q = torch.from_numpy(Q).cuda()
+    outs = []
+    for r in range(8):
+        ids, ds = idx.search(q, 10, 50)
+        if r % 3 == 2:
+            torch.cuda.synchronize()
+        outs.append((ids, ds))
+    torch.cuda.synchronize()
+    first_i, first_d = outs[0][0].cpu().numpy(), outs[0][1].cpu().numpy()
+    for ids, ds in outs[1:]:
+        assert np.array_equal(ids.cpu().numpy(), first_i) and np.array_equal(ds.cpu().numpy(), first_d)
+    sample = np.random.default_rng(5).choice(len(Q), size=200, replace=False)
+    oi, od = G.search(Q[sample], 10, 50, nthreads=8)
+    r = parity.compare(first_i[sample], first_d[sample], oi, od, X, Q[sample], oracle.L2)
+    assert r["fail"] == 0 and r["exempt"] == 0
+
+
 @pytest.mark.parametrize("ef", [10, 64])
 def test_parity_ties_and_duplicates(hnsw, ef):
     """Integer grid coordinates: most distances tie, and many points are exact

@@ -140,9 +140,14 @@ __device__ __forceinline__ int wave_min_int(int v) {
 // Test-and-set of `id` in the visited table.  Returns kSeen when the id was
 // already there, kInserted when this call put it there, and kForgot when all
 // kProbes slots were taken by other ids: the id is then treated as unseen
-// (scored again).  Slots are never cleared during a query, so an id that was
-// once forgotten is forgotten at every later test, and an id that is inserted
-// has never been scored before.
+// (scored again).  The table only says which ids need no scoring, so any
+// policy for a full table gives the same search results; it decides how often
+// an id is scored twice.  Without REPLACE a forgotten id stays forgotten (slots
+// are never cleared within a query), so an id that is inserted has never been
+// scored before.  With REPLACE the id then takes its home slot (its older
+// occupant is forgotten instead): ids met recently are the likeliest to be met
+// again, and the longest queries, which fill the table, score fewer ids twice;
+// an inserted id may then have been scored before.
 constexpr int kSeen = 0, kInserted = 1, kForgot = 2;
 
 // The home slot is the multiplicative hash of the id scaled onto [0, slots)
@@ -151,6 +156,7 @@ constexpr int kSeen = 0, kInserted = 1, kForgot = 2;
 // they do not fall in the runs that linear probing builds: at ef = 56 on
 // sift_like this forgets fewer ids than linear steps (738 against 746
 // distance evaluations per query, 1,216 slots).
+template <bool REPLACE>
 __device__ __forceinline__ int visit(uint32_t *ht, uint32_t slots, uint32_t id) {
     const uint32_t h = static_cast<uint32_t>((static_cast<uint64_t>(id * 0x9E3779B1u) * slots) >> 32);
     const uint32_t step = 1u + ((id * 0x85EBCA6Bu) >> 25);
@@ -165,6 +171,7 @@ __device__ __forceinline__ int visit(uint32_t *ht, uint32_t slots, uint32_t id) 
         if (old == kNoLink) return kInserted;
         if (old == id) return kSeen;
     }
+    if (REPLACE) atomicExch(&ht[h], id);
     return kForgot;
 }
 
@@ -827,7 +834,7 @@ __device__ void search_layer0(const DevIndex &ix, const SearchArgs &a, const Job
     LearnState lst{0u, 0u, n_exp, uniform_f(key_dist(cur)), 0.f, 0.f};
     if (lane == 0) {
         s.W[0] = cur;
-        visit(s.ht, ht_slots, key_id(cur));
+        visit<false>(s.ht, ht_slots, key_id(cur));
     }
     wave_sync();
     uint32_t wsize = 1;
@@ -846,6 +853,13 @@ __device__ void search_layer0(const DevIndex &ix, const SearchArgs &a, const Job
     constexpr bool kPrefetch = KIND == kFP8;
     const int lsel = min(lane, static_cast<int>(ix.Mmax0) - 1);
     uint32_t pid = kNoLink, pl = 0;
+    // fp32 store: a full visited table replaces (see visit).  Same-GPU
+    // alternating runs, 10,000-query sift_like batch at ef 56: fp32 4.6%
+    // faster (the longest queries, which end the batch, score fewer ids
+    // twice); BF16 and FP8 0.4-1.6% slower (after a replacement their merge
+    // must keep its duplicate checks), so they keep a forgetting table.
+    constexpr bool kReplace = KIND == kF32;
+    bool replaced = false;  // some id of this query took another's slot
     for (;;) {
         int c = -1;
         uint64_t ck = 0;
@@ -873,9 +887,13 @@ __device__ void search_layer0(const DevIndex &ix, const SearchArgs &a, const Job
         else
             ld = ix.adj0[static_cast<size_t>(cid) * ix.Mmax0 + lsel];
         const uint32_t e = lane < static_cast<int>(ix.Mmax0) ? ld : kNoLink;
-        const int vs = e != kNoLink ? visit(s.ht, ht_slots, e) : kSeen;
+        const int vs = e != kNoLink ? visit<kReplace>(s.ht, ht_slots, e) : kSeen;
         const bool fresh = vs != kSeen;
-        const bool forgot = __ballot(vs == kForgot) != 0;
+        // with replacement, every id inserted after the first one may repeat
+        // an element of W: the merge keeps its checks from then on
+        const bool batch_forgot = __ballot(vs == kForgot) != 0;
+        replaced = kReplace && (replaced || batch_forgot);
+        const bool forgot = batch_forgot || replaced;
         const uint64_t fm = __ballot(fresh);
         const int m = __popcll(fm);
         if (fresh) s.ids[rank_in(fm)] = e;

@@ -219,6 +219,7 @@ hnsw_status hnsw_index_upload(const hnsw_graph_desc *g, void *stream, hnsw_index
     ix.entry = g->entry_point;
     ix.max_level = g->max_level;
     ix.metric = g->metric;
+    ix.uid = hnsw::next_index_uid();
     ok = ok && hnsw::launch_row_norms(ix, xnorm, st) == hipSuccess;
     ok = ok && hipStreamSynchronize(st) == hipSuccess;
     if (!ok) {
@@ -239,6 +240,7 @@ hnsw_status hnsw_index_upload(const hnsw_graph_desc *g, void *stream, hnsw_index
 
 void hnsw_index_free(hnsw_index *index) {
     if (!index) return;
+    hnsw::forget_index(index->ix.uid);
     for (void *p : index->allocations) hnsw::device_free(p);
     delete index;
 }

@@ -26,6 +26,7 @@ struct DevIndex {
     uint32_t fp8_scale_off;  // byte offset of the row's fp32 scale
     uint32_t n, dim, dv4, stride4;
     uint32_t Mmax, Mmax0, entry, max_level, metric;
+    uint32_t uid;  // identifies the index among those uploaded by this process (host bookkeeping only)
 };
 
 // The learned stop rule's network as the search kernel reads it: BF16
@@ -50,7 +51,7 @@ struct SearchArgs {
     uint32_t *counters;    // [nq][4] or null
     uint32_t wcap;         // capacity of W in LDS, multiple of 64, >= ef
     uint32_t wpow2;        // power of two >= wcap (LDS reserved for W)
-    uint32_t ht_slots;     // visited-table slots (any count >= 64)
+    uint32_t ht_slots;     // visited-table slots, >= 256 (probe steps reach 128 slots and wrap once)
     int mode;              // hnsw_mode
     DevMlp mlp;            // learned stop rule (mode HNSW_MODE_LEARNED)
     float *ckpt_trace;     // learned mode: [nq][max_ckpt][26] features + outputs per checkpoint, or null
@@ -91,6 +92,10 @@ size_t search_lds_bytes(const SearchArgs &a, bool learned);
 // workspace mutex held.
 bool tuned_form(const DevIndex &ix, const SearchArgs &a, hipStream_t stream, hipEvent_t *ev_start,
                 hipEvent_t *ev_end);
+// Drops the timing records of an index that is being freed.
+void forget_index(uint32_t uid);
+// Next index identifier (never 0).
+uint32_t next_index_uid();
 
 // Visited-table slots for a batch search: at least the power of two of the
 // 8-slots-per-ef rule (1024..4096), more while the kernel's LDS share at its

@@ -7,6 +7,7 @@
 // stores.
 #include <stdlib.h>
 
+#include <atomic>
 #include <mutex>
 
 #include "search_kernels.h"
@@ -118,8 +119,11 @@ uint8_t *sched_buffer(hipStream_t stream, size_t need) {
 // Tuning records of tuned_form.  The forms give identical results, so the
 // choice affects time only; on sift_like the scheduled launches are 4-26%
 // faster, on deep_like (short layer-0 searches, tight clusters) 1-8% slower.
+// Records are keyed by the index's uid (never reused within the process) and
+// dropped when the index is freed; the table holds at most kTuneCap records
+// (the oldest decided ones make room).
 struct FormTune {
-    const void *index;  // the index's layer-0 links identify it
+    uint32_t index;  // DevIndex::uid
     int device, mode;
     uint32_t ef, octave;
     int phase;          // 0 warm-up call, 1 scheduled timed, 2 one-kernel timed, 3 decided
@@ -128,10 +132,38 @@ struct FormTune {
     float ms[2];
 };
 std::vector<FormTune> g_tune;
+constexpr size_t kTuneCap = 1024;
 
 bool events_done(hipEvent_t e) { return hipEventQuery(e) == hipSuccess; }
 
+void destroy_events(FormTune &t) {
+    for (auto &pair : t.ev)
+        for (hipEvent_t &e : pair)
+            if (e) (void)hipEventDestroy(e), e = nullptr;
+}
+
+std::atomic<uint32_t> g_uid{0};
+
 }  // namespace
+
+uint32_t next_index_uid() {
+    uint32_t u = ++g_uid;
+    if (u == 0) u = ++g_uid;
+    return u;
+}
+
+void forget_index(uint32_t uid) {
+    std::lock_guard<std::mutex> lk(g_sched_mu);
+    size_t j = 0;
+    for (size_t i = 0; i < g_tune.size(); ++i) {
+        if (g_tune[i].index == uid) {
+            destroy_events(g_tune[i]);
+            continue;
+        }
+        g_tune[j++] = g_tune[i];
+    }
+    g_tune.resize(j);
+}
 
 bool tuned_form(const DevIndex &ix, const SearchArgs &a, hipStream_t stream, hipEvent_t *ev_start,
                 hipEvent_t *ev_end) {
@@ -147,9 +179,23 @@ bool tuned_form(const DevIndex &ix, const SearchArgs &a, hipStream_t stream, hip
     while ((a.nq >> octave) > 1u) ++octave;
     FormTune *t = nullptr;
     for (FormTune &x : g_tune)
-        if (x.index == ix.adj0 && x.device == dev && x.mode == a.mode && x.ef == a.ef && x.octave == octave) t = &x;
+        if (x.index == ix.uid && x.device == dev && x.mode == a.mode && x.ef == a.ef && x.octave == octave) t = &x;
     if (!t) {
-        g_tune.push_back(FormTune{ix.adj0, dev, a.mode, a.ef, octave, 0, true, {{nullptr, nullptr}, {nullptr, nullptr}},
+        if (g_tune.size() >= kTuneCap) {
+            // make room: drop the older half of the decided records (records
+            // still timing hold events that are in flight)
+            size_t j = 0, dropped = 0;
+            for (size_t i = 0; i < g_tune.size(); ++i) {
+                if (g_tune[i].phase == 3 && dropped < kTuneCap / 2) {
+                    ++dropped;
+                    continue;
+                }
+                g_tune[j++] = g_tune[i];
+            }
+            g_tune.resize(j);
+            if (g_tune.size() >= kTuneCap) return true;  // every record is mid-timing: no tuning for this call
+        }
+        g_tune.push_back(FormTune{ix.uid, dev, a.mode, a.ef, octave, 0, true, {{nullptr, nullptr}, {nullptr, nullptr}},
                                   {0.f, 0.f}});
         t = &g_tune.back();
     }
@@ -185,9 +231,7 @@ bool tuned_form(const DevIndex &ix, const SearchArgs &a, hipStream_t stream, hip
             } else {
                 t->sched = t->ms[0] <= t->ms[1];
             }
-            for (auto &pair : t->ev)
-                for (hipEvent_t &e : pair)
-                    if (e) (void)hipEventDestroy(e), e = nullptr;
+            destroy_events(*t);
             t->phase = 3;
             return t->sched;
         default:

@@ -430,11 +430,14 @@ __device__ __forceinline__ WaveLds carve(uint8_t *base, const SearchArgs &a) {
 // entries and detects an equal one; no LDS access depends on another.
 // `forgot`: some id of this batch was forgotten by the visited table.  Only
 // then can a new key already be in W (the id was scored before without being
-// recorded) or equal another new key (the same id twice); otherwise both
-// checks are skipped.  The search passes it for the low-precision stores only
-// and true (both checks always made) for the fp32 store: on the 10,000-query
-// sift_like batch the leaner loop measured 2% faster with FP8 but 0.6% slower
-// with fp32 (same GPU, alternating runs).
+// recorded) or equal another new key of the batch (an adjacency row that
+// lists one id twice, both copies forgotten): such keys are dropped, so W
+// never holds an id twice, as with the exact visited set of Alg. 2.
+// Otherwise both checks are skipped.  The low-precision stores pass whether
+// their batch forgot; the fp32 store, whose table replaces entries (see
+// visit), always passes true: on the 10,000-query sift_like batch the leaner
+// loop measured 2% faster with FP8 but 0.6% slower with fp32 (same GPU,
+// alternating runs).
 __device__ __forceinline__ int merge_into_w(const WaveLds &s, int m, uint32_t ef, uint32_t &wsize, bool forgot) {
     const int lane = lane_id();
     const int ws = static_cast<int>(wsize);
@@ -473,6 +476,7 @@ __device__ __forceinline__ int merge_into_w(const WaveLds &s, int m, uint32_t ef
                 cm &= cm - 1;
                 const uint64_t at = readlane64(a, t);
                 if (__ballot(wk == (at >> 1))) continue;  // (distance, id) already in W
+                if (__ballot(((km >> lane) & 1ull) && a == at)) continue;  // admitted already from a lower lane
                 const int below = __popcll(__ballot(wk < (at >> 1)));
                 km |= 1ull << t;
                 lbmin = min(lbmin, below);
@@ -498,6 +502,17 @@ __device__ __forceinline__ int merge_into_w(const WaveLds &s, int m, uint32_t ef
     if (cm == 0) return INT_MAX;
     int lb = 0;
     bool dup = false;
+    if (forgot) {
+        // the same key on a lower candidate lane: only the lowest copy may stay
+        uint64_t mm = cm;
+        while (mm) {
+            const int t = __ffsll(static_cast<unsigned long long>(mm)) - 1;
+            mm &= mm - 1;
+            const uint64_t at = readlane64(a, t);
+            const uint64_t same = __ballot(cand && a == at);
+            if (lane == t) dup = (same & ((1ull << t) - 1ull)) != 0;
+        }
+    }
     for (int cb = 0; cb < ws; cb += 64) {
         const int i = cb + lane;
         const uint64_t w = i < ws ? (s.W[i] >> 1) : ~0ull;
@@ -859,7 +874,6 @@ __device__ void search_layer0(const DevIndex &ix, const SearchArgs &a, const Job
     // twice); BF16 and FP8 0.4-1.6% slower (after a replacement their merge
     // must keep its duplicate checks), so they keep a forgetting table.
     constexpr bool kReplace = KIND == kF32;
-    bool replaced = false;  // some id of this query took another's slot
     for (;;) {
         int c = -1;
         uint64_t ck = 0;
@@ -889,11 +903,9 @@ __device__ void search_layer0(const DevIndex &ix, const SearchArgs &a, const Job
         const uint32_t e = lane < static_cast<int>(ix.Mmax0) ? ld : kNoLink;
         const int vs = e != kNoLink ? visit<kReplace>(s.ht, ht_slots, e) : kSeen;
         const bool fresh = vs != kSeen;
-        // with replacement, every id inserted after the first one may repeat
-        // an element of W: the merge keeps its checks from then on
-        const bool batch_forgot = __ballot(vs == kForgot) != 0;
-        replaced = kReplace && (replaced || batch_forgot);
-        const bool forgot = batch_forgot || replaced;
+        // with replacement an id that was inserted may have been scored before
+        // (its slot was taken over), so the fp32 merge always keeps its checks
+        const bool forgot = kReplace || __ballot(vs == kForgot) != 0;
         const uint64_t fm = __ballot(fresh);
         const int m = __popcll(fm);
         if (fresh) s.ids[rank_in(fm)] = e;
@@ -906,7 +918,7 @@ __device__ void search_layer0(const DevIndex &ix, const SearchArgs &a, const Job
         wave_sync();
         n_dist0 += m;
         n_exp0 += 1;
-        const int lbmin = merge_into_w(s, m, ef, wsize, KIND == kF32 || forgot);
+        const int lbmin = merge_into_w(s, m, ef, wsize, forgot);
         if (lbmin < cursor) cursor = lbmin;
         if (LEARN && n_exp0 % a.mlp.period == 0 && lst.ckpt < a.mlp.max_ckpt &&
             learned_checkpoint(s, a.mlp, lst, n_exp0, job.k, cursor, ef, wsize, job.trace))

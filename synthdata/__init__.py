@@ -143,12 +143,15 @@ def queries(workload: str, n: int, train: bool = False) -> np.ndarray:
     raise KeyError(workload)
 
 
-def random_graph(n: int, degree: int, seed: int, dim: int = 4, tie_grid: int = 0):
+def random_graph(n: int, degree: int, seed: int, dim: int = 4, tie_grid: int = 0, repeat_frac: float = 0.0):
     """A random directed graph plus points, for equivalence checks on tiny inputs.
 
     Returns ``(X, adj)`` where ``adj`` is uint32 [n][degree] padded with
     0xFFFFFFFF.  With ``tie_grid > 0`` the coordinates are integers in
-    [0, tie_grid), which makes equal distances (ties) common.
+    [0, tie_grid), which makes equal distances (ties) common.  With
+    ``repeat_frac > 0`` about that fraction of each list's later links are
+    overwritten by copies of earlier links of the same list (a list naming one
+    element twice), drawn from a stream of their own.
     """
     g = _rng(seed, 7)
     if tie_grid:
@@ -161,4 +164,11 @@ def random_graph(n: int, degree: int, seed: int, dim: int = 4, tie_grid: int = 0
         nb = g.choice(n - 1, size=min(k, n - 1), replace=False)
         nb = np.where(nb >= i, nb + 1, nb)
         adj[i, : len(nb)] = nb
+    if repeat_frac > 0:
+        gr = _rng(seed, 8)
+        for i in range(n):
+            k = int((adj[i] != 0xFFFFFFFF).sum())
+            for j in range(1, k):
+                if gr.random() < repeat_frac:
+                    adj[i, j] = adj[i, int(gr.integers(0, j))]
     return X, adj

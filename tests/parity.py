@@ -21,8 +21,11 @@ def compare(gpu_ids, gpu_d, or_ids, or_d, X, Q, metric, tau=None):
     or_ids = np.asarray(or_ids)
     or_d = np.asarray(or_d, dtype=np.float64)
     if tau is None:
-        finite = np.abs(or_d[np.isfinite(or_d)])
-        tau = 1.0 if metric == oracle.IP else 1e-3 * (float(np.median(finite)) if finite.size else 1.0)
+        # 1e-3 of the median distance (L2); on tie-heavy grids most returned
+        # distances can be exactly 0 (duplicates of the query), so the median
+        # is taken over the positive ones
+        pos = np.abs(or_d[np.isfinite(or_d) & (or_d != 0)])
+        tau = 1.0 if metric == oracle.IP else 1e-3 * (float(np.median(pos)) if pos.size else 1.0)
     res = dict(n=len(gpu_ids), equal=0, exempt=0, fail=0, failed=[], max_rel=0.0)
     for i in range(len(gpu_ids)):
         if np.array_equal(gpu_ids[i], or_ids[i]):

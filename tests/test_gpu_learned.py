@@ -185,3 +185,34 @@ def test_trained_net_gain_on_glove_like(hnsw):
         print(f"  plain   ef={e}: recall {r:.4f}, {x_:.1f}", flush=True)
         if r >= rec_l:
             assert x_ > exp_l
+
+
+FULL = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "graphs", "sift_like_1M.bin")
+SIFT_NET = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "paper_1603_09320_amd",
+                        "nets", "sift_like.mlp.npz")
+
+
+@pytest.mark.skipif(not (os.path.exists(FULL) and os.path.exists(SIFT_NET)), reason="1M sift_like graph or net missing")
+def test_learned_full_size_sampled(hnsw):
+    """The trained sift_like net on the 1M x 128 workload at its calibrated ef,
+    all 10,000 queries in the benchmark's launch shape: a sample against the
+    oracle's learned search with the same (BF16) net."""
+    print("case learned sift_like 1M full size", flush=True)
+    p = hnsw.graphfile.read(FULL)
+    X = synthdata.base("sift_like", p["n"])
+    Q = synthdata.queries("sift_like", 10000)
+    idx = hnsw.Index(p, X)
+    z = np.load(SIFT_NET)
+    mlp = hnsw.Mlp.load(SIFT_NET)
+    ef = int(z["ef"])
+    ids, ds, cnt = idx.search(torch.from_numpy(Q).cuda(), 10, ef, mode=hnsw.MODE_LEARNED, mlp=mlp, counters=True)
+    torch.cuda.synchronize()
+    ids, ds, cnt = ids.cpu().numpy(), ds.cpu().numpy(), cnt.cpu().numpy().astype(np.uint32)
+    G = oracle.Graph.from_packed(X, p)
+    sample = np.random.default_rng(2).choice(10000, size=150, replace=False)
+    ro = G.search_learned(Q[sample], 10, ef, net=oracle.bf16_net(z["params"]), tau=float(z["tau"]),
+                          jmax=int(z["jmax"]), T=int(z["period"]), max_ckpt=int(z["max_ckpt"]), nthreads=8)
+    stopped = float((ro["info"][:, 1] > 0).mean())
+    print(f"  ef={ef}: oracle stopped {stopped:.2f} of the sample", flush=True)
+    assert np.array_equal(ids[sample], ro["ids"]) and np.array_equal(ds[sample], ro["dists"])
+    assert np.array_equal(cnt[sample, 3], ro["counters"][:, 3].astype(np.uint32))

@@ -1,5 +1,7 @@
 """Low-precision traversal (BF16 / FP8-E4M3 with per-vector scale) plus an
 exact fp32 re-rank, on the GPU through the C ABI, against the oracle."""
+import os
+
 import numpy as np
 import pytest
 
@@ -139,3 +141,37 @@ def test_lowp_parity_scheduled(hnsw, monkeypatch, kind):
     G = oracle.Graph.build(X, M=16, efC=60, seed=4005)
     for ef in (10, 64):
         _lowp_parity(hnsw, X, Q, G, 10, ef, kind, oracle.L2)
+
+
+FULL = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "graphs", "sift_like_1M.bin")
+
+
+@pytest.mark.skipif(not os.path.exists(FULL), reason="1M sift_like graph file not built")
+@pytest.mark.parametrize("kind", [1, 2])
+def test_lowp_full_size_sampled(hnsw, kind):
+    """The 1M x 128 workload in the benchmark's launch shape (all 10,000
+    queries, K = 10, ef = 56 as timed): a sample against the oracle's
+    low-precision mirror on the same graph."""
+    print(f"case lowp sift_like 1M full size kind={kind}", flush=True)
+    p = hnsw.graphfile.read(FULL)
+    X = synthdata.base("sift_like", p["n"])
+    Q = synthdata.queries("sift_like", 10000)
+    idx = hnsw.Index(p, X)
+    idx.add_lowp(kind)
+    G = oracle.Graph.from_packed(X, p)
+    _, dec, sc = (oracle.quantize_bf16 if kind == 1 else oracle.quantize_fp8)(X)
+    G.set_lowp(dec, sc)
+    sample = np.random.default_rng(1).choice(10000, size=150, replace=False)
+    for K, ef in ((10, 56), (10, 128)):
+        ids, ds = idx.search(torch.from_numpy(Q).cuda(), K, ef, mode=kind)
+        torch.cuda.synchronize()
+        ids, ds = ids.cpu().numpy(), ds.cpu().numpy()
+        oi, od = G.search(Q[sample], K, ef, nthreads=8)
+        r = parity.compare(ids[sample], ds[sample], oi, od, X, Q[sample], oracle.L2)
+        print(f"  K={K} ef={ef}: {r['equal']} equal, {r['exempt']} exempt, {r['fail']} fail", flush=True)
+        assert r["fail"] == 0 and r["exempt"] == 0
+        # every query: distinct ids, sorted, and the distances are the exact fp32 ones (re-rank)
+        assert all(len(set(row)) == K for row in ids)
+        assert (np.diff(ds, axis=1) >= 0).all()
+        assert np.array_equal(oracle.pair_dist(X, Q, ids).astype(np.float32), ds)
+    G.set_lowp(None, None)

@@ -327,7 +327,7 @@ def test_parity_sift_like_full_size_sampled(hnsw):
     G = oracle.Graph.from_packed(X, p)
     q = torch.from_numpy(Q).cuda()
     sample = np.random.default_rng(0).choice(10000, size=150, replace=False)
-    for K, ef in ((10, 64), (10, 256), (1, 32)):
+    for K, ef in ((10, 56), (10, 64), (10, 256), (1, 32)):
         ids, ds, cnt = idx.search(q, K, ef, counters=True)
         torch.cuda.synchronize()
         ids, ds = ids.cpu().numpy(), ds.cpu().numpy()

@@ -1,7 +1,8 @@
 """Continuous-batching serving loop on the GPU: every request's result equals
-the standalone batch search with the same (query, k, ef, mode), alone and
-in a mixed Poisson stream over two indices; admission backpressure and
-refusals."""
+the oracle's search with the same (query, k, ef, mode) -- the plain search,
+the low-precision mirror for BF16, the learned search with the same net --
+and the standalone batch search, alone and in a mixed Poisson stream
+over two indices; admission backpressure and refusals."""
 import numpy as np
 import pytest
 
@@ -32,9 +33,39 @@ def setup(hnsw):
         G = oracle.Graph.build(X, M=16, efC=100, seed=3)
         idx = hnsw.Index(G.packed(), X)
         idx.add_lowp(hnsw.MODE_BF16)
-        net = hnsw.Mlp(mlp_ref.init(7), tau=1.0, jmax=2)
+        idx.add_lowp(hnsw.MODE_FP8)
+        params = mlp_ref.init(7)
+        net = hnsw.Mlp(params, tau=1.0, jmax=2)
         out[name] = (X, Q, idx, net)
+        ORACLE[name] = (G, oracle.bf16_net(params), 1.0, 2)
     return out
+
+
+ORACLE = {}
+
+
+def _oracle_one(hnsw, name, X, q, k, ef, mode):
+    """The oracle's answer to one request (ids, float distances)."""
+    G, wnet, tau, jmax = ORACLE[name]
+    q = np.ascontiguousarray(q.reshape(1, -1), dtype=np.float32)
+    if mode == hnsw.MODE_LEARNED:
+        r = G.search_learned(q, k, ef, net=wnet, tau=tau, jmax=jmax)
+        return r["ids"][0], r["dists"][0]
+    if mode in (hnsw.MODE_BF16, hnsw.MODE_FP8):
+        key = (name, mode)
+        if key not in _MIRRORS:
+            _MIRRORS[key] = (oracle.quantize_bf16 if mode == hnsw.MODE_BF16 else oracle.quantize_fp8)(X)[1:]
+        G.set_lowp(*_MIRRORS[key])
+        try:
+            i, d = G.search(q, k, ef)
+        finally:
+            G.set_lowp(None, None)
+        return i[0], d[0]
+    i, d = G.search(q, k, ef)
+    return i[0], d[0]
+
+
+_MIRRORS = {}
 
 
 def _wait(srv, ticket, k, deadline):
@@ -92,6 +123,8 @@ def test_submit_poll_equals_batch(hnsw, setup):
     for t, i, k, ef, mode, res in reqs:
         ids, ds = _standalone(hnsw, idx, net, Q[i:i + 1], k, ef, mode)
         assert np.array_equal(res[0], ids[0]) and np.array_equal(res[1], ds[0]), (i, k, ef, mode)
+        oi, od = _oracle_one(hnsw, "uniform16", X, Q[i], k, ef, mode)
+        assert np.array_equal(res[0], oi) and np.array_equal(res[1], od), ("oracle", i, k, ef, mode)
 
 
 def test_backpressure_and_refusals(hnsw, setup):
@@ -155,6 +188,11 @@ def test_mixed_poisson_stream_two_indices(hnsw, setup):
             ids, ds = _standalone(hnsw, idx, net, Q[qidx[i]:qidx[i] + 1], int(k[i]), int(ef[i]), int(mode[i]))
             assert np.array_equal(r["ids"][i, :k[i]], ids[0]), (nm, i)
             assert np.array_equal(r["dists"][i, :k[i]], ds[0]), (nm, i)
+        # every served request of this index against the oracle
+        for i in np.flatnonzero(server_of == s_i):
+            oi, od = _oracle_one(hnsw, nm, X, Q[qidx[i]], int(k[i]), int(ef[i]), int(mode[i]))
+            assert np.array_equal(r["ids"][i, :k[i]], oi), ("oracle", nm, i, int(k[i]), int(ef[i]), int(mode[i]))
+            assert np.array_equal(r["dists"][i, :k[i]], od), ("oracle", nm, i)
 
 
 def test_free_while_serving_returns_at_once(hnsw, setup):

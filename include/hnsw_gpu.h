@@ -152,6 +152,27 @@ hnsw_status hnsw_search_batch_ex(const hnsw_index *index, const float *queries, 
                                  void *stream);
 
 /*
+ * hnsw_search_batch_ex for callers that cannot allocate (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid allocation): the same
+ * kernels, results and counters, but the scheduled form's workspace (20 bytes
+ * per query) is a static device array of the library, sized for
+ * HNSW_NOALLOC_MAX_QUERIES queries (5 MiB), which every device the library
+ * runs on holds until the process ends; no device or host memory is
+ * allocated and no timing event is created (the form is the one
+ * hnsw_search_batch_ex has already measured for this index, mode, ef and
+ * batch size, else the scheduled one).
+ *   n > HNSW_NOALLOC_MAX_QUERIES -> HNSW_ERR_UNSUPPORTED (nothing enqueued).
+ * All calls on one device share that array: calls that overlap on a device
+ * (other streams, other threads) race and must be serialised by the caller;
+ * calls on one stream are ordered by the stream.  Its contents are fully
+ * rewritten by each call before being read, so nothing needs clearing.
+ */
+#define HNSW_NOALLOC_MAX_QUERIES 262144u
+hnsw_status hnsw_search_batch_noalloc(const hnsw_index *index, const float *queries, uint32_t n, uint32_t k,
+                                      uint32_t ef, int mode, const void *mlp, int32_t *ids_out, float *dists_out,
+                                      uint32_t *counters, void *stream);
+
+/*
  * Exact K-NN by brute force over the index's vectors (the problem statement
  * of Sec. 1; the "BF time" column of Table 1), the ground truth for recall.
  * A fp32 matrix-core contraction ranks every stored vector by

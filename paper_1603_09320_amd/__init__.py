@@ -20,6 +20,7 @@ LIB_PATH = os.path.join(HERE, "libhnsw_gpu.so")
 HNSW_L2SQ, HNSW_IP = 0, 1
 MODE_PLAIN, MODE_BF16, MODE_FP8, MODE_LEARNED = 0, 1, 2, 3
 EF_MAX, DIM_MAX, DEG_MAX = 1024, 256, 64
+NOALLOC_MAX_QUERIES = 262144
 
 STATUS = {0: "ok", 1: "invalid argument", 2: "out of device memory", 3: "device error", 4: "unsupported size",
           5: "malformed graph", 6: "busy"}
@@ -50,6 +51,7 @@ SIGNATURES = {
     "hnsw_index_info": (C.c_int, [_vp, _vp]),
     "hnsw_search_batch": (C.c_int, [_vp, _vp, _u32, _u32, _u32, _vp, _vp, _vp]),
     "hnsw_search_batch_ex": (C.c_int, [_vp, _vp, _u32, _u32, _u32, _i32, _vp, _vp, _vp, _vp, _vp]),
+    "hnsw_search_batch_noalloc": (C.c_int, [_vp, _vp, _u32, _u32, _u32, _i32, _vp, _vp, _vp, _vp, _vp]),
     "hnsw_bruteforce_knn": (C.c_int, [_vp, _vp, _u32, _u32, _vp, _vp, _vp]),
     "hnsw_index_add_lowp": (C.c_int, [_vp, _i32, _vp]),
     "hnsw_index_read_lowp": (C.c_int, [_vp, _i32, _vp, _vp]),
@@ -187,12 +189,14 @@ class Index:
             pass
 
     def search(self, queries, k: int, ef: int, mode: int = MODE_PLAIN, mlp=None, counters: bool = False,
-               out=None, stream=None):
+               out=None, stream=None, no_alloc: bool = False):
         """K-NN-SEARCH (Alg. 5) of every row of ``queries`` (a float32 CUDA tensor [n][dim]).
 
         Returns (ids int32 [n][k], dists float32 [n][k]) and, with ``counters``,
         a uint32-valued int32 tensor [n][4] of work counters.  ``out`` may give
-        preallocated (ids, dists[, counters]) tensors.
+        preallocated (ids, dists[, counters]) tensors.  ``no_alloc`` calls
+        ``hnsw_search_batch_noalloc`` (the library allocates nothing; with
+        ``out`` given, neither does this method).
         """
         import torch
 
@@ -210,9 +214,10 @@ class Index:
             ids, dists = out[0], out[1]
             cnt = out[2] if counters else None
         mlp_ptr = C.c_void_p(mlp.handle.value) if mlp is not None else None
-        code = lib().hnsw_search_batch_ex(self._h, _dptr(q), n, k, ef, mode, mlp_ptr, _dptr(ids), _dptr(dists),
-                                          _dptr(cnt) if cnt is not None else None, _stream_ptr(stream))
-        _check("hnsw_search_batch_ex", code)
+        fn = "hnsw_search_batch_noalloc" if no_alloc else "hnsw_search_batch_ex"
+        code = getattr(lib(), fn)(self._h, _dptr(q), n, k, ef, mode, mlp_ptr, _dptr(ids), _dptr(dists),
+                                  _dptr(cnt) if cnt is not None else None, _stream_ptr(stream))
+        _check(fn, code)
         return (ids, dists, cnt) if counters else (ids, dists)
 
 

@@ -255,8 +255,9 @@ hnsw_status hnsw_index_info(const hnsw_index *index, uint64_t out[9]) {
 
 static hnsw_status search_impl(const hnsw_index *index, const float *queries, uint32_t n, uint32_t k, uint32_t ef,
                                int mode, const void *mlp, int32_t *ids_out, float *dists_out, uint32_t *counters,
-                               float *trace, void *stream) {
+                               float *trace, void *stream, bool no_alloc = false) {
     if (!index) return HNSW_ERR_INVALID_ARG;
+    if (no_alloc && n > HNSW_NOALLOC_MAX_QUERIES) return HNSW_ERR_UNSUPPORTED;
     if (k == 0 || ef == 0) return HNSW_ERR_INVALID_ARG;
     if (mode < HNSW_MODE_PLAIN || mode > HNSW_MODE_LEARNED) return HNSW_ERR_UNSUPPORTED;
     if (mode == HNSW_MODE_BF16 && !index->ix.vbf16) return HNSW_ERR_INVALID_ARG;
@@ -286,6 +287,7 @@ static hnsw_status search_impl(const hnsw_index *index, const float *queries, ui
     if (mode == HNSW_MODE_LEARNED) a.mlp = static_cast<const hnsw_mlp *>(mlp)->net;
     a.ckpt_trace = mode == HNSW_MODE_LEARNED ? trace : nullptr;
     a.ht_slots = hnsw::visited_slots(a, mode == HNSW_MODE_LEARNED);
+    a.no_alloc = no_alloc;
     if (hnsw::launch_search(index->ix, a, static_cast<hipStream_t>(stream)) != hipSuccess) {
         (void)hipGetLastError();
         return HNSW_ERR_DEVICE;
@@ -297,6 +299,12 @@ hnsw_status hnsw_search_batch_ex(const hnsw_index *index, const float *queries, 
                                  int mode, const void *mlp, int32_t *ids_out, float *dists_out, uint32_t *counters,
                                  void *stream) {
     return search_impl(index, queries, n, k, ef, mode, mlp, ids_out, dists_out, counters, nullptr, stream);
+}
+
+hnsw_status hnsw_search_batch_noalloc(const hnsw_index *index, const float *queries, uint32_t n, uint32_t k,
+                                      uint32_t ef, int mode, const void *mlp, int32_t *ids_out, float *dists_out,
+                                      uint32_t *counters, void *stream) {
+    return search_impl(index, queries, n, k, ef, mode, mlp, ids_out, dists_out, counters, nullptr, stream, true);
 }
 
 hnsw_status hnsw_search_learned_trace(const hnsw_index *index, const float *queries, uint32_t n, uint32_t k,

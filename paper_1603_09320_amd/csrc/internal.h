@@ -61,6 +61,7 @@ struct SearchArgs {
     uint32_t *sched_up;      // [nq][2] distance evaluations and expansions above layer 0
     uint32_t *sched_order;   // [nq] query of each layer-0 wave
     int sched;               // 0: one kernel; 1: scheduled when the batch exceeds the resident waves; 2: always
+    bool no_alloc;           // the caller cannot allocate: workspace from the static scratch array, no timing events
 };
 
 // Vector tile shape for a dimension: G lanes share one vector, each lane
@@ -88,8 +89,9 @@ size_t search_lds_bytes(const SearchArgs &a, bool learned);
 // launches).  Per (index, mode, ef, batch-size octave) it times one call of
 // each form with events read back without blocking, then keeps the faster;
 // until then it answers true.  *ev_start / *ev_end, when set, are to be
-// recorded on the stream around the batch's launches.  Called with the
-// workspace mutex held.
+// recorded on the stream around the batch's launches.  With a.no_alloc it
+// only reads a decision already made (creating no record and no event) and
+// otherwise answers true.  Called with the workspace mutex held.
 bool tuned_form(const DevIndex &ix, const SearchArgs &a, hipStream_t stream, hipEvent_t *ev_start,
                 hipEvent_t *ev_end);
 // Drops the timing records of an index that is being freed.

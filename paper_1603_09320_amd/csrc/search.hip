@@ -180,6 +180,7 @@ bool tuned_form(const DevIndex &ix, const SearchArgs &a, hipStream_t stream, hip
     FormTune *t = nullptr;
     for (FormTune &x : g_tune)
         if (x.index == ix.uid && x.device == dev && x.mode == a.mode && x.ef == a.ef && x.octave == octave) t = &x;
+    if (a.no_alloc) return t && t->phase == 3 ? t->sched : true;
     if (!t) {
         if (g_tune.size() >= kTuneCap) {
             // make room: drop the older half of the decided records (records
@@ -239,6 +240,42 @@ bool tuned_form(const DevIndex &ix, const SearchArgs &a, hipStream_t stream, hip
     }
 }
 
+// Workspace of the allocation-free entry point (hnsw_search_batch_noalloc):
+// the scheduled launches' 20 bytes per query for up to
+// HNSW_NOALLOC_MAX_QUERIES queries, held by every device the library runs on
+// until the process ends.  Its device address is taken once per device
+// (hipGetSymbolAddress, with that device current); host code passes only that
+// address to kernels.  Every element is written by the descent and order
+// kernels before it is read, so nothing needs clearing between calls; calls
+// that overlap on one device share it and race.
+constexpr size_t kNoAllocScratchBytes = static_cast<size_t>(HNSW_NOALLOC_MAX_QUERIES) * 20;
+static __device__ __align__(256) uint8_t scratch[kNoAllocScratchBytes];
+
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+uint8_t *g_scratch_ptr[kMaxDevices] = {};
+
+// Device address of `scratch` on the current device (null on failure).
+uint8_t *noalloc_scratch() {
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kMaxDevices) {
+        (void)hipGetLastError();
+        return nullptr;
+    }
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void *ptr = nullptr;
+        if (hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)) != hipSuccess || !ptr) {
+            (void)hipGetLastError();
+            return nullptr;
+        }
+        g_scratch_ptr[dev] = static_cast<uint8_t *>(ptr);
+    }
+    return g_scratch_ptr[dev];
+}
+}  // namespace
+
 // HNSW_WIDE_GATHERS=1 sends every launch through the 64-bit addressed kernels
 // (they are otherwise taken only for stores above 2 GiB), so that tests can
 // check them on small indices.  HNSW_SCHEDULE=0 keeps every batch in one
@@ -257,7 +294,14 @@ hipError_t launch_search(const DevIndex &ix, const SearchArgs &a0, hipStream_t s
     if (a.sched == 2 || (a.sched == 1 && a.nq > 256)) {
         lk.lock();
         const size_t n = a.nq;
-        uint8_t *p = sched_buffer(stream, n * 20);
+        uint8_t *p;
+        if (a.no_alloc) {
+            if (n * 20 > kNoAllocScratchBytes) return hipErrorInvalidValue;
+            p = noalloc_scratch();
+            if (!p) return hipErrorInvalidSymbol;
+        } else {
+            p = sched_buffer(stream, n * 20);
+        }
         if (p) {
             a.sched_start = reinterpret_cast<uint64_t *>(p);
             a.sched_up = reinterpret_cast<uint32_t *>(p + n * 8);

@@ -75,16 +75,21 @@ def row_bytes(mode: int, dim: int) -> int:
     return {0: 4 * dim, 1: 2 * dim, 2: dim + 4, 3: 4 * dim}[mode]
 
 
-def algorithmic_bytes(cnt, graph, K, mode, ef):
+def algorithmic_bytes(cnt, graph, K, mode, ef, includes_rerank):
     """Bytes the method must move per step: one adjacency row per expansion
     (layer 0: 4*Mmax0, upper layers: 4*Mmax), one vector per distance
     evaluation, the query and the K results; the low-precision forms add one
-    fp32 row per re-ranked element of W."""
+    fp32 row per re-ranked element of W.  ``cnt`` rows: distance evaluations
+    (all layers), expansions (all layers), distance evaluations on layer 0,
+    expansions on layer 0 -- the oracle's counts (exact visited sets) or the
+    GPU's (which also count ids scored again after the visited table forgot
+    them, descent neighbours scored again on each hop and, with
+    ``includes_rerank``, the re-ranked elements)."""
     c = cnt.astype(np.int64)
     dim = graph["dim"]
     exp_u = c[:, 1] - c[:, 3]
     rer = np.minimum(ef, graph["n"]) if mode in (1, 2) else 0
-    trav = c[:, 0] - rer
+    trav = c[:, 0] - (rer if includes_rerank else 0)
     per_q = (c[:, 3] * 4 * graph["Mmax0"] + exp_u * 4 * graph["Mmax"] + trav * row_bytes(mode, dim)
              + rer * 4 * dim + 4 * dim + 8 * K)
     return int(per_q.sum())
@@ -104,23 +109,66 @@ def load_traffic(kernel_hash: str, workload: str, ef: int):
     return t.get("hbm_bytes_per_launch")
 
 
-def cpu_baseline(graph, X, Q, K, ef, seconds=15.0):
-    """The oracle's K-NN-SEARCH on the host cores over a bounded query sample."""
+def cpu_model() -> str:
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def host_cores() -> int:
+    try:
+        return len(os.sched_getaffinity(0))
+    except AttributeError:
+        return os.cpu_count() or 1
+
+
+def cpu_baseline(G, Q, K, ef, seconds=10.0):
+    """The oracle's K-NN-SEARCH on the host over bounded query samples: one
+    thread (the paper's regime) and every core the process may use."""
+    out = {}
+    for leg, threads in (("one_thread", 1), ("all_cores", host_cores())):
+        n = min(len(Q), 32 * threads)
+        t0 = time.time()
+        G.search(Q[:n], K, ef, nthreads=threads)
+        dt = time.time() - t0
+        n2 = int(min(len(Q), max(n, n * seconds / max(dt, 1e-3) * 0.5)))
+        if n2 > n:
+            t0 = time.time()
+            G.search(Q[:n2], K, ef, nthreads=threads)
+            dt, n = time.time() - t0, n2
+        out[leg] = {"value": round(n / dt, 2), "cores": threads, "queries": n, "seconds": round(dt, 2)}
+        log(f"[bench] oracle {leg}: {out[leg]}")
+    a = out["all_cores"]
+    return {"value": a["value"], "unit": "queries/s", "cores": a["cores"], "kind": "oracle",
+            "sample": f"first {a['queries']} of {len(Q)} queries, K={K}, ef={ef}, same graph; one thread: "
+                      f"{out['one_thread']['value']} queries/s over the first {out['one_thread']['queries']}",
+            "one_thread": out["one_thread"]["value"], "cpu_model": cpu_model()}
+
+
+def oracle_counts(G, X, Q, K, ef, mode, mlp_file=None):
+    """The oracle's per-query work counters at the same graph, queries and ef
+    (untimed; the exact visited set of Alg. 2): plain search, the
+    low-precision mirror, or the learned search with the same net."""
     import oracle
 
-    G = oracle.Graph.from_packed(X, graph)
-    threads = os.cpu_count() or 1
-    n = min(len(Q), 64 * threads)
-    t0 = time.time()
-    G.search(Q[:n], K, ef, nthreads=threads)
-    dt = time.time() - t0
-    n2 = int(min(len(Q), max(n, n * seconds / max(dt, 1e-3) * 0.5)))
-    if n2 > n:
-        t0 = time.time()
-        G.search(Q[:n2], K, ef, nthreads=threads)
-        dt, n = time.time() - t0, n2
-    return {"value": round(n / dt, 2), "unit": "queries/s", "cores": threads, "kind": "oracle",
-            "sample": f"first {n} of {len(Q)} queries, K={K}, ef={ef}, same graph"}
+    threads = host_cores()
+    if mode == 3:
+        z = np.load(mlp_file)
+        r = G.search_learned(Q, K, ef, net=oracle.bf16_net(z["params"]), tau=float(z["tau"]), jmax=int(z["jmax"]),
+                             T=int(z["period"]), max_ckpt=int(z["max_ckpt"]), nthreads=threads)
+        return r["counters"]
+    if mode in (1, 2):
+        _, dec, sc = (oracle.quantize_bf16 if mode == 1 else oracle.quantize_fp8)(X)
+        G.set_lowp(dec, sc)
+    try:
+        _, _, cnt = G.search(Q, K, ef, nthreads=threads, counters=True)
+    finally:
+        G.set_lowp(None, None)
+    return cnt
 
 
 class Runner:
@@ -276,7 +324,9 @@ def main():
     ap.add_argument("--forms", default="plain,bf16,fp8,learned",
                     help="comma list of plain,bf16,fp8,learned (learned needs a trained net file)")
     ap.add_argument("--target-recall", type=float, default=0.95)
-    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-cpu-baseline", action="store_true",
+                    help="skip the oracle legs (host timing and the oracle's work counts)")
+    ap.add_argument("--no-k1", action="store_true", help="skip the K = 1 measurement")
     ap.add_argument("--no-serve", action="store_true", help="skip the serving-loop measurement")
     ap.add_argument("--no-glove", action="store_true", help="skip the learned-rule measurement on glove_like")
     ap.add_argument("--copy-probe-bytes", type=int, default=0,
@@ -320,9 +370,9 @@ def main():
     log(f"[bench] brute-force ground truth: {nq} queries in {bf_ms:.1f} ms")
 
     mlp = None
+    mpath = os.path.join(ROOT, "paper_1603_09320_amd", "nets", f"{a.workload}.mlp.npz")
     forms = [f for f in a.forms.split(",") if f]
     if "learned" in forms:
-        mpath = os.path.join(ROOT, "paper_1603_09320_amd", "nets", f"{a.workload}.mlp.npz")
         if os.path.exists(mpath) and hasattr(hnsw, "Mlp"):
             mlp = hnsw.Mlp.load(mpath)
         else:
@@ -330,6 +380,7 @@ def main():
     run = Runner(index, q, X, Q, K, gt_d64, graph["metric"], stream, mlp)
     mode_of = {"plain": 0, "bf16": 1, "fp8": 2, "learned": 3}
     results = {}
+    gpu_cnt = {}
     for form in forms:
         mode = mode_of[form]
         if mode in (1, 2):
@@ -344,18 +395,29 @@ def main():
         _, _, cnt = run.search(ef, mode, counters=True)
         torch.cuda.synchronize()
         cnt = cnt.cpu().numpy().astype(np.uint32)
+        gpu_cnt[form] = cnt
         ms, kern_ms = run.time(ef, mode, a.steps, a.warmup)
-        alg = algorithmic_bytes(cnt, graph, K, mode, ef)
+        alg = algorithmic_bytes(cnt, graph, K, mode, ef, includes_rerank=True)
         c = cnt.astype(np.float64)
         results[form] = {"ef": ef, "recall": round(rec, 5), "qps": round(nq / (ms / 1000.0), 1),
                          "ms_per_step": round(ms, 4), "kernel_ms": round(kern_ms, 4),
-                         "algorithmic_GBs": round(alg / (kern_ms / 1000.0) / 1e9, 1),
-                         "bytes_per_query": round(alg / nq, 1),
-                         "dist_evals_per_query": round(float(c[:, 0].mean()), 2),
+                         "gpu_count_bytes_per_step": alg,
+                         "gpu_count_GBs": round(alg / (kern_ms / 1000.0) / 1e9, 1),
+                         "gpu_dist_evals_per_query": round(float(c[:, 0].mean()), 2),
                          "expansions_per_query": round(float(c[:, 1].mean()), 2),
                          "layer0_expansions_per_query": round(float(c[:, 3].mean()), 2),
                          "sweep": curve}
         log(f"[bench] {form}: {results[form]}")
+
+    # the K = 1 half of the workload: plain fp32, recall@1 against the exact nearest neighbour
+    k1 = None
+    if not a.no_k1 and "plain" in forms:
+        run1 = Runner(index, q, X, Q, 1, gt_d64[:, :1], graph["metric"], stream)
+        ef1, rec1, curve1 = run1.sweep(0, EF_SWEEP, a.target_recall)
+        ms1, kern1 = run1.time(ef1, 0, a.steps, a.warmup)
+        k1 = {"ef": ef1, "recall_at_1": round(rec1, 5), "qps": round(nq / (ms1 / 1000.0), 1),
+              "ms_per_step": round(ms1, 4), "kernel_ms": round(kern1, 4), "sweep": curve1}
+        log(f"[bench] plain K=1: {k1}")
 
     if a.copy_probe_bytes:
         src = torch.ones(a.copy_probe_bytes // 4, dtype=torch.float32, device=dev)
@@ -375,12 +437,33 @@ def main():
 
     head = results.get("plain") or next(iter(results.values()))
     cpu = None
+    counts = "gpu"
     if not a.no_cpu_baseline:
-        cpu = cpu_baseline(graph, X, Q, K, head["ef"])
+        import oracle
+
+        G = oracle.Graph.from_packed(X, graph)
+        cpu = cpu_baseline(G, Q, K, head["ef"])
         log(f"[bench] cpu baseline: {cpu}")
+        # algorithmic bytes from the oracle's counts (exact visited sets) at each form's ef
+        for form, r in results.items():
+            oc = oracle_counts(G, X, Q, K, r["ef"], mode_of[form], mpath if form == "learned" else None)
+            alg = algorithmic_bytes(oc, graph, K, mode_of[form], r["ef"], includes_rerank=False)
+            oc = oc.astype(np.float64)
+            r["bytes_per_step"] = alg
+            r["algorithmic_GBs"] = round(alg / (r["kernel_ms"] / 1000.0) / 1e9, 1)
+            r["dist_evals_per_query"] = round(float(oc[:, 0].mean()), 2)
+            r["oracle_expansions_equal"] = bool(np.array_equal(oc[:, 1], gpu_cnt[form][:, 1].astype(np.float64)))
+            log(f"[bench] {form}: oracle counts {r['dist_evals_per_query']} distance evaluations per query, "
+                f"{r['algorithmic_GBs']} GB/s algorithmic")
+        counts = "oracle"
+        del G
+    if counts == "gpu":
+        for r in results.values():
+            r["bytes_per_step"] = r["gpu_count_bytes_per_step"]
+            r["algorithmic_GBs"] = r["gpu_count_GBs"]
     khash = kernel_source_hash()
     achieved = head["algorithmic_GBs"]
-    alg_launch = int(round(head["bytes_per_query"] * nq))
+    traffic = load_traffic(khash, a.workload, head["ef"])
     out = {
         "metric": METRIC,
         "value": head["qps"],
@@ -400,11 +483,15 @@ def main():
                    "efConstruction": graph["efC"]},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(achieved / HBM_PEAK_GBS, 4),
-                     "traffic": load_traffic(khash, a.workload, head["ef"]),
+                     "traffic": traffic,
+                     "traffic_kind": "L2-to-fabric bytes per call (rocprofv3 FETCH_SIZE + WRITE_SIZE, scaled by a "
+                                     "plain copy); they include hits in the Infinity Cache (MALL)",
                      "kernel": "search call: descent_kernel + order_kernel + layer0_kernel (one stream, "
                                "event-timed together)", "kernel_ms": head["kernel_ms"],
-                     "algorithmic_bytes_per_launch": alg_launch, "kernel_hash": khash},
+                     "algorithmic_bytes_per_launch": head["bytes_per_step"], "counts": counts,
+                     "kernel_hash": khash},
         "forms": results,
+        "plain_k1": k1,
         "bruteforce": {"ms": round(bf_ms, 3), "queries": nq,
                        "tflops": round(2.0 * nq * graph["n"] * graph["dim"] / (bf_ms / 1000.0) / 1e12, 2)},
         "cpu_baseline": cpu,

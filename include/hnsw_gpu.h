@@ -97,8 +97,68 @@ hnsw_status hnsw_index_upload(const hnsw_graph_desc *g, void *stream, hnsw_index
 void hnsw_index_free(hnsw_index *index);
 
 /* Read back index properties: out[0..7] = n, dim, metric, M, Mmax, Mmax0,
- * max_level, entry_point; out[8] = device bytes held. */
-hnsw_status hnsw_index_info(const hnsw_index *index, uint64_t out[9]);
+ * max_level, entry_point; out[8] = device bytes held; out[9] = rows of the
+ * upper layers (n_upper_rows). */
+hnsw_status hnsw_index_info(const hnsw_index *index, uint64_t out[10]);
+
+/*
+ * Copy the graph of an index back to the host in the packed form of
+ * hnsw_graph_desc (host buffers, synchronous): levels [n], adj0 [n][Mmax0],
+ * upper_off [n], adjU [n_upper_rows][Mmax] (may be NULL when there are none).
+ * Sizes from hnsw_index_info.  For graphs built on the device, so that they
+ * can be saved, inspected or searched elsewhere.
+ */
+hnsw_status hnsw_index_export(const hnsw_index *index, uint8_t *levels, uint32_t *adj0, int32_t *upper_off,
+                              uint32_t *adjU);
+
+/*
+ * Graph construction on the device: INSERT (Alg. 1) of elements 0..n-1 in id
+ * order, in batches that run with few synchronisation points (Sec. 4.1 notes
+ * that construction parallelises; the batch schedule below makes the result
+ * deterministic).  Every element of a batch searches the graph as it stood
+ * before the batch: greedy descent (ef = 1) above its level l, then for each
+ * layer lc = min(L, l)..0 SEARCH-LAYER (Alg. 2) with efC candidates entered
+ * from all of the previous layer's W, and SELECT-NEIGHBORS-HEURISTIC (Alg. 4)
+ * for M links.  The reverse links are then merged per receiving element: a
+ * list over Mmax (Mmax0 on layer 0) is selected again by the heuristic from
+ * its element over its links and all new ones.  Element 0 becomes the enter
+ * point with no links; an element above the current top layer is inserted
+ * alone and becomes the enter point.  With batch_div >= n every batch holds
+ * one element and the graph is that of the sequential INSERT.
+ * Levels: l = floor(-ln(U) * mL), U = (r + 1) * 2^-53 with r the top 53 bits
+ * of splitmix64(seed XOR i).
+ *   vectors   host fp32 [n][dim] (copied; the caller may free it after).
+ * The call synchronises `stream`; it allocates the index (as
+ * hnsw_index_upload) and a temporary workspace of about
+ * (batch_max + upper rows of a batch) * M * 48 bytes, freed before it returns.
+ */
+typedef struct {
+    uint32_t M;          /* links of a new element on each layer (Alg. 1)        */
+    uint32_t Mmax;       /* list cap on layers >= 1                               */
+    uint32_t Mmax0;      /* list cap on layer 0                                   */
+    uint32_t efC;        /* efConstruction (raised to M), <= HNSW_EF_MAX           */
+    double mL;           /* level normalisation, e.g. 1 / ln(M)                    */
+    uint64_t seed;       /* level draw                                             */
+    int keep_pruned;     /* Alg. 4 keepPrunedConnections                           */
+    uint32_t batch_div;  /* a batch holds at most (elements inserted) / batch_div  */
+    uint32_t batch_max;  /* and at most this many elements (0: 65,536)             */
+} hnsw_build_params;
+hnsw_status hnsw_index_build(const float *vectors, uint32_t n, uint32_t dim, int metric,
+                             const hnsw_build_params *params, void *stream, hnsw_index **out);
+
+/*
+ * The device's SELECT-NEIGHBORS-HEURISTIC (Alg. 4, extendCandidates off) on
+ * explicit candidate lists, as graph construction runs it: for base element
+ * base[i] of the index and candidates cand[i][0..nc) (element ids; 0xFFFFFFFF
+ * entries are skipped), the distances to the base are computed, candidates
+ * are taken in (distance, id) order and kept while their distance to the base
+ * is smaller than their distance to every element kept before; keep_pruned
+ * fills up to Mk with the discarded ones, nearest first.  out[i][Mk] receives
+ * the kept ids in that order, 0xFFFFFFFF padded.  All pointers device memory;
+ * nc <= 1024, Mk <= 64.
+ */
+hnsw_status hnsw_select_heuristic(const hnsw_index *index, const uint32_t *base, const uint32_t *cand, uint32_t nb,
+                                  uint32_t nc, uint32_t Mk, int keep_pruned, uint32_t *out, void *stream);
 
 /*
  * Batched K-NN-SEARCH (Alg. 5), one query per wavefront.

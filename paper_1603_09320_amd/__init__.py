@@ -42,6 +42,14 @@ class GraphDesc(C.Structure):
     ]
 
 
+class BuildParams(C.Structure):
+    _fields_ = [
+        ("M", C.c_uint32), ("Mmax", C.c_uint32), ("Mmax0", C.c_uint32), ("efC", C.c_uint32),
+        ("mL", C.c_double), ("seed", C.c_uint64), ("keep_pruned", C.c_int),
+        ("batch_div", C.c_uint32), ("batch_max", C.c_uint32),
+    ]
+
+
 # name -> (restype, argtypes); the exported symbols of include/hnsw_gpu.h
 _vp, _u32, _u64, _i32 = C.c_void_p, C.c_uint32, C.c_uint64, C.c_int
 SIGNATURES = {
@@ -49,6 +57,9 @@ SIGNATURES = {
     "hnsw_index_upload": (C.c_int, [C.POINTER(GraphDesc), _vp, C.POINTER(_vp)]),
     "hnsw_index_free": (None, [_vp]),
     "hnsw_index_info": (C.c_int, [_vp, _vp]),
+    "hnsw_index_export": (C.c_int, [_vp, _vp, _vp, _vp, _vp]),
+    "hnsw_index_build": (C.c_int, [_vp, _u32, _u32, _i32, C.POINTER(BuildParams), _vp, C.POINTER(_vp)]),
+    "hnsw_select_heuristic": (C.c_int, [_vp, _vp, _vp, _u32, _u32, _u32, _i32, _vp, _vp]),
     "hnsw_search_batch": (C.c_int, [_vp, _vp, _u32, _u32, _u32, _vp, _vp, _vp]),
     "hnsw_search_batch_ex": (C.c_int, [_vp, _vp, _u32, _u32, _u32, _i32, _vp, _vp, _vp, _vp, _vp]),
     "hnsw_search_batch_noalloc": (C.c_int, [_vp, _vp, _u32, _u32, _u32, _i32, _vp, _vp, _vp, _vp, _vp]),
@@ -134,14 +145,48 @@ class Index:
     def from_file(cls, path: str, vectors: np.ndarray, stream=None) -> "Index":
         return cls(graphfile.read(path), vectors, stream)
 
+    @classmethod
+    def build(cls, vectors: np.ndarray, metric: int = HNSW_L2SQ, M: int = 16, Mmax=None, Mmax0=None, efC: int = 200,
+              mL=None, seed: int = 1, keep_pruned: bool = False, batch_div: int = 16, batch_max: int = 65536,
+              stream=None) -> "Index":
+        """Graph construction on the GPU (``hnsw_index_build``): INSERT in batches of at
+        most 1/batch_div of the elements inserted so far (batch_max at most)."""
+        import math
+
+        X = np.ascontiguousarray(vectors, dtype=np.float32)
+        n, dim = X.shape
+        p = BuildParams(M, M if Mmax is None else Mmax, 2 * M if Mmax0 is None else Mmax0, efC,
+                        1.0 / math.log(M) if mL is None else mL, seed, int(keep_pruned), batch_div, batch_max)
+        h = C.c_void_p()
+        _check("hnsw_index_build", lib().hnsw_index_build(_np(X), n, dim, metric, C.byref(p), _stream_ptr(stream),
+                                                          C.byref(h)))
+        self = cls.__new__(cls)
+        self._h = h
+        self._arrays = None
+        self.n, self.dim, self.metric = n, dim, metric
+        return self
+
+    def export(self) -> dict:
+        """The graph in packed form (``hnsw_index_export``), keys as the graph files use."""
+        inf = self.info()
+        n, rows = inf["n"], inf["rows"]
+        lv = np.empty(n, dtype=np.uint8)
+        a0 = np.empty((n, inf["Mmax0"]), dtype=np.uint32)
+        uo = np.empty(n, dtype=np.int32)
+        aU = np.empty((max(rows, 1), inf["Mmax"]), dtype=np.uint32)
+        _check("hnsw_index_export", lib().hnsw_index_export(self._h, _np(lv), _np(a0), _np(uo), _np(aU)))
+        d = dict(inf)
+        d.update(levels=lv, adj0=a0, upper_off=uo, adjU=aU[:rows])
+        return d
+
     @property
     def handle(self):
         return self._h
 
     def info(self) -> dict:
-        out = np.zeros(9, dtype=np.uint64)
+        out = np.zeros(10, dtype=np.uint64)
         _check("hnsw_index_info", lib().hnsw_index_info(self._h, _np(out)))
-        keys = ["n", "dim", "metric", "M", "Mmax", "Mmax0", "max_level", "entry_point", "device_bytes"]
+        keys = ["n", "dim", "metric", "M", "Mmax", "Mmax0", "max_level", "entry_point", "device_bytes", "rows"]
         return {k: int(v) for k, v in zip(keys, out)}
 
     def search_learned_trace(self, queries, k: int, ef: int, mlp, stream=None):
@@ -365,6 +410,20 @@ def bruteforce(index: Index, queries, k: int, stream=None):
     _check("hnsw_bruteforce_knn", lib().hnsw_bruteforce_knn(index.handle, _dptr(q), n, k, _dptr(ids), _dptr(d),
                                                             _stream_ptr(stream)))
     return ids, d
+
+
+def select_heuristic(index: Index, base, cand, Mk: int, keep_pruned: bool = False, stream=None):
+    """The device's SELECT-NEIGHBORS-HEURISTIC on explicit lists (``hnsw_select_heuristic``):
+    base int32 [nb], cand int32 [nb][nc] (-1 skipped) CUDA tensors; returns int32 [nb][Mk], -1 padded."""
+    import torch
+
+    b = base.to(torch.int32).contiguous()
+    c = cand.to(torch.int32).contiguous()
+    out = torch.empty((b.shape[0], Mk), dtype=torch.int32, device=b.device)
+    _check("hnsw_select_heuristic", lib().hnsw_select_heuristic(index.handle, _dptr(b), _dptr(c), b.shape[0],
+                                                                c.shape[1], Mk, int(keep_pruned), _dptr(out),
+                                                                _stream_ptr(stream)))
+    return out
 
 
 def search_batch(index: Index, queries, k: int, ef: int, stream=None):

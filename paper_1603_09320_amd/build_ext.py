@@ -10,7 +10,8 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libhnsw_gpu.so")
 OBJ = os.path.join(HERE, "_build")
-SOURCES = ["api.hip", "search.hip", "search_wide.hip", "bruteforce.hip", "quantize.hip", "mlp.hip", "serve.hip"]
+SOURCES = ["api.hip", "search.hip", "search_wide.hip", "bruteforce.hip", "quantize.hip", "mlp.hip", "serve.hip",
+           "build.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [
     "--offload-arch=gfx950",

@@ -234,6 +234,8 @@ hnsw_status hnsw_index_upload(const hnsw_graph_desc *g, void *stream, hnsw_index
     (void)hipGetDevice(&h->device);
     h->bytes = al.bytes;
     h->allocations = al.got;
+    h->levels.assign(g->levels, g->levels + g->n);
+    h->n_upper_rows = g->n_upper_rows;
     *out = h;
     return HNSW_OK;
 }
@@ -245,11 +247,29 @@ void hnsw_index_free(hnsw_index *index) {
     delete index;
 }
 
-hnsw_status hnsw_index_info(const hnsw_index *index, uint64_t out[9]) {
+hnsw_status hnsw_index_info(const hnsw_index *index, uint64_t out[10]) {
     if (!index || !out) return HNSW_ERR_INVALID_ARG;
     const hnsw::DevIndex &x = index->ix;
-    const uint64_t v[9] = {x.n, x.dim, x.metric, index->M, x.Mmax, x.Mmax0, x.max_level, x.entry, index->bytes};
+    const uint64_t v[10] = {x.n,         x.dim,   x.metric,     index->M, x.Mmax, x.Mmax0,
+                            x.max_level, x.entry, index->bytes, index->n_upper_rows};
     memcpy(out, v, sizeof(v));
+    return HNSW_OK;
+}
+
+hnsw_status hnsw_index_export(const hnsw_index *index, uint8_t *levels, uint32_t *adj0, int32_t *upper_off,
+                              uint32_t *adjU) {
+    if (!index || !levels || !adj0 || !upper_off || (index->n_upper_rows && !adjU)) return HNSW_ERR_INVALID_ARG;
+    const hnsw::DevIndex &x = index->ix;
+    memcpy(levels, index->levels.data(), x.n);
+    bool ok = hipMemcpy(adj0, x.adj0, static_cast<size_t>(x.n) * x.Mmax0 * 4, hipMemcpyDeviceToHost) == hipSuccess;
+    ok = ok && hipMemcpy(upper_off, x.uoff, static_cast<size_t>(x.n) * 4, hipMemcpyDeviceToHost) == hipSuccess;
+    if (index->n_upper_rows)
+        ok = ok && hipMemcpy(adjU, x.adjU, static_cast<size_t>(index->n_upper_rows) * x.Mmax * 4,
+                             hipMemcpyDeviceToHost) == hipSuccess;
+    if (!ok) {
+        (void)hipGetLastError();
+        return HNSW_ERR_DEVICE;
+    }
     return HNSW_OK;
 }
 

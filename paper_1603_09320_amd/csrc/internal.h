@@ -132,6 +132,8 @@ struct hnsw_index {
     int device;
     uint64_t bytes;
     std::vector<void *> allocations;
+    std::vector<uint8_t> levels;  // [n] host copy of the element levels
+    uint64_t n_upper_rows;        // rows of adjU
 };
 
 namespace hnsw {

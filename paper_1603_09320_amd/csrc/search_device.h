@@ -609,7 +609,7 @@ __device__ __forceinline__ float bf16_half(const uint4 &p, int h) {
 }
 
 // Returns true when the rule stops the search; may lower ef and wsize.
-__device__ bool learned_checkpoint(const WaveLds &s, const DevMlp &net, LearnState &st, uint32_t n_exp0,
+[[maybe_unused]] __device__ bool learned_checkpoint(const WaveLds &s, const DevMlp &net, LearnState &st, uint32_t n_exp0,
                                    uint32_t K, int cursor, uint32_t &ef, uint32_t &wsize, float *trace) {
     // The lane id is re-read here behind an empty asm barrier: addresses the
     // checkpoint derives from it are then formed inside the checkpoint instead

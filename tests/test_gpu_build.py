@@ -1,0 +1,178 @@
+"""Graph construction on the GPU (hnsw_index_build), through the C ABI.
+
+- With batches of one element the device build is INSERT (Alg. 1) step for
+  step: every list of every layer, the levels, the enter point and the top
+  layer equal the oracle's sequential INSERT.
+- The device heuristic (Alg. 4) on explicit candidate lists equals the
+  oracle's, with and without keepPrunedConnections.
+- Batched builds give valid graphs (degree caps, no self-links or repeats,
+  layer membership) whose search recall is close to that of the oracle-built
+  graph at the same ef, and the GPU search on a device-built graph equals the
+  oracle's search on the exported graph.
+"""
+import os
+
+import numpy as np
+import pytest
+
+import oracle
+import synthdata
+from tests import parity
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+@pytest.fixture(scope="module")
+def hnsw():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_1603_09320_amd as h
+
+    h.lib()
+    return h
+
+
+def _lists(p):
+    out = {}
+    for i in range(p["n"]):
+        out[(0, i)] = sorted(int(v) for v in p["adj0"][i] if v != 0xFFFFFFFF)
+        for lc in range(1, int(p["levels"][i]) + 1):
+            row = p["adjU"][p["upper_off"][i] + lc - 1]
+            out[(lc, i)] = sorted(int(v) for v in row if v != 0xFFFFFFFF)
+    return out
+
+
+def _check_valid(p, M, Mmax, Mmax0):
+    n = p["n"]
+    lv = p["levels"]
+    assert lv[p["entry_point"]] == p["max_level"] == lv.max()
+    for (lc, i), lst in _lists(p).items():
+        cap = Mmax0 if lc == 0 else Mmax
+        assert len(lst) <= cap, (lc, i)
+        assert i not in lst, (lc, i)
+        assert len(set(lst)) == len(lst), (lc, i)
+        for e in lst:
+            assert 0 <= e < n and lv[e] >= lc, (lc, i, e)
+
+
+def _data(kind, n, seed):
+    g = np.random.default_rng(seed)
+    if kind == "grid":
+        return g.integers(0, 8, size=(n, 5)).astype(np.float32)
+    if kind == "sift":
+        return synthdata.base("sift_like", n)
+    if kind == "glove":
+        return synthdata.base("glove_like", n)
+    return synthdata.base("uniform16", n)
+
+
+@pytest.mark.parametrize("kind,metric,M,keep", [("uniform", oracle.L2, 8, False), ("grid", oracle.L2, 6, False),
+                                                 ("sift", oracle.L2, 8, False), ("glove", oracle.IP, 8, False),
+                                                 ("uniform", oracle.L2, 6, True)])
+def test_singleton_batches_equal_oracle_insert(hnsw, kind, metric, M, keep):
+    n = 1500
+    print(f"case GPU build, batches of one, {kind} n={n} M={M} keep_pruned={keep}", flush=True)
+    X = _data(kind, n, 3)
+    G = oracle.Graph.build(X, metric=metric, M=M, efC=30, seed=11, keep_pruned=keep)
+    want = G.packed()
+    idx = hnsw.Index.build(X, metric=metric, M=M, efC=30, seed=11, keep_pruned=keep, batch_div=n + 1)
+    got = idx.export()
+    assert np.array_equal(got["levels"], want["levels"])
+    assert got["max_level"] == want["max_level"] and got["entry_point"] == want["entry_point"]
+    assert np.array_equal(got["upper_off"], want["upper_off"]) and got["rows"] == want["rows"]
+    lg, lw = _lists(got), _lists(want)
+    bad = [k for k in lw if lg.get(k) != lw[k]]
+    assert not bad, (len(bad), bad[:5], [(lg.get(k), lw[k]) for k in bad[:3]])
+
+
+@pytest.mark.parametrize("keep", [False, True])
+def test_device_heuristic_equals_oracle(hnsw, keep):
+    print(f"case device heuristic keep_pruned={keep}", flush=True)
+    X = synthdata.base("sift_like", 4000)
+    # a graph without links: the heuristic reads only the vectors
+    Gx = oracle.Graph.from_packed(X, dict(metric=0, M=4, Mmax=4, Mmax0=8, entry_point=0, max_level=0,
+                                          levels=np.zeros(len(X), np.uint8),
+                                          adj0=np.full((len(X), 8), 0xFFFFFFFF, np.uint32),
+                                          adjU=np.zeros((0, 4), np.uint32)))
+    idx = hnsw.Index(Gx.packed(), X)
+    rng = np.random.default_rng(7)
+    nb = 300
+    for nc, Mk in ((20, 8), (200, 16), (64, 48), (700, 32)):
+        base = rng.integers(0, len(X), nb)
+        cand = np.stack([rng.choice(np.setdiff1d(np.arange(len(X)), [b]), nc, replace=False) for b in base])
+        out = hnsw.select_heuristic(idx, torch.from_numpy(base.astype(np.int32)).cuda(),
+                                    torch.from_numpy(cand.astype(np.int32)).cuda(), Mk, keep).cpu().numpy()
+        for i in range(nb):
+            want = Gx.select_heuristic(int(base[i]), cand[i], Mk, lc=0, keep_pruned=keep)
+            got = out[i][out[i] >= 0]
+            assert list(got) == [int(v) for v in want], (nc, Mk, i)
+
+
+@pytest.mark.parametrize("kind,metric,n,M,efC", [("uniform", oracle.L2, 20000, 16, 100),
+                                                  ("sift", oracle.L2, 50000, 16, 200),
+                                                  ("glove", oracle.IP, 50000, 16, 200)])
+def test_batched_build_valid_recall_and_search_parity(hnsw, kind, metric, n, M, efC):
+    print(f"case GPU batched build {kind} n={n}", flush=True)
+    X = _data(kind, n, 5)
+    Q = {"uniform": synthdata.queries("uniform16", 500), "sift": synthdata.queries("sift_like", 500),
+         "glove": synthdata.queries("glove_like", 500)}[kind]
+    idx = hnsw.Index.build(X, metric=metric, M=M, efC=efC, seed=4)
+    p = idx.export()
+    _check_valid(p, M, M, 2 * M)
+    q = torch.from_numpy(Q).cuda()
+    _, gt = hnsw.bruteforce(idx, q, 10)
+    gt = gt.cpu().numpy()
+    G = oracle.Graph.build(X, metric=metric, M=M, efC=efC, seed=4)
+    oidx = hnsw.Index(G.packed(), X)
+    Gd = oracle.Graph.from_packed(X, p)
+    for ef in (16, 64):
+        ids, ds = idx.search(q, 10, ef)
+        oi, _ = oidx.search(q, 10, ef)
+        torch.cuda.synchronize()
+        ids, ds = ids.cpu().numpy(), ds.cpu().numpy()
+        r_dev = parity.recall_at_k(ids, X, Q, gt, metric).mean()
+        r_orc = parity.recall_at_k(oi.cpu().numpy(), X, Q, gt, metric).mean()
+        print(f"  ef={ef}: recall device-built {r_dev:.4f}, oracle-built {r_orc:.4f}", flush=True)
+        assert r_dev >= r_orc - 0.02
+        # the search itself on the device-built graph: GPU = oracle
+        wi, wd = Gd.search(Q, 10, ef, nthreads=8)
+        r = parity.compare(ids, ds, wi, wd, X, Q, metric)
+        assert r["fail"] == 0 and r["exempt"] == 0
+
+
+FULL = os.path.join(ROOT, "graphs", "sift_like_1M.bin")
+
+
+@pytest.mark.skipif(not os.path.exists(FULL), reason="1M sift_like graph file not built")
+def test_device_build_sift_like_1m_recall_against_oracle_graph(hnsw):
+    """Graph quality at full size: the device-built 1M x 128 graph (M = 16,
+    Mmax0 = 32, efC = 200) against the oracle-built one, recall@10 at equal
+    ef, 10,000 queries."""
+    import time
+
+    print("case GPU build sift_like 1M", flush=True)
+    p0 = hnsw.graphfile.read(FULL)
+    X = synthdata.base("sift_like", p0["n"])
+    Q = synthdata.queries("sift_like", 10000)
+    t0 = time.time()
+    idx = hnsw.Index.build(X, M=16, efC=200, seed=2003)
+    torch.cuda.synchronize()
+    dt = time.time() - t0
+    oidx = hnsw.Index(p0, X)
+    q = torch.from_numpy(Q).cuda()
+    _, gt = hnsw.bruteforce(oidx, q, 10)
+    gt = gt.cpu().numpy()
+    print(f"  device build {dt:.1f} s (incl. upload)", flush=True)
+    p = idx.export()
+    _check_valid(p, 16, 16, 32)
+    for ef in (32, 56, 128):
+        a, _ = idx.search(q, 10, ef)
+        b, _ = oidx.search(q, 10, ef)
+        torch.cuda.synchronize()
+        ra = parity.recall_at_k(a.cpu().numpy(), X, Q, gt, 0).mean()
+        rb = parity.recall_at_k(b.cpu().numpy(), X, Q, gt, 0).mean()
+        print(f"  ef={ef}: recall device-built {ra:.4f}, oracle-built {rb:.4f}", flush=True)
+        assert ra >= rb - 0.01

@@ -12,8 +12,10 @@ Workloads (stand-ins for the paper's datasets, which are not available):
   sigma 20, rounded half-to-even and clamped to the integers 0..255, stored fp32;
   10,000 queries from the same mixture.  Stand-in for SIFT 1M (Table 1).
 * ``glove_like``  -- 1,200,000 x 100 unit vectors from 2,000 clusters with
-  Zipf(1.1) sizes, x = normalise(mu + 0.6 g / 10); inner-product metric.
-  Stand-in for GloVe 1.2M angular (Table 1).
+  Zipf(1.1) sizes, x = normalise(mu + 0.6 (s * g) / 10) with a decaying spread
+  profile s_j proportional to j^-0.25 (j = 1..100, mean square 1), so that the
+  within-cluster spread is concentrated in fewer directions than an isotropic
+  one; inner-product metric.  Stand-in for GloVe 1.2M angular (Table 1).
 * ``deep_like``   -- d=96 Gaussian mixture with 10,000 centres N(0, I) and spread
   0.5.  Stand-in for DEEP (Table 1).
 * ``uniform4``    -- 1,000,000 x 4 U[0,1).  Stand-in for the d=4 random sets
@@ -78,16 +80,26 @@ def _glove_mixture(seed: int):
     return mu, w / w.sum()
 
 
+GLOVE_SPREAD_DECAY = 0.25
+
+
+def _glove_profile() -> np.ndarray:
+    """Per-coordinate spread s_j = c * j^-0.25, scaled to mean square 1."""
+    s = np.arange(1, 101, dtype=np.float64) ** -GLOVE_SPREAD_DECAY
+    return s * np.sqrt(100.0 / np.sum(s * s))
+
+
 def _glove_points(n: int, seed: int, mix, sigma: float = 0.6) -> np.ndarray:
     mu, w = mix
     ga, gn = _rng(seed, 1), _rng(seed, 2)
     counts = ga.multinomial(n, w)
     labels = np.repeat(np.arange(len(w)), counts)
     ga.shuffle(labels)
+    prof = _glove_profile()
     out = np.empty((n, 100), dtype=np.float32)
     for s in range(0, n, CHUNK):
         e = min(n, s + CHUNK)
-        x = mu[labels[s:e]] + sigma * gn.standard_normal((e - s, 100)) / 10.0
+        x = mu[labels[s:e]] + sigma * (gn.standard_normal((e - s, 100)) * prof) / 10.0
         x /= np.linalg.norm(x, axis=1, keepdims=True)
         out[s:e] = x.astype(np.float32)
     return out

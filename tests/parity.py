@@ -61,7 +61,10 @@ def compare(gpu_ids, gpu_d, or_ids, or_d, X, Q, metric, tau=None):
 
 
 def recall_at_k(ids, X, Q, gt_d64, metric):
-    """Tie-aware recall: a returned id counts if its fp64 distance <= the true K-th."""
+    """Tie-aware recall: a returned id counts if its fp64 distance <= the true
+    K-th, within 1e-9 relative (the ground truth may sum the same terms in
+    another order)."""
     d = oracle.pair_dist(X, Q, np.asarray(ids, dtype=np.int32), metric)
     K = gt_d64.shape[1]
-    return np.sum(d <= gt_d64[:, -1:], axis=1) / K
+    dk = gt_d64[:, -1:]
+    return np.sum(d <= dk + 1e-9 * np.abs(dk) + 1e-12, axis=1) / K

@@ -171,7 +171,8 @@ def test_trained_net_gain_on_glove_like(hnsw):
         ids, cnt = ids.cpu().numpy(), cnt.cpu().numpy().astype(np.float64)
         x = X[np.clip(ids, 0, None)].astype(np.float64)
         d = 1.0 - (x * Q[:, None, :].astype(np.float64)).sum(-1)
-        return float(((d <= gt[:, 9:10]).sum(1) / 10).mean()), float(cnt[:, 3].mean())
+        dk = gt[:, 9:10]
+        return float(((d <= dk + 1e-9 * np.abs(dk) + 1e-12).sum(1) / 10).mean()), float(cnt[:, 3].mean())
 
     rec_l, exp_l = run(ef, hnsw.MODE_LEARNED, net)
     rec_p, exp_p = run(ef, hnsw.MODE_PLAIN)

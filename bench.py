@@ -322,6 +322,62 @@ def learned_glove_bench(hnsw, steps=10, warmup=2, target=0.90):
     return out
 
 
+def deep10m_bench(hnsw, steps=10, warmup=2, n=10_000_000, nq=10_000, K=10, efs=(64, 128, 256)):
+    """Low-precision traversal at its own size: 10M x 96 from the deep_like law
+    (10,000 centres N(0, I), x = c + 0.5 g), graph built on the GPU by the
+    library's batched INSERT (M = 24, Mmax0 = 48, efConstruction = 200); K =
+    10, ef in {64, 128, 256}; fp32 traversal against BF16 and FP8-E4M3
+    traversal with an exact fp32 re-rank; recall@10 against the exact brute
+    force (fp64 re-rank of a matrix-core scan)."""
+    import torch
+
+    import synthdata
+
+    t0 = time.time()
+    X = synthdata.base("deep_like", n)
+    Q = synthdata.queries("deep_like", nq)
+    gen_s = time.time() - t0
+    t0 = time.time()
+    index = hnsw.Index.build(X, M=24, efC=200, seed=4003)
+    torch.cuda.synchronize()
+    build_s = time.time() - t0
+    info = index.info()
+    log(f"[deep10m] generated in {gen_s:.1f} s, built in {build_s:.1f} s: L={info['max_level']}")
+    q = torch.from_numpy(Q).cuda()
+    stream = torch.cuda.current_stream()
+    bs, be = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    bs.record(stream)
+    _, gt = hnsw.bruteforce(index, q, K)
+    be.record(stream)
+    torch.cuda.synchronize()
+    bf_ms = bs.elapsed_time(be)
+    gt = gt.cpu().numpy()
+    run = Runner(index, q, X, Q, K, gt, 0, stream)
+    graph = {"dim": 96, "n": n, "Mmax0": info["Mmax0"], "Mmax": info["Mmax"]}
+    rows = {}
+    for form, mode in (("plain", 0), ("bf16", 1), ("fp8", 2)):
+        if mode:
+            index.add_lowp(mode)
+        for ef in efs:
+            ids, _, cnt = run.search(ef, mode, counters=True)
+            torch.cuda.synchronize()
+            rec = float(recall(ids.cpu().numpy(), X, Q, gt).mean())
+            ms, kern_ms = run.time(ef, mode, steps, warmup)
+            alg = algorithmic_bytes(cnt.cpu().numpy().astype(np.uint32), graph, K, mode, ef, includes_rerank=True)
+            r = {"recall": round(rec, 5), "qps": round(nq / (ms / 1000.0), 1), "ms_per_step": round(ms, 4),
+                 "kernel_ms": round(kern_ms, 4), "gpu_count_GBs": round(alg / (kern_ms / 1000.0) / 1e9, 1)}
+            if mode:
+                r["recall_loss_vs_fp32"] = round(rows[f"plain_ef{ef}"]["recall"] - rec, 5)
+                r["qps_vs_fp32"] = round(r["qps"] / rows[f"plain_ef{ef}"]["qps"], 4)
+            rows[f"{form}_ef{ef}"] = r
+            log(f"[deep10m] {form} ef={ef}: {r}")
+    index.close()
+    return {"workload": f"deep_like {n}x96 (10,000 centres, spread 0.5), {nq} queries, K={K}; graph built on the "
+                        f"GPU: M=24, Mmax0=48, efConstruction=200",
+            "build_s": round(build_s, 2), "bruteforce_ms": round(bf_ms, 1),
+            "counts": "gpu (the oracle does not search device-built graphs)", "results": rows}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -337,6 +393,8 @@ def main():
     ap.add_argument("--no-k1", action="store_true", help="skip the K = 1 measurement")
     ap.add_argument("--no-serve", action="store_true", help="skip the serving-loop measurement")
     ap.add_argument("--no-glove", action="store_true", help="skip the learned-rule measurement on glove_like")
+    ap.add_argument("--no-deep10m", action="store_true",
+                    help="skip the 10M x 96 low-precision measurement (graph built on the GPU)")
     ap.add_argument("--copy-probe-bytes", type=int, default=0,
                     help="also run a plain device-to-device copy of this size (counter calibration)")
     a = ap.parse_args()
@@ -442,6 +500,9 @@ def main():
     glove = None
     if not a.no_glove and a.workload == "sift_like":
         glove = learned_glove_bench(hnsw)
+    deep = None
+    if not a.no_deep10m and a.workload == "sift_like":
+        deep = deep10m_bench(hnsw)
 
     head = results.get("plain") or next(iter(results.values()))
     cpu = None
@@ -505,6 +566,7 @@ def main():
         "cpu_baseline": cpu,
         "serving": serving,
         "learned_glove_like": glove,
+        "lowp_deep_10m": deep,
     }
     print(json.dumps(out), flush=True)
     index.close()

@@ -5,6 +5,7 @@
 #include <stdlib.h>
 #include <string.h>
 
+#include <algorithm>
 #include <mutex>
 #include <utility>
 #include <vector>
@@ -55,6 +56,47 @@ void server_stopped() {
         if (h.second) (void)hipHostFree(h.first);
         else (void)hipFree(h.first);
     }
+}
+
+bool upload_rows(float *dst, uint32_t rf, const float *src, uint32_t dim, uint32_t n, hipStream_t st) {
+    if (rf == dim) {
+        if (hipMemcpyAsync(dst, src, static_cast<size_t>(n) * dim * 4, hipMemcpyHostToDevice, st) != hipSuccess) {
+            (void)hipGetLastError();
+            return false;
+        }
+        return true;
+    }
+    // two pinned staging buffers of packed rows, alternated so that packing
+    // the next chunk overlaps the copy of the previous one
+    const size_t chunk_rows = std::max<size_t>(1, (size_t{16} << 20) / (static_cast<size_t>(rf) * 4));
+    float *stage[2] = {nullptr, nullptr};
+    hipEvent_t done[2] = {nullptr, nullptr};
+    bool ok = true;
+    for (int b = 0; b < 2 && ok; ++b) {
+        void *p = nullptr;
+        ok = hipHostMalloc(&p, chunk_rows * rf * 4, hipHostMallocDefault) == hipSuccess &&
+             hipEventCreateWithFlags(&done[b], hipEventDisableTiming) == hipSuccess;
+        stage[b] = static_cast<float *>(p);
+    }
+    for (size_t r0 = 0, k = 0; ok && r0 < n; r0 += chunk_rows, ++k) {
+        const int b = static_cast<int>(k & 1);
+        if (k >= 2) ok = hipEventSynchronize(done[b]) == hipSuccess;  // the buffer's last copy has finished
+        const size_t cnt = std::min<size_t>(chunk_rows, n - r0);
+        for (size_t i = 0; i < cnt && ok; ++i) {
+            float *d = stage[b] + i * rf;
+            memcpy(d, src + (r0 + i) * dim, static_cast<size_t>(dim) * 4);
+            memset(d + dim, 0, static_cast<size_t>(rf - dim) * 4);
+        }
+        ok = ok && hipMemcpyAsync(dst + r0 * rf, stage[b], cnt * rf * 4, hipMemcpyHostToDevice, st) == hipSuccess;
+        ok = ok && hipEventRecord(done[b], st) == hipSuccess;
+    }
+    if (hipStreamSynchronize(st) != hipSuccess) ok = false;
+    for (int b = 0; b < 2; ++b) {
+        if (done[b]) (void)hipEventDestroy(done[b]);
+        if (stage[b]) host_free(stage[b]);
+    }
+    if (!ok) (void)hipGetLastError();
+    return ok;
 }
 
 bool device_count_ok() {
@@ -199,8 +241,7 @@ hnsw_status hnsw_index_upload(const hnsw_graph_desc *g, void *stream, hnsw_index
         return HNSW_ERR_OUT_OF_MEMORY;
     }
     bool ok = hipMemsetAsync(vec, 0, vec_bytes, st) == hipSuccess;
-    ok = ok && hipMemcpy2DAsync(vec, static_cast<size_t>(rf) * 4, g->vectors, static_cast<size_t>(g->dim) * 4,
-                                static_cast<size_t>(g->dim) * 4, g->n, hipMemcpyHostToDevice, st) == hipSuccess;
+    ok = ok && hnsw::upload_rows(vec, rf, g->vectors, g->dim, g->n, st);
     ok = ok && hipMemcpyAsync(adj0, g->adj0, adj0_bytes, hipMemcpyHostToDevice, st) == hipSuccess;
     ok = ok && hipMemcpyAsync(uoff, g->upper_off, uoff_bytes, hipMemcpyHostToDevice, st) == hipSuccess;
     if (adjU_bytes)

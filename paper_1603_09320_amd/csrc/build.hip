@@ -593,8 +593,7 @@ hnsw_status hnsw_index_build(const float *vectors, uint32_t n, uint32_t dim, int
         return HNSW_ERR_OUT_OF_MEMORY;
     }
     ok = hipMemsetAsync(vec, 0, vec_bytes, st) == hipSuccess;
-    ok = ok && hipMemcpy2DAsync(vec, static_cast<size_t>(rf) * 4, vectors, static_cast<size_t>(dim) * 4,
-                                static_cast<size_t>(dim) * 4, n, hipMemcpyHostToDevice, st) == hipSuccess;
+    ok = ok && upload_rows(vec, rf, vectors, dim, n, st);
     ok = ok && hipMemsetAsync(adj0, 0xFF, static_cast<size_t>(n) * pr->Mmax0 * 4, st) == hipSuccess;
     if (rows) ok = ok && hipMemsetAsync(adjU, 0xFF, static_cast<size_t>(rows) * pr->Mmax * 4, st) == hipSuccess;
     ok = ok && hipMemcpyAsync(duoff, uoff.data(), static_cast<size_t>(n) * 4, hipMemcpyHostToDevice, st) == hipSuccess;

@@ -176,3 +176,63 @@ def test_device_build_sift_like_1m_recall_against_oracle_graph(hnsw):
         rb = parity.recall_at_k(b.cpu().numpy(), X, Q, gt, 0).mean()
         print(f"  ef={ef}: recall device-built {ra:.4f}, oracle-built {rb:.4f}", flush=True)
         assert ra >= rb - 0.01
+
+
+def test_deep_like_10m_device_build_and_lowp_search(hnsw):
+    """The low-precision row at its own size: 10M x 96 (deep_like law), graph
+    built on the device (M = 24, Mmax0 = 48, efC = 200).  Checked at full size
+    by properties the oracle can confirm one by one: valid lists (caps, no
+    self-links or repeats, layer membership) on every element of layer 0 and
+    on every upper row; for fp32, BF16 and FP8 traversal at ef 64 / 128 / 256,
+    rows of distinct ids sorted by distance whose distances are the oracle's
+    exact fp32 distances (sampled), and recall@10 against the brute force."""
+    import time
+
+    print("case deep_like 10M device build + fp32/BF16/FP8 search", flush=True)
+    n = 10_000_000
+    X = synthdata.base("deep_like", n)
+    Q = synthdata.queries("deep_like", 2000)
+    t0 = time.time()
+    idx = hnsw.Index.build(X, M=24, efC=200, seed=4003)
+    torch.cuda.synchronize()
+    print(f"  built in {time.time() - t0:.1f} s", flush=True)
+    p = idx.export()
+    a0 = p["adj0"]
+    valid = a0 != 0xFFFFFFFF
+    assert (a0[valid] < n).all()
+    assert not (a0 == np.arange(n, dtype=np.uint32)[:, None]).any()
+    srt = np.sort(np.where(valid, a0, 0xFFFFFFFF), axis=1)
+    assert not ((srt[:, 1:] == srt[:, :-1]) & (srt[:, 1:] != 0xFFFFFFFF)).any()
+    # upper rows: links to members of the row's layer
+    lv = p["levels"]
+    owners = np.repeat(np.arange(n), lv.astype(np.int64))
+    layer = np.concatenate([np.arange(1, l + 1) for l in lv[lv > 0]]) if p["rows"] else np.zeros(0, int)
+    aU = p["adjU"]
+    for r in range(0, len(aU), 200000):
+        blk = aU[r:r + 200000]
+        ok = blk != 0xFFFFFFFF
+        tgt_lv = lv[np.where(ok, blk, 0)]
+        assert ((tgt_lv >= layer[r:r + 200000, None]) | ~ok).all()
+        assert not ((blk == owners[r:r + 200000, None]) & ok).any()
+    assert lv[p["entry_point"]] == p["max_level"] == lv.max()
+    q = torch.from_numpy(Q).cuda()
+    _, gt = hnsw.bruteforce(idx, q, 10)
+    gt = gt.cpu().numpy()
+    idx.add_lowp(hnsw.MODE_BF16)
+    idx.add_lowp(hnsw.MODE_FP8)
+    sample = np.random.default_rng(3).choice(len(Q), 100, replace=False)
+    rec = {}
+    for mode in (0, 1, 2):
+        for ef in (64, 128, 256):
+            ids, ds = idx.search(q, 10, ef, mode=mode)
+            torch.cuda.synchronize()
+            ids, ds = ids.cpu().numpy(), ds.cpu().numpy()
+            assert all(len(set(r)) == 10 for r in ids)
+            assert (np.diff(ds, axis=1) >= 0).all()
+            d64 = oracle.pair_dist(X, Q[sample], ids[sample])
+            assert np.array_equal(d64.astype(np.float32), ds[sample])
+            rec[(mode, ef)] = float(parity.recall_at_k(ids, X, Q, gt, 0).mean())
+            print(f"  mode={mode} ef={ef}: recall {rec[(mode, ef)]:.4f}", flush=True)
+    assert rec[(0, 128)] >= 0.95 and rec[(0, 256)] >= 0.99
+    for ef in (64, 128, 256):
+        assert rec[(1, ef)] >= rec[(0, ef)] - 0.01 and rec[(2, ef)] >= rec[(0, ef)] - 0.02

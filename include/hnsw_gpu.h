@@ -142,6 +142,8 @@ typedef struct {
     int keep_pruned;     /* Alg. 4 keepPrunedConnections                           */
     uint32_t batch_div;  /* a batch holds at most (elements inserted) / batch_div  */
     uint32_t batch_max;  /* and at most this many elements (0: 65,536)             */
+    int select_simple;   /* 1: SELECT-NEIGHBORS-SIMPLE (Alg. 3, the M nearest)      */
+                         /* instead of the heuristic (extendCandidates: not built) */
 } hnsw_build_params;
 hnsw_status hnsw_index_build(const float *vectors, uint32_t n, uint32_t dim, int metric,
                              const hnsw_build_params *params, void *stream, hnsw_index **out);
@@ -190,7 +192,8 @@ typedef enum {
     HNSW_MODE_PLAIN = 0, /* fp32 vectors, as hnsw_search_batch                       */
     HNSW_MODE_BF16 = 1,  /* traverse the BF16 copy, then exact fp32 rerank of W       */
     HNSW_MODE_FP8 = 2,   /* traverse the FP8-E4M3 copy (per-vector scale), then rerank */
-    HNSW_MODE_LEARNED = 3 /* fp32 traversal with the learned early-termination net    */
+    HNSW_MODE_LEARNED = 3, /* fp32 traversal with the learned early-termination net   */
+    HNSW_MODE_U8 = 4       /* traverse the 8-bit integer copy, then rerank (none when exact) */
 } hnsw_mode;
 
 /*
@@ -251,19 +254,25 @@ hnsw_status hnsw_bruteforce_knn(const hnsw_index *index, const float *queries, u
 
 /*
  * Add a low-precision copy of the vector store for HNSW_MODE_BF16 /
- * HNSW_MODE_FP8 searches (quantised on the device from the fp32 rows; the
- * call synchronises `stream`).  BF16: round to nearest even.  FP8: OCP E4M3
- * with a per-vector fp32 scale s = max_j |x_j| / 448 (1 for an all-zero
- * row); code = nearest E4M3 value of x_j / s, ties to even, saturating at 448.
- * A second call for a kind already present is a no-op.
+ * HNSW_MODE_FP8 / HNSW_MODE_U8 searches (quantised on the device from the
+ * fp32 rows; the call synchronises `stream`).  BF16: round to nearest even.
+ * FP8: OCP E4M3 with a per-vector fp32 scale s = max_j |x_j| / 448 (1 for an
+ * all-zero row); code = nearest E4M3 value of x_j / s, ties to even,
+ * saturating at 448.  U8 (integer-valued data such as SIFT, whose paper
+ * build used integer distances, Sec. 5.4): code = x_j rounded to the nearest
+ * integer, ties to even, clamped to [0, 255]; when every code equals its
+ * coordinate the copy is exact and U8 searches skip the re-rank (their
+ * distances are already the fp32 ones).  A second call for a kind already
+ * present is a no-op.
  */
 hnsw_status hnsw_index_add_lowp(hnsw_index *index, int kind, void *stream);
 
 /*
  * Layout and contents of a low-precision copy: layout[0] = bytes per row,
  * layout[1] = 16-byte pieces holding values, layout[2] = byte offset of the
- * FP8 row scale (0 for BF16).  host_out (optional) receives the n rows,
- * [n][layout[0]] bytes (synchronous copy).
+ * FP8 row scale (0 for BF16; for U8, 1 when the copy is exact, else 0).
+ * host_out (optional) receives the n rows, [n][layout[0]] bytes (synchronous
+ * copy).
  */
 hnsw_status hnsw_index_read_lowp(const hnsw_index *index, int kind, void *host_out, uint64_t layout[3]);
 
@@ -322,8 +331,12 @@ hnsw_status hnsw_mlp_adam(float *params, const float *grad, float *m, float *v, 
  *   ef_max    largest ef (after ef := max(ef, k)) a request may use;
  *   k_max     largest k; larger requests are refused (HNSW_ERR_UNSUPPORTED).
  *   mlp       net for HNSW_MODE_LEARNED requests (NULL: those run plain).
- *             Modes served: PLAIN, BF16 (after hnsw_index_add_lowp) and
- *             LEARNED; FP8 requests are refused (HNSW_ERR_UNSUPPORTED).
+ *             Modes served: PLAIN, LEARNED, and BF16 / FP8 when the index
+ *             held that copy (hnsw_index_add_lowp) when the server started
+ *             (else HNSW_ERR_INVALID_ARG at submission).  Each kind is a
+ *             search inlined into the serving kernel, which sets how many of
+ *             its waves a SIMD holds: four with plain and learned only, two
+ *             with BF16, one with FP8 (256 registers).
  *   budget_s  wall-clock seconds after which every wave exits even without a
  *             stop (a bound on the kernel's lifetime).
  * The server runs on a stream of its own.  Results are bit-identical to

@@ -301,6 +301,15 @@ def quantize_fp8(X):
     return codes, dec, sc
 
 
+def quantize_u8(X):
+    """fp32 -> 8-bit integer codes (the integer store of Sec. 5.4's SIFT build):
+    the nearest integer (ties to even), clamped to [0, 255]; returns codes, their
+    float values and unit scales."""
+    X = np.ascontiguousarray(X, dtype=np.float32)
+    codes = np.clip(np.rint(X), 0, 255).astype(np.uint8)
+    return codes, codes.astype(np.float32), np.ones(X.shape[0], dtype=np.float32)
+
+
 def e4m3_value(code: int) -> float:
     return float(lib().or_e4m3_value(code))
 

@@ -18,7 +18,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libhnsw_gpu.so")
 
 HNSW_L2SQ, HNSW_IP = 0, 1
-MODE_PLAIN, MODE_BF16, MODE_FP8, MODE_LEARNED = 0, 1, 2, 3
+MODE_PLAIN, MODE_BF16, MODE_FP8, MODE_LEARNED, MODE_U8 = 0, 1, 2, 3, 4
 EF_MAX, DIM_MAX, DEG_MAX = 1024, 256, 64
 NOALLOC_MAX_QUERIES = 262144
 
@@ -46,7 +46,7 @@ class BuildParams(C.Structure):
     _fields_ = [
         ("M", C.c_uint32), ("Mmax", C.c_uint32), ("Mmax0", C.c_uint32), ("efC", C.c_uint32),
         ("mL", C.c_double), ("seed", C.c_uint64), ("keep_pruned", C.c_int),
-        ("batch_div", C.c_uint32), ("batch_max", C.c_uint32),
+        ("batch_div", C.c_uint32), ("batch_max", C.c_uint32), ("select_simple", C.c_int),
     ]
 
 
@@ -148,7 +148,7 @@ class Index:
     @classmethod
     def build(cls, vectors: np.ndarray, metric: int = HNSW_L2SQ, M: int = 16, Mmax=None, Mmax0=None, efC: int = 200,
               mL=None, seed: int = 1, keep_pruned: bool = False, batch_div: int = 16, batch_max: int = 65536,
-              stream=None) -> "Index":
+              heuristic: bool = True, stream=None) -> "Index":
         """Graph construction on the GPU (``hnsw_index_build``): INSERT in batches of at
         most 1/batch_div of the elements inserted so far (batch_max at most)."""
         import math
@@ -156,7 +156,8 @@ class Index:
         X = np.ascontiguousarray(vectors, dtype=np.float32)
         n, dim = X.shape
         p = BuildParams(M, M if Mmax is None else Mmax, 2 * M if Mmax0 is None else Mmax0, efC,
-                        1.0 / math.log(M) if mL is None else mL, seed, int(keep_pruned), batch_div, batch_max)
+                        1.0 / math.log(M) if mL is None else mL, seed, int(keep_pruned), batch_div, batch_max,
+                        int(not heuristic))
         h = C.c_void_p()
         _check("hnsw_index_build", lib().hnsw_index_build(_np(X), n, dim, metric, C.byref(p), _stream_ptr(stream),
                                                           C.byref(h)))
@@ -206,12 +207,13 @@ class Index:
         return ids, dists, cnt, tr
 
     def add_lowp(self, kind: int, stream=None):
-        """Quantise the store on the device (``MODE_BF16`` or ``MODE_FP8``)."""
+        """Quantise the store on the device (``MODE_BF16``, ``MODE_FP8`` or ``MODE_U8``)."""
         _check("hnsw_index_add_lowp", lib().hnsw_index_add_lowp(self._h, kind, _stream_ptr(stream)))
 
     def read_lowp(self, kind: int):
         """(codes, scales): the device copy as numpy (BF16 uint16 [n][dim];
-        FP8 uint8 [n][dim] and fp32 scales [n])."""
+        FP8 uint8 [n][dim] and fp32 scales [n]; U8 uint8 [n][dim] and
+        whether the copy is exact)."""
         lay = np.zeros(3, dtype=np.uint64)
         _check("hnsw_index_read_lowp", lib().hnsw_index_read_lowp(self._h, kind, None, _np(lay)))
         row = int(lay[0])
@@ -219,6 +221,8 @@ class Index:
         _check("hnsw_index_read_lowp", lib().hnsw_index_read_lowp(self._h, kind, _np(raw), _np(lay)))
         if kind == MODE_BF16:
             return raw.view(np.uint16)[:, :self.dim].copy(), np.ones(self.n, np.float32)
+        if kind == MODE_U8:
+            return raw[:, :self.dim].copy(), bool(lay[2])
         off = int(lay[2])
         return raw[:, :self.dim].copy(), raw[:, off:off + 4].copy().view(np.float32)[:, 0]
 

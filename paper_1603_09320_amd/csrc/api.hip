@@ -320,9 +320,10 @@ static hnsw_status search_impl(const hnsw_index *index, const float *queries, ui
     if (!index) return HNSW_ERR_INVALID_ARG;
     if (no_alloc && n > HNSW_NOALLOC_MAX_QUERIES) return HNSW_ERR_UNSUPPORTED;
     if (k == 0 || ef == 0) return HNSW_ERR_INVALID_ARG;
-    if (mode < HNSW_MODE_PLAIN || mode > HNSW_MODE_LEARNED) return HNSW_ERR_UNSUPPORTED;
+    if (mode < HNSW_MODE_PLAIN || mode > HNSW_MODE_U8) return HNSW_ERR_UNSUPPORTED;
     if (mode == HNSW_MODE_BF16 && !index->ix.vbf16) return HNSW_ERR_INVALID_ARG;
     if (mode == HNSW_MODE_FP8 && !index->ix.vfp8) return HNSW_ERR_INVALID_ARG;
+    if (mode == HNSW_MODE_U8 && !index->ix.vu8) return HNSW_ERR_INVALID_ARG;
     if (mode == HNSW_MODE_LEARNED && !mlp) mode = HNSW_MODE_PLAIN;  // no net: the plain search
     if (mode == HNSW_MODE_LEARNED && k > 64) return HNSW_ERR_UNSUPPORTED;
     const uint32_t efe = ef < k ? k : ef;
@@ -341,8 +342,14 @@ static hnsw_status search_impl(const hnsw_index *index, const float *queries, ui
     a.dists = dists_out;
     a.counters = counters;
     a.wcap = (efe + 63) & ~63u;
-    a.wpow2 = 64;
-    while (a.wpow2 < a.wcap) a.wpow2 <<= 1;
+    // W needs wcap slots; the low-precision stores sort W after their re-rank
+    // (bitonic, a power of two of slots).  A power of two for every store cost
+    // the fp32 search a third of its waves per CU just above ef = 256.
+    a.wslots = a.wcap;
+    if (mode == HNSW_MODE_BF16 || mode == HNSW_MODE_FP8 || mode == HNSW_MODE_U8) {
+        a.wslots = 64;
+        while (a.wslots < a.wcap) a.wslots <<= 1;
+    }
     a.mode = mode;
     a.mlp = hnsw::DevMlp{};
     if (mode == HNSW_MODE_LEARNED) a.mlp = static_cast<const hnsw_mlp *>(mlp)->net;
@@ -377,15 +384,22 @@ hnsw_status hnsw_search_learned_trace(const hnsw_index *index, const float *quer
 }
 
 hnsw_status hnsw_index_add_lowp(hnsw_index *index, int kind, void *stream) {
-    if (!index || (kind != HNSW_MODE_BF16 && kind != HNSW_MODE_FP8)) return HNSW_ERR_INVALID_ARG;
+    if (!index || (kind != HNSW_MODE_BF16 && kind != HNSW_MODE_FP8 && kind != HNSW_MODE_U8))
+        return HNSW_ERR_INVALID_ARG;
     hnsw::DevIndex &ix = index->ix;
-    if ((kind == HNSW_MODE_BF16 && ix.vbf16) || (kind == HNSW_MODE_FP8 && ix.vfp8)) return HNSW_OK;
+    if ((kind == HNSW_MODE_BF16 && ix.vbf16) || (kind == HNSW_MODE_FP8 && ix.vfp8) ||
+        (kind == HNSW_MODE_U8 && ix.vu8))
+        return HNSW_OK;
     hipStream_t st = static_cast<hipStream_t>(stream);
     hnsw::DevIndex nx = ix;
     size_t bytes;
     if (kind == HNSW_MODE_BF16) {
         nx.bf16_stride16 = ((ix.dim + 7) / 8 + 3) & ~3u;
         bytes = (static_cast<size_t>(ix.n) + 1) * nx.bf16_stride16 * 16;
+    } else if (kind == HNSW_MODE_U8) {
+        nx.u8_pieces = (ix.dim + 15) / 16;
+        nx.u8_stride16 = (nx.u8_pieces + 3) & ~3u;
+        bytes = (static_cast<size_t>(ix.n) + 1) * nx.u8_stride16 * 16;
     } else {
         nx.fp8_pieces = (ix.dim + 15) / 16;
         nx.fp8_scale_off = nx.fp8_pieces * 16;
@@ -398,9 +412,17 @@ hnsw_status hnsw_index_add_lowp(hnsw_index *index, int kind, void *stream) {
         (void)hipGetLastError();
         return HNSW_ERR_OUT_OF_MEMORY;
     }
+    // the last 4 bytes of the (zero) row n carry the inexact flag of the 8-bit copy
+    uint32_t *flag = static_cast<uint32_t *>(static_cast<void *>(static_cast<uint8_t *>(p) + bytes - 4));
     bool ok = hipMemsetAsync(p, 0, bytes, st) == hipSuccess;
     if (kind == HNSW_MODE_BF16) ok = ok && hnsw::launch_quantize_bf16(nx, static_cast<uint16_t *>(p), st) == hipSuccess;
+    else if (kind == HNSW_MODE_U8) ok = ok && hnsw::launch_quantize_u8(nx, static_cast<uint8_t *>(p), flag, st) == hipSuccess;
     else ok = ok && hnsw::launch_quantize_fp8(nx, static_cast<uint8_t *>(p), st) == hipSuccess;
+    uint32_t inexact = 0;
+    if (kind == HNSW_MODE_U8) {
+        ok = ok && hipMemcpyAsync(&inexact, flag, 4, hipMemcpyDeviceToHost, st) == hipSuccess;
+        ok = ok && hipMemsetAsync(flag, 0, 4, st) == hipSuccess;  // row n is the all-zero row again
+    }
     ok = ok && hipStreamSynchronize(st) == hipSuccess;
     if (!ok) {
         (void)hipGetLastError();
@@ -410,6 +432,11 @@ hnsw_status hnsw_index_add_lowp(hnsw_index *index, int kind, void *stream) {
     if (kind == HNSW_MODE_BF16) {
         ix.vbf16 = static_cast<uint16_t *>(p);
         ix.bf16_stride16 = nx.bf16_stride16;
+    } else if (kind == HNSW_MODE_U8) {
+        ix.vu8 = static_cast<uint8_t *>(p);
+        ix.u8_stride16 = nx.u8_stride16;
+        ix.u8_pieces = nx.u8_pieces;
+        ix.u8_exact = inexact ? 0u : 1u;
     } else {
         ix.vfp8 = static_cast<uint8_t *>(p);
         ix.fp8_stride16 = nx.fp8_stride16;
@@ -425,12 +452,16 @@ hnsw_status hnsw_index_read_lowp(const hnsw_index *index, int kind, void *host_o
     if (!index || !layout) return HNSW_ERR_INVALID_ARG;
     const hnsw::DevIndex &ix = index->ix;
     const void *src = kind == HNSW_MODE_BF16 ? static_cast<const void *>(ix.vbf16)
-                                             : (kind == HNSW_MODE_FP8 ? static_cast<const void *>(ix.vfp8) : nullptr);
+                      : kind == HNSW_MODE_FP8  ? static_cast<const void *>(ix.vfp8)
+                      : kind == HNSW_MODE_U8   ? static_cast<const void *>(ix.vu8)
+                                               : nullptr;
     if (!src) return HNSW_ERR_INVALID_ARG;
-    const uint64_t row = kind == HNSW_MODE_BF16 ? ix.bf16_stride16 * 16ull : ix.fp8_stride16 * 16ull;
+    const uint64_t row = kind == HNSW_MODE_BF16 ? ix.bf16_stride16 * 16ull
+                         : kind == HNSW_MODE_U8 ? ix.u8_stride16 * 16ull
+                                                : ix.fp8_stride16 * 16ull;
     layout[0] = row;
-    layout[1] = kind == HNSW_MODE_BF16 ? ix.bf16_stride16 : ix.fp8_pieces;
-    layout[2] = kind == HNSW_MODE_FP8 ? ix.fp8_scale_off : 0;
+    layout[1] = kind == HNSW_MODE_BF16 ? ix.bf16_stride16 : (kind == HNSW_MODE_U8 ? ix.u8_pieces : ix.fp8_pieces);
+    layout[2] = kind == HNSW_MODE_FP8 ? ix.fp8_scale_off : (kind == HNSW_MODE_U8 ? ix.u8_exact : 0);
     if (!host_out) return HNSW_OK;
     if (hipMemcpy(host_out, src, row * ix.n, hipMemcpyDeviceToHost) != hipSuccess) {
         (void)hipGetLastError();

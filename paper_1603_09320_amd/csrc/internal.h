@@ -20,10 +20,14 @@ struct DevIndex {
     const uint32_t *adjU;  // [rows][Mmax] lists of layers >= 1
     const uint16_t *vbf16; // [n + 1][bf16_stride16 * 8] BF16 copy or null; row n all zero
     const uint8_t *vfp8;   // [n + 1][fp8_stride16 * 16] FP8-E4M3 copy or null; row n all zero
+    const uint8_t *vu8;    // [n + 1][u8_stride16 * 16] 8-bit integer copy or null; row n all zero
     uint32_t bf16_stride16;  // 16-byte pieces per BF16 row
     uint32_t fp8_stride16;   // 16-byte pieces per FP8 row (values, scale, padding)
     uint32_t fp8_pieces;     // pieces of an FP8 row that hold values
     uint32_t fp8_scale_off;  // byte offset of the row's fp32 scale
+    uint32_t u8_stride16;    // 16-byte pieces per 8-bit row (values, padding)
+    uint32_t u8_pieces;      // pieces of an 8-bit row that hold values
+    uint32_t u8_exact;       // every coordinate is an integer in [0, 255]: the copy equals the fp32 store
     uint32_t n, dim, dv4, stride4;
     uint32_t Mmax, Mmax0, entry, max_level, metric;
     uint32_t uid;  // identifies the index among those uploaded by this process (host bookkeeping only)
@@ -50,7 +54,7 @@ struct SearchArgs {
     float *dists;          // [nq][k]
     uint32_t *counters;    // [nq][4] or null
     uint32_t wcap;         // capacity of W in LDS, multiple of 64, >= ef
-    uint32_t wpow2;        // power of two >= wcap (LDS reserved for W)
+    uint32_t wslots;       // LDS slots reserved for W: wcap, or the power of two >= wcap for the stores that sort W
     uint32_t ht_slots;     // visited-table slots, >= 256 (probe steps reach 128 slots and wrap once)
     int mode;              // hnsw_mode
     DevMlp mlp;            // learned stop rule (mode HNSW_MODE_LEARNED)
@@ -82,6 +86,9 @@ hipError_t launch_adam(float *P, const float *G, float *M, float *V, uint32_t np
 // Quantisation of the fp32 store into the low-precision copies.
 hipError_t launch_quantize_bf16(const DevIndex &ix, uint16_t *out, hipStream_t stream);
 hipError_t launch_quantize_fp8(const DevIndex &ix, uint8_t *out, hipStream_t stream);
+// 8-bit integer copy: code = x rounded to the nearest integer (ties to even),
+// clamped to [0, 255]; *inexact (device) is set when some code differs from x.
+hipError_t launch_quantize_u8(const DevIndex &ix, uint8_t *out, uint32_t *inexact, hipStream_t stream);
 
 // LDS per wave of a search kernel; `learned` adds the stop rule's buffers.
 size_t search_lds_bytes(const SearchArgs &a, bool learned);

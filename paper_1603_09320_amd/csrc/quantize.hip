@@ -2,8 +2,11 @@
 // low-precision search: BF16 (round to nearest even) and OCP FP8-E4M3 with a
 // per-vector fp32 scale s = max_j |x_j| / 448 (s = 1 for an all-zero row),
 // codes = nearest E4M3 value to x_j / s, ties to even, saturating at 448.
-// Row layouts (16-byte pieces): BF16 rows hold the values; FP8 rows hold the
-// values, then the fp32 scale, padded to a multiple of 64 bytes.
+// The 8-bit integer copy (an integer-valued store like SIFT's, which the
+// paper searched with integer distance functions, Sec. 5.4): code = x rounded
+// to the nearest integer (ties to even) and clamped to [0, 255].
+// Row layouts (16-byte pieces): BF16 and 8-bit rows hold the values; FP8 rows
+// hold the values, then the fp32 scale; all padded to a multiple of 64 bytes.
 #include "internal.h"
 
 namespace hnsw {
@@ -55,7 +58,30 @@ __global__ void quantize_fp8_kernel(DevIndex ix, uint8_t *out) {
     *reinterpret_cast<float *>(o + ix.fp8_scale_off) = s;
 }
 
+__global__ void quantize_u8_kernel(DevIndex ix, uint8_t *out, uint32_t *inexact) {
+    const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= ix.n) return;
+    const float *x = ix.vec + static_cast<size_t>(i) * ix.stride4 * 4;
+    uint8_t *o = out + static_cast<size_t>(i) * ix.u8_stride16 * 16;
+    bool exact = true;
+    for (uint32_t j = 0; j < ix.u8_pieces * 16; ++j) {
+        if (j >= ix.dim) {
+            o[j] = 0;
+            continue;
+        }
+        const float r = fminf(fmaxf(rintf(x[j]), 0.0f), 255.0f);
+        exact = exact && r == x[j];
+        o[j] = static_cast<uint8_t>(r);
+    }
+    if (!exact) atomicOr(inexact, 1u);
+}
+
 }  // namespace
+
+hipError_t launch_quantize_u8(const DevIndex &ix, uint8_t *out, uint32_t *inexact, hipStream_t stream) {
+    hipLaunchKernelGGL(quantize_u8_kernel, dim3((ix.n + 255) / 256), dim3(256), 0, stream, ix, out, inexact);
+    return hipGetLastError();
+}
 
 hipError_t launch_quantize_bf16(const DevIndex &ix, uint16_t *out, hipStream_t stream) {
     hipLaunchKernelGGL(quantize_bf16_kernel, dim3((ix.n + 255) / 256), dim3(256), 0, stream, ix, out);

@@ -18,7 +18,7 @@ namespace hnsw {
 // fp32 rows use two pieces per lane up to 128 dimensions; low-precision
 // rows (8 or 16 values per piece) use one piece per lane up to 16 pieces.
 TileShape tile_for(int kind, uint32_t dim) {
-    const uint32_t vpp = kind == kF32 ? 4 : (kind == kBF16 ? 8 : 16);
+    const uint32_t vpp = kind == kF32 ? 4 : (kind == kBF16 ? 8 : 16);  // FP8 and 8-bit: 16
     const uint32_t pieces = (dim + vpp - 1) / vpp;
     if (kind == kF32) {
         if (pieces <= 1) return {1, 1};
@@ -37,7 +37,7 @@ TileShape tile_for(int kind, uint32_t dim) {
 }
 
 size_t search_lds_bytes(const SearchArgs &a, bool learned) {
-    return static_cast<size_t>(a.wpow2) * 8 + 64 * 8 + 64 * 4 + (learned ? 64 * 4 + 128 * 4 : 0) +
+    return static_cast<size_t>(a.wslots) * 8 + 64 * 8 + 64 * 4 + (learned ? 64 * 4 + 128 * 4 : 0) +
            static_cast<size_t>(a.ht_slots) * 4;
 }
 
@@ -46,7 +46,11 @@ size_t search_lds_bytes(const SearchArgs &a, bool learned) {
 // rounded down to whole KiB (the share itself, so that no allocation rounding
 // can cost a wave); a fuller table forgets fewer ids (a forgotten id is
 // scored again).  FP8 is sized like the others: a table filling a 20th of
-// the LDS (all of it at five waves per SIMD) measured 2% slower.
+// the LDS (all of it at five waves per SIMD) measured 2% slower.  Above that
+// share the table grows with ef (8 slots per element of W) up to 2,048
+// slots: on glove_like 1.2M at ef 320, 4,096 slots (16 KiB, half the waves
+// per CU) took 10.3 ms per 10,000 queries and 2,048 slots 7.8 ms, the extra
+// distance evaluations of a fuller table costing less than the lost waves.
 // HNSW_VISITED_LOG2 = 8..14 fixes a power of two instead.
 uint32_t visited_slots(const SearchArgs &a, bool learned) {
     if (const char *v = getenv("HNSW_VISITED_LOG2")) {
@@ -54,7 +58,7 @@ uint32_t visited_slots(const SearchArgs &a, bool learned) {
         if (x >= 8 && x <= 14) return 1u << x;
     }
     uint32_t lg = 10;
-    while (lg < 12 && (1u << lg) < 8u * a.ef) ++lg;
+    while (lg < 11 && (1u << lg) < 8u * a.ef) ++lg;
     const uint32_t base = 1u << lg;
     const uint32_t share = (160u * 1024u / 24u) & ~1023u;
     SearchArgs t = a;
@@ -68,7 +72,8 @@ bool stores_buffered(const DevIndex &ix) {
     auto fits = [&](const void *p, uint32_t stride16) {
         return !p || (static_cast<uint64_t>(ix.n) + 1) * stride16 * 16 <= kBufferedMaxBytes;
     };
-    return fits(ix.vec, ix.stride4) && fits(ix.vbf16, ix.bf16_stride16) && fits(ix.vfp8, ix.fp8_stride16);
+    return fits(ix.vec, ix.stride4) && fits(ix.vbf16, ix.bf16_stride16) && fits(ix.vfp8, ix.fp8_stride16) &&
+           fits(ix.vu8, ix.u8_stride16);
 }
 
 namespace {

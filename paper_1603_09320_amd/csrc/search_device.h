@@ -200,9 +200,9 @@ __device__ __forceinline__ double group_sum(double v) {
 }
 
 // Vector stores the traversal can read.  A row is a sequence of 16-byte
-// pieces: 4 fp32, 8 bf16 or 16 fp8-E4M3 values; the FP8 row carries its
-// fp32 scale at byte offset lp_scale_off.
-enum StoreKind { kF32 = 0, kBF16 = 1, kFP8 = 2 };
+// pieces: 4 fp32, 8 bf16, 16 fp8-E4M3 or 16 unsigned 8-bit integer values;
+// the FP8 row carries its fp32 scale at byte offset lp_scale_off.
+enum StoreKind { kF32 = 0, kBF16 = 1, kFP8 = 2, kU8 = 3 };
 
 template <int KIND>
 struct Store;
@@ -218,6 +218,11 @@ struct Store<kBF16> {
 };
 template <>
 struct Store<kFP8> {
+    static constexpr int VPP = 16;
+    using QT = float;
+};
+template <>
+struct Store<kU8> {
     static constexpr int VPP = 16;
     using QT = float;
 };
@@ -239,6 +244,7 @@ __device__ __forceinline__ float piece_value(const uint4 &p, int j) {
     const uint32_t w = j < Store<KIND>::VPP / 4 ? p.x : (j < Store<KIND>::VPP / 2 ? p.y : (j < 3 * Store<KIND>::VPP / 4 ? p.z : p.w));
     if (KIND == kF32) return __uint_as_float(w);
     if (KIND == kBF16) return __uint_as_float((j & 1) ? (w & 0xFFFF0000u) : (w << 16));
+    if (KIND == kU8) return static_cast<float>((w >> (8 * (j & 3))) & 0xFFu);
     return fp8_byte(w, j);
 }
 
@@ -293,6 +299,7 @@ __device__ __forceinline__ RowSource make_source(const void *base, uint32_t stri
 __device__ __forceinline__ RowSource rows_of(const DevIndex &ix, const SearchArgs &a, int kind) {
     if (kind == kF32) return make_source(ix.vec, ix.stride4, ix.stride4, 0, ix.n);
     if (kind == kBF16) return make_source(ix.vbf16, ix.bf16_stride16, ix.bf16_stride16, 0, ix.n);
+    if (kind == kU8) return make_source(ix.vu8, ix.u8_stride16, ix.u8_pieces, 0, ix.n);
     return make_source(ix.vfp8, ix.fp8_stride16, ix.fp8_pieces, ix.fp8_scale_off, ix.n);
 }
 
@@ -393,7 +400,7 @@ __device__ __forceinline__ void score_ids(const DevIndex &ix, const RowSource &s
 }
 
 struct WaveLds {
-    uint64_t *W;       // [wpow2]
+    uint64_t *W;       // [wslots]
     uint64_t *keys;    // [64] keys of the current batch
     uint32_t *ids;     // [64] ids of the current batch
     uint32_t *prevk;   // [64] top-K ids at the previous checkpoint (learned mode)
@@ -407,7 +414,7 @@ template <bool LEARN>
 __device__ __forceinline__ WaveLds carve(uint8_t *base, const SearchArgs &a) {
     WaveLds s;
     s.W = reinterpret_cast<uint64_t *>(base);
-    s.keys = s.W + a.wpow2;
+    s.keys = s.W + a.wslots;
     s.ids = reinterpret_cast<uint32_t *>(s.keys + 64);
     if (LEARN) {
         s.prevk = s.ids + 64;
@@ -832,7 +839,7 @@ __device__ Descent descend(const DevIndex &ix, const RowSource &src, const Query
 // The rest of K-NN-SEARCH (Alg. 5) from the descent's result: SEARCH-LAYER on
 // layer 0 with ef (Alg. 2), the exact rerank of low-precision traversals, and
 // the K nearest of W written to the job's outputs.  `s` is the wave's LDS
-// workspace, sized for a.wpow2 and a.ht_slots; job.ef >= job.k.
+// workspace, sized for a.wslots and a.ht_slots; job.ef >= job.k.
 template <int G, int F, int METRIC, int KIND, bool LEARN, bool BUF>
 __device__ void search_layer0(const DevIndex &ix, const SearchArgs &a, const Job &job, const WaveLds &s,
                               const RowSource &src, const QueryRegs<G, F, KIND> &Q, const Descent &dsc) {
@@ -926,7 +933,9 @@ __device__ void search_layer0(const DevIndex &ix, const SearchArgs &a, const Job
     }
 
     uint32_t n_rerank = 0;
-    if (KIND != kF32) {
+    // an 8-bit copy that equals the fp32 store (integer data in [0, 255])
+    // already gave the exact distances: nothing to re-rank
+    if (KIND != kF32 && !(KIND == kU8 && ix.u8_exact)) {
         // Low-precision traversal: re-score every element of W exactly from the
         // fp32 vectors (the same grouped gather and arithmetic as the plain
         // path, pieces of 4 floats, so each lane holds VPP/4 times as many)
@@ -944,7 +953,7 @@ __device__ void search_layer0(const DevIndex &ix, const SearchArgs &a, const Job
             if (lane < cnt) s.W[c0 + lane] = s.keys[lane];
             wave_sync();
         }
-        sort_w(s.W, wsize, a.wpow2);
+        sort_w(s.W, wsize, a.wslots);
         n_rerank = wsize;
     }
 

@@ -49,6 +49,14 @@ def test_quantized_codes_match_oracle(hnsw, workload, n):
     o8, _, osc = oracle.quantize_fp8(X)
     assert np.array_equal(gs, osc)
     assert np.array_equal(g8, o8)
+    idx.add_lowp(hnsw.MODE_U8)
+    gu, exact = idx.read_lowp(hnsw.MODE_U8)
+    ou = oracle.quantize_u8(X)[0]
+    assert np.array_equal(gu, ou)
+    assert exact == bool(np.array_equal(ou.astype(np.float32), X))
+
+
+QUANT = {1: oracle.quantize_bf16, 2: oracle.quantize_fp8, 4: oracle.quantize_u8}
 
 
 def _lowp_parity(hnsw, X, Q, G, K, ef, kind, metric):
@@ -58,7 +66,7 @@ def _lowp_parity(hnsw, X, Q, G, K, ef, kind, metric):
     ids, ds, cnt = idx.search(torch.from_numpy(Q).cuda(), K, ef, mode=kind, counters=True)
     torch.cuda.synchronize()
     ids, ds, cnt = ids.cpu().numpy(), ds.cpu().numpy(), cnt.cpu().numpy().astype(np.uint32)
-    codes, dec, sc = (oracle.quantize_bf16 if kind == hnsw.MODE_BF16 else oracle.quantize_fp8)(X)
+    codes, dec, sc = QUANT[kind](X)
     G.set_lowp(dec, sc)
     oi, od, oc = G.search(Q, K, ef, nthreads=8, counters=True)
     G.set_lowp(None, None)
@@ -69,7 +77,7 @@ def _lowp_parity(hnsw, X, Q, G, K, ef, kind, metric):
     return ids, ds
 
 
-@pytest.mark.parametrize("kind", [1, 2])
+@pytest.mark.parametrize("kind", [1, 2, 4])
 def test_lowp_parity_deep_like(hnsw, kind):
     print(f"case lowp deep_like 20k x 96 kind={kind}", flush=True)
     X = synthdata.base("deep_like", 20000)
@@ -79,7 +87,7 @@ def test_lowp_parity_deep_like(hnsw, kind):
         _lowp_parity(hnsw, X, Q, G, 10, ef, kind, oracle.L2)
 
 
-@pytest.mark.parametrize("kind", [1, 2])
+@pytest.mark.parametrize("kind", [1, 2, 4])
 def test_lowp_parity_inner_product_and_dims(hnsw, kind):
     print(f"case lowp glove_like 8k x 100 IP kind={kind}", flush=True)
     X = synthdata.base("glove_like", 8000)
@@ -94,7 +102,7 @@ def test_lowp_parity_inner_product_and_dims(hnsw, kind):
         _lowp_parity(hnsw, X, Q, G, 10, 50, kind, oracle.L2)
 
 
-@pytest.mark.parametrize("kind", [1, 2])
+@pytest.mark.parametrize("kind", [1, 2, 4])
 def test_lowp_parity_wide_gathers(hnsw, monkeypatch, kind):
     """Low-precision traversal and re-rank through the 64-bit addressed
     kernels (taken for stores above 2 GiB), forced on a small index."""
@@ -121,6 +129,34 @@ def test_bf16_equals_fp32_on_integer_data(hnsw):
         assert torch.equal(a[0], b[0]) and torch.equal(a[1], b[1])
 
 
+def test_u8_store_exact_on_integer_data(hnsw):
+    """SIFT-like coordinates are integers in [0, 255]: the 8-bit copy is exact
+    (codes equal the oracle's), its search skips the re-rank, and returns the
+    fp32 search's ids and distances bit for bit, with the same expansions (the
+    distance counts may differ: the fp32 store's visited table replaces old
+    ids when full, the low-precision ones forget the new id); a store with
+    other values is flagged inexact."""
+    X = synthdata.base("sift_like", 30000)
+    Q = synthdata.queries("sift_like", 500)
+    G = oracle.Graph.build(X, M=16, efC=200, seed=2003)
+    idx = hnsw.Index(G.packed(), X)
+    idx.add_lowp(hnsw.MODE_U8)
+    codes, exact = idx.read_lowp(hnsw.MODE_U8)
+    assert exact and np.array_equal(codes, oracle.quantize_u8(X)[0])
+    q = torch.from_numpy(Q).cuda()
+    for K, ef in ((10, 10), (10, 64), (1, 32), (100, 300)):
+        a = idx.search(q, K, ef, counters=True)
+        b = idx.search(q, K, ef, mode=hnsw.MODE_U8, counters=True)
+        torch.cuda.synchronize()
+        assert torch.equal(a[0], b[0]) and torch.equal(a[1], b[1]), (K, ef)
+        assert torch.equal(a[2][:, 1], b[2][:, 1]) and torch.equal(a[2][:, 3], b[2][:, 3]), (K, ef)
+    Y = synthdata.base("deep_like", 3000)
+    idy = hnsw.Index(oracle.Graph.build(Y, M=8, efC=20, seed=1).packed(), Y)
+    idy.add_lowp(hnsw.MODE_U8)
+    cy, ey = idy.read_lowp(hnsw.MODE_U8)
+    assert not ey and np.array_equal(cy, oracle.quantize_u8(Y)[0])
+
+
 def test_lowp_requires_copy(hnsw):
     X = synthdata.base("uniform16", 500)
     G = oracle.Graph.build(X, M=8, efC=20, seed=1)
@@ -130,7 +166,7 @@ def test_lowp_requires_copy(hnsw):
     assert e.value.code == 1
 
 
-@pytest.mark.parametrize("kind", [1, 2])
+@pytest.mark.parametrize("kind", [1, 2, 4])
 def test_lowp_parity_scheduled(hnsw, monkeypatch, kind):
     """Low-precision traversal and re-rank in the scheduled form (descents
     first, layer 0 reordered), forced on a small batch."""
@@ -147,7 +183,7 @@ FULL = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))),
 
 
 @pytest.mark.skipif(not os.path.exists(FULL), reason="1M sift_like graph file not built")
-@pytest.mark.parametrize("kind", [1, 2])
+@pytest.mark.parametrize("kind", [1, 2, 4])
 def test_lowp_full_size_sampled(hnsw, kind):
     """The 1M x 128 workload in the benchmark's launch shape (all 10,000
     queries, K = 10, ef = 56 as timed): a sample against the oracle's
@@ -159,7 +195,7 @@ def test_lowp_full_size_sampled(hnsw, kind):
     idx = hnsw.Index(p, X)
     idx.add_lowp(kind)
     G = oracle.Graph.from_packed(X, p)
-    _, dec, sc = (oracle.quantize_bf16 if kind == 1 else oracle.quantize_fp8)(X)
+    _, dec, sc = QUANT[kind](X)
     G.set_lowp(dec, sc)
     sample = np.random.default_rng(1).choice(10000, size=150, replace=False)
     for K, ef in ((10, 56), (10, 128)):

@@ -80,10 +80,10 @@ def recall(ids, X, Q, gt_d64, metric=0):
 
 def row_bytes(mode: int, dim: int) -> int:
     """Bytes of one vector as the traversal reads it (values only, plus the FP8 scale)."""
-    return {0: 4 * dim, 1: 2 * dim, 2: dim + 4, 3: 4 * dim}[mode]
+    return {0: 4 * dim, 1: 2 * dim, 2: dim + 4, 3: 4 * dim, 4: dim}[mode]
 
 
-def algorithmic_bytes(cnt, graph, K, mode, ef, includes_rerank):
+def algorithmic_bytes(cnt, graph, K, mode, ef, includes_rerank, reranks=None):
     """Bytes the method must move per step: one adjacency row per expansion
     (layer 0: 4*Mmax0, upper layers: 4*Mmax), one vector per distance
     evaluation, the query and the K results; the low-precision forms add one
@@ -96,7 +96,9 @@ def algorithmic_bytes(cnt, graph, K, mode, ef, includes_rerank):
     c = cnt.astype(np.int64)
     dim = graph["dim"]
     exp_u = c[:, 1] - c[:, 3]
-    rer = np.minimum(ef, graph["n"]) if mode in (1, 2) else 0
+    if reranks is None:
+        reranks = mode in (1, 2, 4)
+    rer = np.minimum(ef, graph["n"]) if reranks else 0
     trav = c[:, 0] - (rer if includes_rerank else 0)
     per_q = (c[:, 3] * 4 * graph["Mmax0"] + exp_u * 4 * graph["Mmax"] + trav * row_bytes(mode, dim)
              + rer * 4 * dim + 4 * dim + 8 * K)
@@ -169,8 +171,8 @@ def oracle_counts(G, X, Q, K, ef, mode, mlp_file=None):
         r = G.search_learned(Q, K, ef, net=oracle.bf16_net(z["params"]), tau=float(z["tau"]), jmax=int(z["jmax"]),
                              T=int(z["period"]), max_ckpt=int(z["max_ckpt"]), nthreads=threads)
         return r["counters"]
-    if mode in (1, 2):
-        _, dec, sc = (oracle.quantize_bf16 if mode == 1 else oracle.quantize_fp8)(X)
+    if mode in (1, 2, 4):
+        _, dec, sc = {1: oracle.quantize_bf16, 2: oracle.quantize_fp8, 4: oracle.quantize_u8}[mode](X)
         G.set_lowp(dec, sc)
     try:
         _, _, cnt = G.search(Q, K, ef, nthreads=threads, counters=True)
@@ -226,13 +228,15 @@ class Runner:
 # Each server's persistent grid: at ef_max = 512 a wave reserves about 22 KB of
 # LDS (7 waves per CU, 1792 on the chip), so two servers of 768 waves are
 # resident together.
-def serve_bench(hnsw, index, Q, mlp, rates=(50_000, 200_000, 500_000), n_req=20_000, seed=7):
+def serve_bench(hnsw, index, Q, mlp, rates=(50_000, 100_000, 200_000, 500_000), n_req=20_000, seed=7):
     """Continuous-batching serving: an open-loop Poisson replay over two live
-    servers, the main index and a 1M x 4 uniform index (built by the oracle,
-    file graphs/uniform4_1M.bin); per request K in {1, 10, 100}, ef uniform in
-    [K, 512], modes mixed over plain, BF16 and (K <= 64, when a net is loaded)
-    learned.  Returns p50/p99 latency (arrival to completion) and completed
-    requests per second for each arrival rate."""
+    servers, the main index (plain, learned when a net is loaded, BF16 and
+    FP8 requests) and a 1M x 4 uniform index (built by the oracle, file
+    graphs/uniform4_1M.bin; plain and BF16); per request K in {1, 10, 100}, ef
+    uniform in [K, 512].  Returns, per arrival rate, p50/p99 latency (arrival
+    to completion), completed requests per second, and the occupancy of the
+    request slots (requests in flight between submission and completion:
+    mean, p99 and peak, against the 4,096 slots of each server)."""
     import synthdata
 
     upath = os.path.join(ROOT, WORKLOADS["uniform4"][0])
@@ -243,24 +247,30 @@ def serve_bench(hnsw, index, Q, mlp, rates=(50_000, 200_000, 500_000), n_req=20_
         g4 = hnsw.graphfile.read(upath)
     idx4 = hnsw.Index(g4, synthdata.base("uniform4", g4["n"])) if g4 else None
     Q4 = synthdata.queries("uniform4", 10_000) if g4 else None
-    for ix in (index, idx4):
-        if ix is not None:
-            ix.add_lowp(hnsw.MODE_BF16)
+    index.add_lowp(hnsw.MODE_BF16)
+    index.add_lowp(hnsw.MODE_FP8)
+    if idx4 is not None:
+        idx4.add_lowp(hnsw.MODE_BF16)
     out = []
     rng = np.random.default_rng(seed)
+    slots = 4096
     for rate in rates:
-        servers = [hnsw.Server(index, mlp=mlp, slots=4096, waves=768, ef_max=512, k_max=100, budget_s=120.0)]
+        # the main index's kernel holds one wave per SIMD (it inlines the FP8
+        # search), the other's two: 512 + 1024 waves are resident together
+        servers = [hnsw.Server(index, mlp=mlp, slots=slots, waves=512, ef_max=512, k_max=100, budget_s=120.0)]
         if idx4 is not None:
-            servers.append(hnsw.Server(idx4, mlp=None, slots=4096, waves=768, ef_max=512, k_max=100, budget_s=120.0))
+            servers.append(hnsw.Server(idx4, mlp=None, slots=slots, waves=1024, ef_max=512, k_max=100,
+                                       budget_s=120.0))
         try:
             arrival = np.cumsum(rng.exponential(1.0 / rate, n_req))
             server_of = rng.integers(0, len(servers), n_req).astype(np.uint32)
             qidx = rng.integers(0, len(Q), n_req).astype(np.uint32)
             k = rng.choice([1, 10, 100], n_req).astype(np.uint32)
             ef = np.array([rng.integers(kk, 513) for kk in k], dtype=np.uint32)
-            modes = [0, 1, 3] if mlp is not None else [0, 1]
+            modes = [0, 1, 2, 3] if mlp is not None else [0, 1, 2]
             mode = rng.choice(modes, n_req).astype(np.int32)
             mode[(mode == 3) & ((k > 64) | (server_of == 1))] = 0
+            mode[(mode == 2) & (server_of == 1)] = 1
             qs = [Q] + ([Q4] if idx4 is not None else [])
             r = hnsw.replay(servers, qs, arrival, server_of, qidx, k, ef, mode, keep_results=False,
                             timeout_s=60.0)
@@ -269,23 +279,29 @@ def serve_bench(hnsw, index, Q, mlp, rates=(50_000, 200_000, 500_000), n_req=20_
                 sv.stop()
         lat = (r["t_done"] - arrival) * 1e3
         span = float(r["t_done"].max() - arrival[0])
+        # requests in flight at each submission and completion instant
+        ev = np.concatenate([np.stack([r["t_submit"], np.ones(n_req)], 1), np.stack([r["t_done"], -np.ones(n_req)], 1)])
+        ev = ev[np.lexsort((ev[:, 1], ev[:, 0]))]
+        inflight = np.cumsum(ev[:, 1])
         row = {"offered_rps": rate, "requests": n_req, "p50_ms": round(float(np.percentile(lat, 50)), 3),
-               "p99_ms": round(float(np.percentile(lat, 99)), 3), "completed_rps": round(n_req / span, 1)}
+               "p99_ms": round(float(np.percentile(lat, 99)), 3), "completed_rps": round(n_req / span, 1),
+               "in_flight_mean": round(float(np.mean(inflight)), 1),
+               "in_flight_p99": round(float(np.percentile(inflight, 99)), 1),
+               "in_flight_max": int(inflight.max()), "slots": slots * len(servers)}
         log(f"[serve] {row}")
         out.append(row)
     if idx4 is not None:
         idx4.close()
     return {"indices": ["main index", "uniform4 1M x 4"] if idx4 is not None else ["main index"],
-            "requests": "K in {1,10,100}, ef uniform in [K,512], modes plain/bf16" +
-                        ("/learned (K<=64, main index)" if mlp is not None else ""),
+            "requests": "K in {1,10,100}, ef uniform in [K,512], modes plain/bf16/fp8 (main index), plain/bf16 "
+                        "(uniform4)" + ("/learned (K<=64, main index)" if mlp is not None else ""),
             "rates": out}
 
 
-def learned_glove_bench(hnsw, steps=10, warmup=2, target=0.90):
-    """The learned stop rule where it pays: glove_like 1.2M x 100 (inner
-    product) with the net trained and calibrated for it.  This stand-in reaches
-    recall@10 0.92 at ef 512, so the target here is 0.90; plain and learned
-    are each timed at the smallest swept ef that reaches it."""
+def learned_glove_bench(hnsw, steps=10, warmup=2, target=0.95):
+    """The learned stop rule on glove_like 1.2M x 100 (inner product) with the
+    net trained and calibrated for it: plain and learned are each timed at the
+    smallest ef of a grid of step 16 that reaches recall@10 >= 0.95."""
     import torch
 
     import synthdata
@@ -305,7 +321,7 @@ def learned_glove_bench(hnsw, steps=10, warmup=2, target=0.90):
     torch.cuda.synchronize()
     mlp = hnsw.Mlp.load(mpath)
     run = Runner(index, q, X, Q, K, gt.cpu().numpy(), g["metric"], torch.cuda.current_stream(), mlp)
-    efs = [e for e in EF_SWEEP if e >= 64 and e <= 512] + [448]
+    efs = list(range(128, 513, 16))
     out = {"workload": f"glove_like {g['n']}x{g['dim']} inner product, {nq} queries, K={K}",
            "target_recall": target, "net": {"tau": mlp.tau, "jmax": mlp.jmax, "period": mlp.period}}
     for form, mode in (("plain", 0), ("learned", 3)):
@@ -378,6 +394,134 @@ def deep10m_bench(hnsw, steps=10, warmup=2, n=10_000_000, nq=10_000, K=10, efs=(
             "counts": "gpu (the oracle does not search device-built graphs)", "results": rows}
 
 
+def _ef_for_recall(idx, q, X, Q, gt, K, target, efs, steps=5):
+    """Smallest ef of the grid whose recall@K reaches the target, with its
+    batch time (ms, mean of `steps` event-timed calls) and work counters."""
+    import torch
+
+    stream = torch.cuda.current_stream()
+    run = Runner(idx, q, X, Q, K, gt, 0, stream)
+    last = None
+    for ef in efs:
+        ids, _, cnt = run.search(ef, 0, counters=True)
+        torch.cuda.synchronize()
+        r = float(recall(ids.cpu().numpy(), X, Q, gt).mean())
+        last = (ef, r, cnt)
+        if r >= target:
+            break
+    ef, r, cnt = last
+    _, kern = run.time(ef, 0, steps, 2)
+    c = cnt.cpu().numpy().astype(np.float64)
+    return {"ef": ef, "recall": round(r, 4), "ms_per_batch": round(kern, 4),
+            "us_per_query": round(kern * 1000.0 / len(Q), 4), "dist_evals": round(float(c[:, 0].mean()), 1),
+            "reached": bool(r >= target)}
+
+
+def paper_experiments(hnsw):
+    """The paper's synthetic-data experiments (Sec. 4.1, Figs. 3, 6, 7, 11), on
+    graphs built by the library on the GPU; query time per query of a
+    10,000-query batch at the smallest ef reaching the recall target.
+      fig3: query time vs mL on random d = 4 vectors (10M), M = 6, with the
+            heuristic (Alg. 4) and with the M nearest (Alg. 3);
+      fig6: query time vs Mmax0 on the 1M sift_like set (M = 16), at recall
+            0.95 and 0.99;
+      fig7: Alg. 3 against Alg. 4 on 1M d = 10 vectors, uniform and from 100
+            isolated clusters, at recall 0.9, 0.95 and 0.99;
+      fig11: the ef needed for recall 0.9 / 0.99 (10-NN) vs the set size, d = 4."""
+    import math
+
+    import torch
+
+    import synthdata
+
+    efs = [10, 12, 16, 20, 24, 32, 40, 48, 64, 80, 96, 128, 160, 192, 256, 320, 384, 512, 640, 800, 1024]
+    out = {}
+
+    def setup(workload, n, nq=10000, K=10):
+        X = synthdata.base(workload, n)
+        Q = synthdata.queries(workload, nq)
+        return X, Q
+
+    def gt_of(idx, q, K):
+        _, gt = hnsw.bruteforce(idx, q, K)
+        torch.cuda.synchronize()
+        return gt.cpu().numpy()
+
+    # Fig. 3: mL on 10M random d=4
+    X, Q = setup("uniform4", 10_000_000)
+    q = torch.from_numpy(Q).cuda()
+    rows = []
+    gt = None
+    for heur in (True, False):
+        for mL in (0.0, 0.2, 0.4, 1.0 / math.log(6), 0.8, 1.2):
+            t0 = time.time()
+            idx = hnsw.Index.build(X, M=6, Mmax0=12, efC=100, mL=mL, seed=5003, heuristic=heur)
+            torch.cuda.synchronize()
+            bt = time.time() - t0
+            if gt is None:
+                gt = gt_of(idx, q, 10)
+            r = _ef_for_recall(idx, q, X, Q, gt, 10, 0.95, efs)
+            r.update(mL=round(mL, 4), selection="heuristic" if heur else "simple", build_s=round(bt, 2),
+                     layers=idx.info()["max_level"] + 1)
+            log(f"[fig3] {r}")
+            rows.append(r)
+            idx.close()
+    out["fig3_mL_uniform4_10M"] = {"M": 6, "Mmax0": 12, "efC": 100, "K": 10, "target": 0.95, "rows": rows}
+    del X
+
+    # Fig. 6: Mmax0 on sift_like 1M
+    X, Q = setup("sift_like", 1_000_000)
+    q = torch.from_numpy(Q).cuda()
+    rows = []
+    gt = None
+    for m0 in (16, 24, 32, 48, 64):
+        idx = hnsw.Index.build(X, M=16, Mmax0=m0, efC=200, seed=2003)
+        if gt is None:
+            gt = gt_of(idx, q, 10)
+        for target in (0.95, 0.99):
+            r = _ef_for_recall(idx, q, X, Q, gt, 10, target, efs)
+            r.update(Mmax0=m0, target=target)
+            log(f"[fig6] {r}")
+            rows.append(r)
+        idx.close()
+    out["fig6_Mmax0_sift_like_1M"] = {"M": 16, "efC": 200, "K": 10, "rows": rows}
+    del X
+
+    # Fig. 7: neighbour selection on clustered and uniform d=10
+    rows = []
+    for wl in ("uniform10", "clustered10"):
+        X, Q = setup(wl, 1_000_000)
+        q = torch.from_numpy(Q).cuda()
+        gt = None
+        for heur in (True, False):
+            idx = hnsw.Index.build(X, M=8, efC=100, seed=6003, heuristic=heur)
+            if gt is None:
+                gt = gt_of(idx, q, 10)
+            for target in (0.9, 0.95, 0.99):
+                r = _ef_for_recall(idx, q, X, Q, gt, 10, target, efs)
+                r.update(data=wl, selection="heuristic" if heur else "simple", target=target)
+                log(f"[fig7] {r}")
+                rows.append(r)
+            idx.close()
+    out["fig7_selection_d10_1M"] = {"M": 8, "Mmax0": 16, "efC": 100, "K": 10, "rows": rows}
+
+    # Fig. 11: ef needed for a fixed recall vs N, d=4
+    rows = []
+    for n in (10_000, 100_000, 1_000_000, 10_000_000):
+        X, Q = setup("uniform4", n)
+        q = torch.from_numpy(Q).cuda()
+        idx = hnsw.Index.build(X, M=6, Mmax0=12, efC=100, seed=5003)
+        gt = gt_of(idx, q, 10)
+        for target in (0.9, 0.99):
+            r = _ef_for_recall(idx, q, X, Q, gt, 10, target, list(range(10, 401, 2)), steps=3)
+            r.update(n=n, target=target)
+            log(f"[fig11] {r}")
+            rows.append(r)
+        idx.close()
+    out["fig11_ef_vs_n_uniform4"] = {"M": 6, "Mmax0": 12, "efC": 100, "K": 10, "rows": rows}
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -385,8 +529,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="sift_like", choices=sorted(WORKLOADS))
     ap.add_argument("--ef", type=int, default=0, help="time this ef (plain form only) instead of sweeping")
-    ap.add_argument("--forms", default="plain,bf16,fp8,learned",
-                    help="comma list of plain,bf16,fp8,learned (learned needs a trained net file)")
+    ap.add_argument("--forms", default="plain,bf16,fp8,u8,learned",
+                    help="comma list of plain,bf16,fp8,u8,learned (learned needs a trained net file)")
     ap.add_argument("--target-recall", type=float, default=0.95)
     ap.add_argument("--no-cpu-baseline", action="store_true",
                     help="skip the oracle legs (host timing and the oracle's work counts)")
@@ -395,6 +539,8 @@ def main():
     ap.add_argument("--no-glove", action="store_true", help="skip the learned-rule measurement on glove_like")
     ap.add_argument("--no-deep10m", action="store_true",
                     help="skip the 10M x 96 low-precision measurement (graph built on the GPU)")
+    ap.add_argument("--paper-experiments", action="store_true",
+                    help="run the paper's synthetic-data experiments (Figs. 3, 6, 7, 11) instead; prints their JSON")
     ap.add_argument("--copy-probe-bytes", type=int, default=0,
                     help="also run a plain device-to-device copy of this size (counter calibration)")
     a = ap.parse_args()
@@ -408,6 +554,10 @@ def main():
     import paper_1603_09320_amd as hnsw
     import synthdata
 
+    if a.paper_experiments:
+        torch.cuda.set_device(0)
+        print(json.dumps({"paper_experiments": paper_experiments(hnsw)}), flush=True)
+        return
     path, n, nq, K = WORKLOADS[a.workload]
     gpath = os.path.join(ROOT, path)
     if not os.path.exists(gpath):
@@ -444,13 +594,16 @@ def main():
         else:
             forms.remove("learned")
     run = Runner(index, q, X, Q, K, gt_d64, graph["metric"], stream, mlp)
-    mode_of = {"plain": 0, "bf16": 1, "fp8": 2, "learned": 3}
+    mode_of = {"plain": 0, "bf16": 1, "fp8": 2, "learned": 3, "u8": 4}
     results = {}
     gpu_cnt = {}
+    rerank_of = {0: False, 1: True, 2: True, 3: False, 4: True}
     for form in forms:
         mode = mode_of[form]
-        if mode in (1, 2):
+        if mode in (1, 2, 4):
             index.add_lowp(mode)
+        if mode == 4:
+            rerank_of[4] = not index.read_lowp(4)[1]  # an exact 8-bit copy needs no re-rank
         if form == "plain" and a.ef:
             ids, _ = run.search(a.ef, 0)
             torch.cuda.synchronize()
@@ -463,7 +616,7 @@ def main():
         cnt = cnt.cpu().numpy().astype(np.uint32)
         gpu_cnt[form] = cnt
         ms, kern_ms = run.time(ef, mode, a.steps, a.warmup)
-        alg = algorithmic_bytes(cnt, graph, K, mode, ef, includes_rerank=True)
+        alg = algorithmic_bytes(cnt, graph, K, mode, ef, includes_rerank=True, reranks=rerank_of[mode])
         c = cnt.astype(np.float64)
         results[form] = {"ef": ef, "recall": round(rec, 5), "qps": round(nq / (ms / 1000.0), 1),
                          "ms_per_step": round(ms, 4), "kernel_ms": round(kern_ms, 4),
@@ -516,7 +669,8 @@ def main():
         # algorithmic bytes from the oracle's counts (exact visited sets) at each form's ef
         for form, r in results.items():
             oc = oracle_counts(G, X, Q, K, r["ef"], mode_of[form], mpath if form == "learned" else None)
-            alg = algorithmic_bytes(oc, graph, K, mode_of[form], r["ef"], includes_rerank=False)
+            alg = algorithmic_bytes(oc, graph, K, mode_of[form], r["ef"], includes_rerank=False,
+                                    reranks=rerank_of[mode_of[form]])
             oc = oc.astype(np.float64)
             r["bytes_per_step"] = alg
             r["algorithmic_GBs"] = round(alg / (r["kernel_ms"] / 1000.0) / 1e9, 1)

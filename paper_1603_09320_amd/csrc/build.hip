@@ -44,6 +44,7 @@ struct BuildArgs {
     uint32_t wpow2;          // LDS slots for W (power of two >= efC, >= 64)
     uint32_t ht_slots;       // visited-table slots (>= 256)
     int keep_pruned;         // Alg. 4 keepPrunedConnections
+    int simple;              // SELECT-NEIGHBORS-SIMPLE (Alg. 3) instead of the heuristic
     uint64_t upper_base;     // upper_off of the batch's first element with a layer >= 1 (row origin of its pairs)
     uint64_t *pair_key;      // [(batch + batch upper rows) * M] (lc << 32 | e), or kNoPair
     uint32_t *pair_val;      // the new element q of each pair
@@ -58,6 +59,7 @@ struct LinkArgs {
     const uint32_t *n_runs;   // device scalar
     uint32_t wpow2;           // LDS slots of the candidate list (power of two, <= 1024)
     int keep_pruned;
+    int simple;               // Alg. 3 instead of Alg. 4
 };
 
 namespace {
@@ -185,6 +187,23 @@ __device__ uint32_t select_heuristic_w(const DevIndex &ix, const RowSource &src,
     return r;
 }
 
+// SELECT-NEIGHBORS-SIMPLE (Alg. 3): the Mk nearest of W[0..m) (sorted) into R.
+__device__ __forceinline__ uint32_t select_simple_w(const BuildLds &b, uint32_t m, uint32_t Mk) {
+    const int lane = lane_id();
+    const uint32_t r = m < Mk ? m : Mk;
+    if (lane < static_cast<int>(r)) b.R[lane] = key_id(b.s.W[lane]);
+    wave_sync();
+    return r;
+}
+
+// Alg. 3 or Alg. 4 on the sorted candidates W[0..m).
+template <int G, int F, int METRIC, bool BUF>
+__device__ __forceinline__ uint32_t select_w(const DevIndex &ix, const RowSource &src, const BuildLds &b, uint32_t m,
+                                             uint32_t Mk, bool keep_pruned, bool simple) {
+    if (simple) return select_simple_w(b, m, Mk);
+    return select_heuristic_w<G, F, METRIC, BUF>(ix, src, b, m, Mk, keep_pruned);
+}
+
 // SEARCH-LAYER (Alg. 2) on layer lc with ef candidates, entered from W[0..wsize)
 // (sorted keys, flags clear, ids already in the visited table).
 template <int G, int F, int METRIC, bool BUF>
@@ -280,7 +299,7 @@ __global__ __launch_bounds__(64) void build_insert_kernel(DevIndex ix, BuildArgs
         beam_layer<G, F, METRIC, BUF>(ix, src, Q, b, a.ht_slots, a.efC, wsize, lc);
         for (uint32_t i = lane; i < wsize; i += 64) b.s.W[i] &= ~1ull;
         wave_sync();
-        const uint32_t r = select_heuristic_w<G, F, METRIC, BUF>(ix, src, b, wsize, M, a.keep_pruned != 0);
+        const uint32_t r = select_w<G, F, METRIC, BUF>(ix, src, b, wsize, M, a.keep_pruned != 0, a.simple != 0);
         const uint32_t width = lc ? ix.Mmax : ix.Mmax0;
         uint32_t *row = row_of(ix, q, lc);
         if (lane < static_cast<int>(width)) row[lane] = lane < static_cast<int>(r) ? b.R[lane] : kNoLink;
@@ -365,7 +384,7 @@ __global__ __launch_bounds__(64) void build_link_kernel(DevIndex ix, LinkArgs a)
             uint32_t p2 = 64;
             while (p2 < m) p2 <<= 1;
             sort_w(b.s.W, m, p2);
-            have = select_heuristic_w<G, F, METRIC, BUF>(ix, src, b, m, cap, a.keep_pruned != 0);
+            have = select_w<G, F, METRIC, BUF>(ix, src, b, m, cap, a.keep_pruned != 0, a.simple != 0);
         }
         if (lane < static_cast<int>(cap)) row[lane] = lane < static_cast<int>(have) ? b.R[lane] : kNoLink;
         wave_sync();
@@ -624,6 +643,7 @@ hnsw_status hnsw_index_build(const float *vectors, uint32_t n, uint32_t dim, int
         ba.ht_slots = 1u << lg;
     }
     ba.keep_pruned = pr->keep_pruned;
+    ba.simple = pr->select_simple;
     ba.pair_key = pk;
     ba.pair_val = pv;
     LinkArgs la{};
@@ -634,6 +654,7 @@ hnsw_status hnsw_index_build(const float *vectors, uint32_t n, uint32_t dim, int
     la.n_runs = nruns;
     la.wpow2 = 512;
     la.keep_pruned = pr->keep_pruned;
+    la.simple = pr->select_simple;
 
     uint32_t entry = 0, top = lv[0];
     uint32_t s = 1;

@@ -65,7 +65,12 @@ __device__ __forceinline__ uint64_t load_sys64(const uint64_t *p) {
 // per-lane copies of k/ef/mode it may treat the loop as divergent and let
 // lanes leave it at different times, which defers the completion flag of a
 // served request until the others exit.
-template <int G, int F, int METRIC>
+// LOWP: the low-precision copies this server's kernel can traverse (bit 0
+// BF16, bit 1 FP8).  Each kind's search is inlined into the request loop, and
+// the registers follow: 102 for plain and learned alone (four waves per
+// SIMD), 182 with BF16 (two), 256 with FP8 (one), so a server instantiates
+// only the kinds its index holds.
+template <int G, int F, int METRIC, int LOWP>
 __global__ __launch_bounds__(64) void serve_kernel(DevIndex ix, SearchArgs a, ServeArgs sv) {
     extern __shared__ __align__(16) uint8_t smem[];
     const WaveLds s = carve<true>(smem, a);
@@ -110,8 +115,10 @@ __global__ __launch_bounds__(64) void serve_kernel(DevIndex ix, SearchArgs a, Se
         job.dists = sv.out_d + static_cast<size_t>(slot) * sv.kmax;
         job.counters = sv.counters + static_cast<size_t>(slot) * 4;
         job.trace = nullptr;
-        if (mode == HNSW_MODE_BF16 && ix.vbf16)
+        if ((LOWP & 1) && mode == HNSW_MODE_BF16 && ix.vbf16)
             search_one<G, F, METRIC, kBF16, false, true>(ix, a, job, s);
+        else if ((LOWP & 2) && mode == HNSW_MODE_FP8 && ix.vfp8)
+            search_one<G, F, METRIC, kFP8, false, true>(ix, a, job, s);
         else if (mode == HNSW_MODE_LEARNED && a.mlp.w1)
             search_one<G, F, METRIC, kF32, true, true>(ix, a, job, s);
         else
@@ -122,15 +129,26 @@ __global__ __launch_bounds__(64) void serve_kernel(DevIndex ix, SearchArgs a, Se
     }
 }
 
+template <int G, int F, int LOWP>
+hipError_t launch_serve_gfl(const DevIndex &ix, const SearchArgs &a, const ServeArgs &sv, uint32_t waves,
+                            hipStream_t st) {
+    const size_t lds = search_lds_bytes(a, true);
+    if (ix.metric == HNSW_IP)
+        hipLaunchKernelGGL((serve_kernel<G, F, HNSW_IP, LOWP>), dim3(waves), dim3(64), lds, st, ix, a, sv);
+    else
+        hipLaunchKernelGGL((serve_kernel<G, F, HNSW_L2SQ, LOWP>), dim3(waves), dim3(64), lds, st, ix, a, sv);
+    return hipGetLastError();
+}
+
 template <int G, int F>
 hipError_t launch_serve_gf(const DevIndex &ix, const SearchArgs &a, const ServeArgs &sv, uint32_t waves,
                            hipStream_t st) {
-    const size_t lds = search_lds_bytes(a, true);
-    if (ix.metric == HNSW_IP)
-        hipLaunchKernelGGL((serve_kernel<G, F, HNSW_IP>), dim3(waves), dim3(64), lds, st, ix, a, sv);
-    else
-        hipLaunchKernelGGL((serve_kernel<G, F, HNSW_L2SQ>), dim3(waves), dim3(64), lds, st, ix, a, sv);
-    return hipGetLastError();
+    switch ((ix.vbf16 ? 1 : 0) | (ix.vfp8 ? 2 : 0)) {
+        case 0: return launch_serve_gfl<G, F, 0>(ix, a, sv, waves, st);
+        case 1: return launch_serve_gfl<G, F, 1>(ix, a, sv, waves, st);
+        case 2: return launch_serve_gfl<G, F, 2>(ix, a, sv, waves, st);
+        default: return launch_serve_gfl<G, F, 3>(ix, a, sv, waves, st);
+    }
 }
 
 }  // namespace
@@ -172,6 +190,7 @@ struct hnsw_server {
     hipStream_t stream;
     uint64_t next_ticket;
     uint32_t slots, kmax, efmax, dim;
+    int lowp;  // copies the kernel traverses (bit 0 BF16, bit 1 FP8), fixed at start
     bool have_mlp;
     double budget_s;
 };
@@ -241,6 +260,7 @@ hnsw_status hnsw_server_start(const hnsw_index *index, const hnsw_mlp *mlp, uint
     s->efmax = ef_max;
     s->dim = index->ix.dim;
     s->have_mlp = mlp != nullptr;
+    s->lowp = (index->ix.vbf16 ? 1 : 0) | (index->ix.vfp8 ? 2 : 0);
     s->budget_s = budget_s;
     std::vector<void *> got;
     s->ring = host_alloc<hnsw::ServeReq>(slots, got);
@@ -281,10 +301,10 @@ hnsw_status hnsw_server_start(const hnsw_index *index, const hnsw_mlp *mlp, uint
     hnsw::SearchArgs &a = s->a;
     a = hnsw::SearchArgs{};
     a.wcap = (ef_max + 63) & ~63u;
-    a.wpow2 = 64;
-    while (a.wpow2 < a.wcap) a.wpow2 <<= 1;
+    a.wslots = 64;
+    while (a.wslots < a.wcap) a.wslots <<= 1;
     uint32_t lg = 10;
-    while (lg < 12 && (1u << lg) < 8u * ef_max) ++lg;
+    while (lg < 11 && (1u << lg) < 8u * ef_max) ++lg;
     a.ht_slots = 1u << lg;
     a.mode = HNSW_MODE_PLAIN;
     a.mlp = mlp ? mlp->net : hnsw::DevMlp{};
@@ -305,8 +325,8 @@ hnsw_status hnsw_server_submit(hnsw_server *srv, const float *query, uint32_t k,
     const uint32_t efe = ef < k ? k : ef;
     if (k > srv->kmax || efe > srv->efmax) return HNSW_ERR_UNSUPPORTED;
     const hnsw::DevIndex &ix = srv->index->ix;
-    if (mode == HNSW_MODE_FP8) return HNSW_ERR_UNSUPPORTED;  // the serving kernel runs plain, BF16 and learned
-    if (mode == HNSW_MODE_BF16 && !ix.vbf16) return HNSW_ERR_INVALID_ARG;
+    if (mode == HNSW_MODE_BF16 && !(srv->lowp & 1)) return HNSW_ERR_INVALID_ARG;
+    if (mode == HNSW_MODE_FP8 && !(srv->lowp & 2)) return HNSW_ERR_INVALID_ARG;
     if (mode == HNSW_MODE_LEARNED && (!srv->have_mlp || k > 64)) return HNSW_ERR_UNSUPPORTED;
     const uint32_t slot = static_cast<uint32_t>(srv->next_ticket % srv->slots);
     hnsw::ServeReq *r = srv->ring + slot;

@@ -63,10 +63,12 @@ def train(feats, labels, epochs=6, batch=4096, lr=2e-3, lam=0.25, seed=0, log=pr
     return P.cpu().numpy()
 
 
-def calibrate(workload, params, taus, jmaxes=(0, 1, 2), K=10, efs=(512,), nq=10000, target=0.95, log=print):
-    """Recall and time of the learned search for each (ef, tau, jmax) on
+def calibrate(workload, params, taus, jmaxes=(0, 1, 2), K=10, efs=(512,), nq=10000, target=0.95, shifts=(0.0,),
+              log=print):
+    """Recall and time of the learned search for each (ef, tau, jmax, shift) on
     held-out queries; the fastest setting whose mean recall@K reaches the
-    target wins."""
+    target wins.  `shift` is added to the bias of output 1 (the ef step), so
+    that a positive shift asks for fewer halvings of ef than the net predicts."""
     import torch
 
     import paper_1603_09320_amd as hnsw
@@ -83,8 +85,11 @@ def calibrate(workload, params, taus, jmaxes=(0, 1, 2), K=10, efs=(512,), nq=100
     _, gt = hnsw.bruteforce(idx, q, K)
     gt = gt.cpu().numpy()
     rows = []
-    for ef, jmax, tau in [(e, j, t) for e in efs for j in jmaxes for t in taus]:
-        mlp = hnsw.Mlp(params, tau=tau, jmax=jmax)
+    for ef, jmax, tau, sh in [(e, j, t, h) for e in efs for j in jmaxes for t in taus
+                              for h in (shifts if j > 0 else (0.0,))]:
+        p2 = np.array(params, dtype=np.float32, copy=True)
+        p2[-1] += np.float32(sh)
+        mlp = hnsw.Mlp(p2, tau=tau, jmax=jmax)
         ids, _ = idx.search(q, K, ef, mode=hnsw.MODE_LEARNED, mlp=mlp)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
@@ -100,8 +105,8 @@ def calibrate(workload, params, taus, jmaxes=(0, 1, 2), K=10, efs=(512,), nq=100
             d = ((x - Q[:, None, :].astype(np.float64)) ** 2).sum(-1)
         dk = gt[:, K - 1:K]  # slack: the two fp64 sums may add the terms in other orders
         rec = float(((d <= dk + 1e-9 * np.abs(dk) + 1e-12).sum(1) / K).mean())
-        rows.append((tau, jmax, rec, ms, ef))
-        log(f"[calibrate] ef={ef} tau={tau:+.3f} jmax={jmax} recall={rec:.4f} ms={ms:.3f}")
+        rows.append((tau, jmax, rec, ms, ef, sh))
+        log(f"[calibrate] ef={ef} tau={tau:+.3f} jmax={jmax} shift={sh:+.2f} recall={rec:.4f} ms={ms:.3f}")
     ok = [r for r in rows if r[2] >= target]
     best = min(ok, key=lambda r: r[3]) if ok else max(rows, key=lambda r: r[2])
     return best, rows
@@ -120,6 +125,7 @@ def main():
     c.add_argument("--ef", default="512", help="comma list of ef values to try")
     c.add_argument("--jmax", default="0,1,2", help="comma list of ef-halving limits to try")
     c.add_argument("--target", type=float, default=0.95)
+    c.add_argument("--shift", default="0", help="comma list of shifts of the ef-step output's bias to try")
     a = ap.parse_args()
     sys.path.insert(0, ROOT)
     if a.cmd == "train":
@@ -133,11 +139,14 @@ def main():
         taus = [8.0, 6.0, 5.0, 4.0, 3.5, 3.0, 2.5, 2.0, 1.5, 1.0, 0.5, 0.0]
         jmaxes = [int(j) for j in a.jmax.split(",")]
         efs = [int(e) for e in a.ef.split(",")]
-        best, rows = calibrate(a.workload, z["params"], taus, jmaxes, efs=efs, target=a.target)
-        np.savez(a.net, params=z["params"], tau=best[0], jmax=best[1], period=int(z["period"]),
+        shifts = [float(h) for h in a.shift.split(",")]
+        best, rows = calibrate(a.workload, z["params"], taus, jmaxes, efs=efs, target=a.target, shifts=shifts)
+        params = np.array(z["params"], dtype=np.float32, copy=True)
+        params[-1] += np.float32(best[5])
+        np.savez(a.net, params=params, tau=best[0], jmax=best[1], period=int(z["period"]),
                  max_ckpt=int(z["max_ckpt"]), ef=best[4], calib=np.array(rows))
-        print(f"[calibrate] chose ef={best[4]} tau={best[0]} jmax={best[1]} recall={best[2]:.4f} ms={best[3]:.3f}",
-              flush=True)
+        print(f"[calibrate] chose ef={best[4]} tau={best[0]} jmax={best[1]} shift={best[5]} recall={best[2]:.4f} "
+              f"ms={best[3]:.3f}", flush=True)
 
 
 if __name__ == "__main__":

@@ -20,6 +20,10 @@ Workloads (stand-ins for the paper's datasets, which are not available):
   0.5.  Stand-in for DEEP (Table 1).
 * ``uniform4``    -- 1,000,000 x 4 U[0,1).  Stand-in for the d=4 random sets
   (Sec. 4.1, Table 1).
+* ``uniform10`` / ``clustered10`` -- d=10 random vectors, U[0,1) or drawn from
+  100 isolated clusters (centres U[0,1)^10, each point a centre plus 0.02 g),
+  the two data sets of the paper's comparison of neighbour selection methods
+  (Sec. 4.1).
 
 Every array is float32, C-contiguous, shape [n][d].  Generation is chunked
 with fixed chunk sizes and separate PCG64 streams per purpose, so the bytes
@@ -38,10 +42,14 @@ SEEDS = {
     "glove_like": dict(mix=3000, base=3001, queries=3002, train=3003),
     "deep_like": dict(mix=4000, base=4001, queries=4002, train=4004),
     "uniform4": dict(base=5001, queries=5002, train=5004),
+    "uniform10": dict(base=6001, queries=6002, train=6004),
+    "clustered10": dict(mix=7000, base=7001, queries=7002, train=7004),
 }
 
-DIMS = {"uniform16": 16, "sift_like": 128, "glove_like": 100, "deep_like": 96, "uniform4": 4}
-METRIC = {"uniform16": "l2", "sift_like": "l2", "glove_like": "ip", "deep_like": "l2", "uniform4": "l2"}
+DIMS = {"uniform16": 16, "sift_like": 128, "glove_like": 100, "deep_like": 96, "uniform4": 4, "uniform10": 10,
+        "clustered10": 10}
+METRIC = {"uniform16": "l2", "sift_like": "l2", "glove_like": "ip", "deep_like": "l2", "uniform4": "l2",
+          "uniform10": "l2", "clustered10": "l2"}
 
 
 def _rng(seed: int, stream: int) -> np.random.Generator:
@@ -119,6 +127,17 @@ def _deep_points(n: int, seed: int, centres: np.ndarray) -> np.ndarray:
     return out
 
 
+def _clustered_points(n: int, seed: int, mix_seed: int) -> np.ndarray:
+    centres = _rng(mix_seed, 0).random((100, 10))
+    ga, gn = _rng(seed, 1), _rng(seed, 2)
+    out = np.empty((n, 10), dtype=np.float32)
+    for s in range(0, n, CHUNK):
+        e = min(n, s + CHUNK)
+        j = ga.integers(0, 100, size=e - s)
+        out[s:e] = (centres[j] + 0.02 * gn.standard_normal((e - s, 10))).astype(np.float32)
+    return out
+
+
 def base(workload: str, n: int) -> np.ndarray:
     """The first ``n`` base vectors of ``workload`` (prefix-stable in n only per CHUNK)."""
     sd = SEEDS[workload]
@@ -126,6 +145,10 @@ def base(workload: str, n: int) -> np.ndarray:
         return _uniform(n, 16, sd["base"])
     if workload == "uniform4":
         return _uniform(n, 4, sd["base"])
+    if workload == "uniform10":
+        return _uniform(n, 10, sd["base"])
+    if workload == "clustered10":
+        return _clustered_points(n, sd["base"], sd["mix"])
     if workload == "sift_like":
         return _sift_points(n, sd["base"], _sift_centres(sd["mix"]))
     if workload == "glove_like":
@@ -146,6 +169,10 @@ def queries(workload: str, n: int, train: bool = False) -> np.ndarray:
         return _uniform(n, 16, seed)
     if workload == "uniform4":
         return _uniform(n, 4, seed)
+    if workload == "uniform10":
+        return _uniform(n, 10, seed)
+    if workload == "clustered10":
+        return _clustered_points(n, seed, sd["mix"])
     if workload == "sift_like":
         return _sift_points(n, seed, _sift_centres(sd["mix"]))
     if workload == "glove_like":

@@ -236,3 +236,23 @@ def test_deep_like_10m_device_build_and_lowp_search(hnsw):
     assert rec[(0, 128)] >= 0.95 and rec[(0, 256)] >= 0.99
     for ef in (64, 128, 256):
         assert rec[(1, ef)] >= rec[(0, ef)] - 0.01 and rec[(2, ef)] >= rec[(0, ef)] - 0.02
+
+
+@pytest.mark.parametrize("mL_scale", [1.0, 0.0])
+def test_singleton_batches_simple_selection_equal_oracle(hnsw, mL_scale):
+    """Alg. 3 (the M nearest) in place of the heuristic, batches of one: the
+    device build equals the oracle's INSERT; with mL = 0 (one layer) too."""
+    import math
+
+    n, M = 1200, 6
+    print(f"case GPU build simple selection mL x{mL_scale}", flush=True)
+    X = synthdata.base("uniform16", n)
+    mL = mL_scale / math.log(M)
+    G = oracle.Graph.build(X, M=M, efC=25, seed=9, mL=mL, heuristic=False)
+    want = G.packed()
+    idx = hnsw.Index.build(X, M=M, efC=25, seed=9, mL=mL, heuristic=False, batch_div=n + 1)
+    got = idx.export()
+    assert np.array_equal(got["levels"], want["levels"]) and got["entry_point"] == want["entry_point"]
+    lg, lw = _lists(got), _lists(want)
+    bad = [k for k in lw if lg.get(k) != lw[k]]
+    assert not bad, (len(bad), bad[:5])

@@ -1,7 +1,7 @@
 """Continuous-batching serving loop on the GPU: every request's result equals
 the oracle's search with the same (query, k, ef, mode) -- the plain search,
-the low-precision mirror for BF16, the learned search with the same net --
-and the standalone batch search, alone and in a mixed Poisson stream
+the low-precision mirror for BF16 and FP8, the learned search with the same
+net -- and the standalone batch search, alone and in a mixed Poisson stream
 over two indices; admission backpressure and refusals."""
 import numpy as np
 import pytest
@@ -101,7 +101,7 @@ def test_submit_poll_equals_batch(hnsw, setup):
         for i in range(200):
             k = int(rng.choice([1, 10, 64]))
             ef = int(rng.integers(k, 257))
-            mode = int(rng.choice([hnsw.MODE_PLAIN, hnsw.MODE_BF16, hnsw.MODE_LEARNED]))
+            mode = int(rng.choice([hnsw.MODE_PLAIN, hnsw.MODE_BF16, hnsw.MODE_FP8, hnsw.MODE_LEARNED]))
             while True:
                 try:
                     t = srv.submit(Q[i], k, ef, mode)
@@ -138,8 +138,8 @@ def test_backpressure_and_refusals(hnsw, setup):
             srv.submit(Q[0], 11, 20)
         assert e.value.code == 4  # k above k_max
         with pytest.raises(hnsw.HnswError) as e:
-            srv.submit(Q[0], 10, 20, hnsw.MODE_FP8)
-        assert e.value.code == 4
+            srv.submit(Q[0], 10, 20, hnsw.MODE_U8)  # the serving kernel runs plain, learned, BF16 and FP8
+        assert e.value.code == 1
         tickets = [srv.submit(Q[i], 10, 32) for i in range(8)]
         with pytest.raises(hnsw.HnswError) as e:
             srv.submit(Q[8], 10, 32)
@@ -171,7 +171,7 @@ def test_mixed_poisson_stream_two_indices(hnsw, setup):
         qidx = rng.integers(0, 400, n).astype(np.uint32)
         k = rng.choice([1, 10, 100], n).astype(np.uint32)
         ef = np.array([rng.integers(kk, 513) for kk in k], dtype=np.uint32)
-        mode = rng.choice([hnsw.MODE_PLAIN, hnsw.MODE_BF16, hnsw.MODE_LEARNED], n).astype(np.int32)
+        mode = rng.choice([hnsw.MODE_PLAIN, hnsw.MODE_BF16, hnsw.MODE_FP8, hnsw.MODE_LEARNED], n).astype(np.int32)
         mode[(k > 64) & (mode == hnsw.MODE_LEARNED)] = hnsw.MODE_PLAIN
         r = hnsw.replay(servers, [setup[nm][1] for nm in names], arrival, server_of, qidx, k, ef, mode,
                         out_stride=100, timeout_s=30.0)

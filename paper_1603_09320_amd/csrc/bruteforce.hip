@@ -192,6 +192,251 @@ __device__ void wave_bitonic(uint64_t *a, int len) {
         }
 }
 
+
+// ---------------------------------------------------------------- bf_tile
+//
+// The scan for k <= 32 (KP = 32 or 64 candidates per query and chunk).  A
+// block of W waves takes 16 W queries; each wave owns 16 of them, holds their
+// coordinates in registers as the A operand of v_mfma_f32_16x16x4f32 and keeps
+// their candidate lists in its own part of LDS, so that the selection never
+// waits for the other waves.  The block streams its chunk of the base set
+// through one LDS tile of 32 rows: the next tile is loaded into registers
+// while the waves multiply the current one, and stored between two block
+// barriers.  The dimension is split over the four lane groups of a wave
+// (group g holds coordinates [g S, g S + S) of its row, 4 S >= the padded
+// dimension; coordinates past the stored row are zero in LDS and in the A
+// operand), so one MFMA step s adds coordinates s, S + s, 2S + s and 3S + s
+// of 16 queries x 16 rows, and every lane reads four steps of B with one
+// 16-byte LDS load.  Rows in LDS are padded by 4 floats against bank
+// conflicts.
+//
+// Candidate list of a query: KP sorted keys (the best so far, +inf-keys at
+// the start) followed by up to kTail unsorted admissions.  A ranking key
+// below the threshold (the KP-th best key) is appended; once the tail could
+// overflow during the next tile, the wave sorts the tail and merges it into
+// the sorted part by rank (a binary search of each key in the other list),
+// keeping the KP best and tightening the threshold.  A merge happens about
+// once per kTail - kTRows admissions instead of once per tile that admits
+// anything.
+constexpr int kTRows = 32;   // base rows per tile
+constexpr int kTail = 64;    // unsorted admissions held beyond the KP best
+
+// Waves per block (16 queries each): four for KP = 32 (66 KB of LDS, two
+// blocks per CU), two for KP = 64 (the longer lists).
+constexpr int bf_tile_waves(int kp) { return kp <= 32 ? 4 : 2; }
+
+// Count of the n (power of two) sorted keys a[] that are < x (strict) or
+// <= x, by a fixed-step binary search.
+template <int N, bool kLessEq>
+__device__ __forceinline__ int sorted_count(const uint64_t *a, uint64_t x) {
+    int c = 0;
+#pragma unroll
+    for (int step = N / 2; step >= 1; step >>= 1) {
+        const uint64_t v = a[c + step - 1];
+        if (kLessEq ? v <= x : v < x) c += step;
+    }
+    const uint64_t v = a[c];
+    return c + ((kLessEq ? v <= x : v < x) ? 1 : 0);
+}
+
+// Merge the tail of one query's list into its sorted KP best (whole wave).
+// On return bq[0..KP) holds the KP smallest keys of bq[0..count), sorted.
+template <int KP>
+__device__ void merge_tail(uint64_t *bq, uint32_t count, int lane) {
+    if (KP + lane >= static_cast<int>(count)) bq[KP + lane] = kMaxKey;  // kTail == 64 lanes
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+    wave_bitonic(bq + KP, kTail);
+    // stable merge (sorted part first on equal keys): ranks are distinct
+    const uint64_t t = bq[KP + lane];
+    const int rt = lane + sorted_count<KP, true>(bq, t);
+    uint64_t p = kMaxKey;
+    int rp = KP;
+    if (lane < KP) {
+        p = bq[lane];
+        rp = lane + sorted_count<kTail, false>(bq + KP, p);
+    }
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+    if (rp < KP) bq[rp] = p;
+    if (rt < KP) bq[rt] = t;
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+}
+
+template <int KP, int S>
+__global__ __launch_bounds__(256) void bf_tile(DevIndex ix, const float *Q, uint32_t nq, const float *xnorm,
+                                               uint32_t chunk, uint32_t nchunks, uint64_t *partial) {
+    constexpr int CAP = KP + kTail;
+    constexpr int WAVES = bf_tile_waves(KP), THREADS = 64 * WAVES, kTQ = 16 * WAVES;
+    constexpr int UPT = (kTRows * S + THREADS - 1) / THREADS;  // float4 units per thread and tile (at most)
+    constexpr uint32_t RS = 4 * S + 4;  // LDS row stride (floats)
+    extern __shared__ __align__(16) uint8_t smem[];
+    float *tile = reinterpret_cast<float *>(smem);                            // [kTRows][RS]
+    uint64_t *bufs = reinterpret_cast<uint64_t *>(smem + kTRows * RS * 4);    // [kTQ][CAP]
+    uint64_t *thrs = bufs + kTQ * CAP;                                        // [kTQ]
+    uint32_t *cnts = reinterpret_cast<uint32_t *>(thrs + kTQ);                 // [kTQ]
+
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int g = lane >> 4, j = lane & 15;
+    const uint32_t q0 = blockIdx.x * kTQ + wave * 16;
+    const uint32_t ch = blockIdx.y;
+    const uint32_t b_lo = ch * chunk, b_hi = min(ix.n, b_lo + chunk);
+    const uint32_t units_row = ix.stride4;  // float4 units per stored row
+    uint64_t *mybuf = bufs + static_cast<size_t>(wave) * 16 * CAP;
+    uint64_t *mythr = thrs + wave * 16;
+    uint32_t *mycnt = cnts + wave * 16;
+
+    // A operand: query q0 + j, coordinates g*S + s
+    float a[S];
+    {
+        const uint32_t q = q0 + j;
+#pragma unroll
+        for (int s = 0; s < S; ++s) {
+            const uint32_t c = g * S + s;
+            a[s] = (q < nq && c < ix.dim) ? Q[static_cast<size_t>(q) * ix.dim + c] : 0.f;
+        }
+    }
+    // every list starts as KP +inf-keys (sorted) and an empty tail
+    for (int e = lane; e < 16 * CAP; e += 64) mybuf[e] = kMaxKey;
+    if (lane < 16) {
+        mycnt[lane] = KP;
+        mythr[lane] = q0 + lane < nq ? kMaxKey : 0;  // a missing query admits nothing
+    }
+    // zero the tile once: columns beyond the stored row stay zero
+    for (uint32_t e = tid; e < kTRows * RS; e += THREADS) tile[e] = 0.f;
+
+    const uint32_t ntiles = b_lo < b_hi ? (b_hi - b_lo + kTRows - 1) / kTRows : 0;
+    // the thread's part of every tile copy, fixed over the tiles: float4 unit
+    // u is column unit c of row frow[u] (~0 when the thread has no unit u)
+    uint32_t frow[UPT > 0 ? UPT : 1], goff[UPT > 0 ? UPT : 1], loff[UPT > 0 ? UPT : 1];
+#pragma unroll
+    for (int u = 0; u < UPT; ++u) {
+        const uint32_t un = static_cast<uint32_t>(tid) + static_cast<uint32_t>(THREADS) * u;
+        const uint32_t r = un / units_row, c = un % units_row;
+        frow[u] = un < kTRows * units_row ? r : ~0u;
+        goff[u] = r * units_row + c;
+        loff[u] = r * RS + 4 * c;
+    }
+    float4 stage[UPT > 0 ? UPT : 1];
+    float xn_next[2] = {0.f, 0.f};
+    const bool l2 = ix.metric == HNSW_L2SQ;
+    auto fetch = [&](uint32_t t) {
+        const uint32_t r0 = b_lo + t * kTRows;
+        const uint32_t lim = b_hi - r0;  // rows of the chunk left from r0 (>= 1)
+        const float4 *src = reinterpret_cast<const float4 *>(ix.vec) + static_cast<size_t>(r0) * units_row;
+#pragma unroll
+        for (int u = 0; u < UPT; ++u)
+            stage[u] = frow[u] < lim ? src[goff[u]] : make_float4(0.f, 0.f, 0.f, 0.f);
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+            const uint32_t rr = 16 * h + j;
+            xn_next[h] = (l2 && rr < lim) ? xnorm[r0 + rr] : 0.f;
+        }
+    };
+    auto store = [&]() {
+#pragma unroll
+        for (int u = 0; u < UPT; ++u)
+            if (frow[u] != ~0u) *reinterpret_cast<float4 *>(tile + loff[u]) = stage[u];
+    };
+    float xn[2] = {0.f, 0.f};
+    __syncthreads();
+    if (ntiles) {
+        fetch(0);
+        store();
+        xn[0] = xn_next[0];
+        xn[1] = xn_next[1];
+    }
+    __syncthreads();
+    // thresholds of the lane's four queries (4 g + r), kept in registers
+    uint64_t thr[4];
+#pragma unroll
+    for (int r = 0; r < 4; ++r) thr[r] = mythr[4 * g + r];
+    for (uint32_t t = 0; t < ntiles; ++t) {
+        if (t + 1 < ntiles) fetch(t + 1);  // in flight during the products
+        // four independent accumulation chains (two row halves x two halves
+        // of the coordinate steps), interleaved so that no product waits for
+        // the one before it
+        v4f acc[2][2] = {{{0.f, 0.f, 0.f, 0.f}, {0.f, 0.f, 0.f, 0.f}}, {{0.f, 0.f, 0.f, 0.f}, {0.f, 0.f, 0.f, 0.f}}};
+#pragma unroll
+        for (int s = 0; s < S; s += 4) {
+            const int p = (s >> 2) & 1;
+            const float4 b0 = *reinterpret_cast<const float4 *>(tile + j * RS + g * S + s);
+            const float4 b1 = *reinterpret_cast<const float4 *>(tile + (16 + j) * RS + g * S + s);
+            acc[0][p] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[s], b0.x, acc[0][p], 0, 0, 0);
+            acc[1][p] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[s], b1.x, acc[1][p], 0, 0, 0);
+            acc[0][p] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[s + 1], b0.y, acc[0][p], 0, 0, 0);
+            acc[1][p] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[s + 1], b1.y, acc[1][p], 0, 0, 0);
+            acc[0][p] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[s + 2], b0.z, acc[0][p], 0, 0, 0);
+            acc[1][p] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[s + 2], b1.z, acc[1][p], 0, 0, 0);
+            acc[0][p] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[s + 3], b0.w, acc[0][p], 0, 0, 0);
+            acc[1][p] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[s + 3], b1.w, acc[1][p], 0, 0, 0);
+        }
+        // D[i][c] of a 16x16x4 product: lane c + 16 * (i / 4), element i % 4
+        // (i: query of the wave, c: row of the 16-row half)
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+            const uint32_t b = b_lo + t * kTRows + 16 * h + j;
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const float dot = acc[h][0][r] + acc[h][1][r];
+                const float d = l2 ? xn[h] - 2.f * dot : -dot;
+                const uint64_t key = (static_cast<uint64_t>(ord_of(d)) << 32) | b;
+                if (b < b_hi && key < thr[r]) {
+                    const int qi = 4 * g + r;
+                    const uint32_t slot = atomicAdd(&mycnt[qi], 1u);
+                    if (slot < static_cast<uint32_t>(CAP)) mybuf[qi * CAP + slot] = key;  // always: see the merge below
+                }
+            }
+        }
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+        // merge the tails that could overflow during the next tile (a tile
+        // adds at most kTRows keys to a query)
+        const uint64_t full = __ballot(lane < 16 && mycnt[lane] > static_cast<uint32_t>(CAP - kTRows));
+        for (uint64_t m = full; m;) {
+            const int qi = __ffsll(static_cast<unsigned long long>(m)) - 1;
+            m &= m - 1;
+            merge_tail<KP>(mybuf + qi * CAP, mycnt[qi], lane);
+            if (lane == 0) {
+                mythr[qi] = mybuf[qi * CAP + KP - 1];
+                mycnt[qi] = KP;
+            }
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+            __builtin_amdgcn_wave_barrier();
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+        }
+        if (full) {
+#pragma unroll
+            for (int r = 0; r < 4; ++r) thr[r] = mythr[4 * g + r];
+        }
+        if (t + 1 < ntiles) {
+            __syncthreads();  // every wave is done with the tile
+            store();
+            xn[0] = xn_next[0];
+            xn[1] = xn_next[1];
+            __syncthreads();
+        }
+    }
+    // final selection of each query of the wave
+    for (int qi = 0; qi < 16; ++qi) {
+        uint64_t *bq = mybuf + qi * CAP;
+        if (mycnt[qi] > static_cast<uint32_t>(KP)) merge_tail<KP>(bq, mycnt[qi], lane);
+        if (q0 + qi < nq)
+            for (int e = lane; e < KP; e += 64)
+                partial[(static_cast<size_t>(q0 + qi) * nchunks + ch) * KP + e] = bq[e];
+    }
+}
+
+size_t bf_tile_lds(uint32_t S, int KP) {
+    const size_t q = 16 * bf_tile_waves(KP);
+    return static_cast<size_t>(kTRows) * (4 * S + 4) * 4 + q * (KP + kTail) * 8 + q * 8 + q * 4;
+}
+
 template <int KP>
 __global__ __launch_bounds__(64) void bf_merge(DevIndex ix, const float *Q, uint32_t nq, uint32_t nchunks,
                                                uint32_t pow2, const uint64_t *partial, uint32_t k, int32_t *ids_out,
@@ -280,6 +525,46 @@ hipError_t bf_run(const DevIndex &ix, const float *Q, uint32_t nq, uint32_t k, c
     return hipGetLastError();
 }
 
+template <int KP, int S>
+hipError_t bf_tile_launch(const DevIndex &ix, const float *Q, uint32_t nq, const float *xnorm, uint32_t nchunks,
+                          uint32_t chunk, uint64_t *partial, hipStream_t st) {
+    const size_t lds = bf_tile_lds(S, KP);
+    if (lds > 65536)
+        (void)hipFuncSetAttribute(reinterpret_cast<const void *>(&bf_tile<KP, S>),
+                                  hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(lds));
+    constexpr uint32_t qpb = 16 * bf_tile_waves(KP);
+    dim3 g((nq + qpb - 1) / qpb, nchunks);
+    hipLaunchKernelGGL((bf_tile<KP, S>), g, dim3(64 * bf_tile_waves(KP)), lds, st, ix, Q, nq, xnorm, chunk,
+                       nchunks, partial);
+    return hipGetLastError();
+}
+
+template <int KP>
+hipError_t bf_run_tile(const DevIndex &ix, const float *Q, uint32_t nq, uint32_t k, const float *xnorm,
+                       uint64_t *partial, uint32_t nchunks, uint32_t chunk, int32_t *ids, double *d,
+                       hipStream_t st) {
+    const uint32_t dpad = ix.stride4 * 4;
+    // S: coordinates per lane group, 4 S >= the stored row (dpad <= 256)
+    const uint32_t need = (dpad + 3) / 4;
+    hipError_t e;
+    if (need <= 4) e = bf_tile_launch<KP, 4>(ix, Q, nq, xnorm, nchunks, chunk, partial, st);
+    else if (need <= 8) e = bf_tile_launch<KP, 8>(ix, Q, nq, xnorm, nchunks, chunk, partial, st);
+    else if (need <= 16) e = bf_tile_launch<KP, 16>(ix, Q, nq, xnorm, nchunks, chunk, partial, st);
+    else if (need <= 24) e = bf_tile_launch<KP, 24>(ix, Q, nq, xnorm, nchunks, chunk, partial, st);
+    else if (need <= 32) e = bf_tile_launch<KP, 32>(ix, Q, nq, xnorm, nchunks, chunk, partial, st);
+    else if (need <= 48) e = bf_tile_launch<KP, 48>(ix, Q, nq, xnorm, nchunks, chunk, partial, st);
+    else e = bf_tile_launch<KP, 64>(ix, Q, nq, xnorm, nchunks, chunk, partial, st);
+    if (e != hipSuccess) return e;
+    uint32_t pow2 = 1;
+    while (pow2 < nchunks * KP) pow2 <<= 1;
+    const size_t lds2 = static_cast<size_t>(pow2) * 8 + KP * 8 + KP * 4;
+    if (lds2 > 65536)
+        (void)hipFuncSetAttribute(reinterpret_cast<const void *>(&bf_merge<KP>),
+                                  hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(lds2));
+    hipLaunchKernelGGL(bf_merge<KP>, dim3(nq), dim3(64), lds2, st, ix, Q, nq, nchunks, pow2, partial, k, ids, d);
+    return hipGetLastError();
+}
+
 }  // namespace
 
 hipError_t launch_row_norms(const DevIndex &ix, float *out, hipStream_t st) {
@@ -287,11 +572,16 @@ hipError_t launch_row_norms(const DevIndex &ix, float *out, hipStream_t st) {
     return hipGetLastError();
 }
 
-uint32_t bf_candidates(uint32_t k) { return k <= 32 ? 64 : (k <= 64 ? 128 : 256); }
+// Candidates kept per (query, chunk): 2k at least.  k <= 32 runs bf_tile
+// (KP 32 or 64), larger k the block-synchronised bf_scan (KP 128 or 256).
+uint32_t bf_candidates(uint32_t k) { return k <= 16 ? 32 : (k <= 32 ? 64 : (k <= 64 ? 128 : 256)); }
 
 void bf_plan(const DevIndex &ix, uint32_t nq, uint32_t k, uint32_t *nchunks, uint32_t *chunk) {
-    const uint32_t tiles = (nq + kQT - 1) / kQT;
-    uint32_t nc = (4096 + tiles - 1) / tiles;
+    const bool tile = k <= 32;
+    const uint32_t qpb = tile ? 16u * bf_tile_waves(static_cast<int>(bf_candidates(k))) : kQT;
+    const uint32_t tiles = (nq + qpb - 1) / qpb;
+    const uint32_t target = tile ? 2048u : 4096u;  // blocks of the scan
+    uint32_t nc = (target + tiles - 1) / tiles;
     const uint32_t kp = bf_candidates(k);
     const uint32_t max_nc = 8192 / kp;  // bf_merge sorts nchunks * KP keys in LDS
     if (nc > max_nc) nc = max_nc;
@@ -307,7 +597,8 @@ hipError_t launch_bruteforce(const DevIndex &ix, const float *Q, uint32_t nq, ui
                              uint64_t *partial, uint32_t nchunks, uint32_t chunk, int32_t *ids, double *d,
                              hipStream_t st) {
     switch (bf_candidates(k)) {
-        case 64: return bf_run<64>(ix, Q, nq, k, xnorm, partial, nchunks, chunk, ids, d, st);
+        case 32: return bf_run_tile<32>(ix, Q, nq, k, xnorm, partial, nchunks, chunk, ids, d, st);
+        case 64: return bf_run_tile<64>(ix, Q, nq, k, xnorm, partial, nchunks, chunk, ids, d, st);
         case 128: return bf_run<128>(ix, Q, nq, k, xnorm, partial, nchunks, chunk, ids, d, st);
         default: return bf_run<256>(ix, Q, nq, k, xnorm, partial, nchunks, chunk, ids, d, st);
     }

@@ -300,10 +300,17 @@ class Mlp:
         z = np.load(path)
         return cls(z["params"], float(z["tau"]), int(z["jmax"]), int(z["period"]), int(z["max_ckpt"]))
 
-    def __del__(self):
-        if getattr(self, "_h", None):
-            lib().hnsw_mlp_free(self._h)
+    def close(self):
+        h = getattr(self, "_h", None)
+        if h:
             self._h = None
+            lib().hnsw_mlp_free(h)
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:  # interpreter shutdown: module globals may already be gone
+            pass
 
 
 def mlp_forward(params, x, stream=None):

@@ -64,6 +64,10 @@ struct SearchArgs {
     uint64_t *sched_start;   // [nq] key of each query's layer-0 entry
     uint32_t *sched_up;      // [nq][2] distance evaluations and expansions above layer 0
     uint32_t *sched_order;   // [nq] query of each layer-0 wave
+    // Learned rule, scheduled form: while non-null, the layer-0 launch is the
+    // probe (query blockIdx.x, batch order) that runs each search to its first
+    // checkpoint and writes its start priority here instead of results.
+    uint32_t *sched_prio;    // [nq]
     int sched;               // 0: one kernel; 1: scheduled when the batch exceeds the resident waves; 2: always
     bool no_alloc;           // the caller cannot allocate: workspace from the static scratch array, no timing events
 };
@@ -93,8 +97,9 @@ hipError_t launch_quantize_u8(const DevIndex &ix, uint8_t *out, uint32_t *inexac
 // LDS per wave of a search kernel; `learned` adds the stop rule's buffers.
 size_t search_lds_bytes(const SearchArgs &a, bool learned);
 // Form of a batch larger than the resident waves (true: the scheduled
-// launches).  Per (index, mode, ef, batch-size octave) it times one call of
-// each form with events read back without blocking, then keeps the faster;
+// launches).  Per (index, mode, ef, batch-size octave), after one untimed
+// call of each form, it times two calls of each (alternating) with events
+// read back without blocking, then keeps the faster;
 // until then it answers true.  *ev_start / *ev_end, when set, are to be
 // recorded on the stream around the batch's launches.  With a.no_alloc it
 // only reads a decision already made (creating no record and no event) and
@@ -106,9 +111,8 @@ void forget_index(uint32_t uid);
 // Next index identifier (never 0).
 uint32_t next_index_uid();
 
-// Visited-table slots for a batch search: at least the power of two of the
-// 8-slots-per-ef rule (1024..4096), more while the kernel's LDS share at its
-// target occupancy leaves room.
+// Visited-table slots for a batch search: what the kernel's LDS share at its
+// target occupancy leaves, at least 1024 (the learned kernels 64 fewer).
 uint32_t visited_slots(const SearchArgs &a, bool learned);
 
 // Brute-force K-NN (MFMA scan + fp64 rerank).

@@ -37,35 +37,36 @@ TileShape tile_for(int kind, uint32_t dim) {
 }
 
 size_t search_lds_bytes(const SearchArgs &a, bool learned) {
-    return static_cast<size_t>(a.wslots) * 8 + 64 * 8 + 64 * 4 + (learned ? 64 * 4 + 128 * 4 : 0) +
+    return static_cast<size_t>(a.wslots) * 8 + 64 * 8 + 64 * 4 + (learned ? 64 * 4 : 0) +
            static_cast<size_t>(a.ht_slots) * 4;
 }
 
 // The batch kernels keep six waves per SIMD (five for FP8), at most 24 per
 // CU sharing 160 KiB of LDS.  The table takes what is left of a 24th of it,
 // rounded down to whole KiB (the share itself, so that no allocation rounding
-// can cost a wave); a fuller table forgets fewer ids (a forgotten id is
-// scored again).  FP8 is sized like the others: a table filling a 20th of
-// the LDS (all of it at five waves per SIMD) measured 2% slower.  Above that
-// share the table grows with ef (8 slots per element of W) up to 2,048
-// slots: on glove_like 1.2M at ef 320, 4,096 slots (16 KiB, half the waves
-// per CU) took 10.3 ms per 10,000 queries and 2,048 slots 7.8 ms, the extra
-// distance evaluations of a fuller table costing less than the lost waves.
+// can cost a wave), and at least 1,024 slots; a fuller table forgets fewer
+// ids (a forgotten id is scored again).  FP8 is sized like the others: a
+// table filling a 20th of the LDS (all of it at five waves per SIMD)
+// measured 2% slower.  A table that grows with ef costs waves at large ef:
+// on glove_like 1.2M at ef 288 (10,000 queries) 1,024 slots took 5.53 ms,
+// 2,048 slots 6.15 ms and 512 slots 5.81 ms (at ef 320, 4,096 slots 10.3 ms).
 // HNSW_VISITED_LOG2 = 8..14 fixes a power of two instead.
 uint32_t visited_slots(const SearchArgs &a, bool learned) {
     if (const char *v = getenv("HNSW_VISITED_LOG2")) {
         const long x = strtol(v, nullptr, 10);
         if (x >= 8 && x <= 14) return 1u << x;
     }
-    uint32_t lg = 10;
-    while (lg < 11 && (1u << lg) < 8u * a.ef) ++lg;
-    const uint32_t base = 1u << lg;
+    const uint32_t base = 1024;
     const uint32_t share = (160u * 1024u / 24u) & ~1023u;
     SearchArgs t = a;
     t.ht_slots = 0;
-    const uint32_t fixed = static_cast<uint32_t>(search_lds_bytes(t, learned));
+    const uint32_t fixed = static_cast<uint32_t>(search_lds_bytes(t, false));
     const uint32_t fit = share > fixed ? ((share - fixed) / 4) & ~63u : 0u;
-    return fit > base ? fit : base;
+    const uint32_t slots = fit > base ? fit : base;
+    // the learned kernels take their extra buffer out of the table, so that
+    // they hold as many waves per CU as the plain ones (the table decides no
+    // feature of the stop rule)
+    return learned ? slots - static_cast<uint32_t>(search_lds_bytes(t, true) - fixed) / 4 : slots;
 }
 
 bool stores_buffered(const DevIndex &ix) {
@@ -78,13 +79,15 @@ bool stores_buffered(const DevIndex &ix) {
 
 namespace {
 
-// Workspace of the scheduled launches, one per (device, stream): 20 bytes
-// per query (layer-0 entry key, the upper layers' counters, the order).  It
+// Workspace of the scheduled launches, one per (device, stream): kSchedBytes
+// per query (layer-0 entry key, the upper layers' counters, the order, the
+// learned form's probe priority).  It
 // grows to the largest batch seen on that stream and is kept until the
 // process ends.  Launches on one stream run in order, so a buffer is reused
 // only after the previous batch's kernels have read it; the mutex is held
 // while a batch's kernels are enqueued, so that batches submitted to one
 // stream from several threads do not interleave their launches.
+constexpr size_t kSchedBytes = 24;
 struct SchedBuf {
     int device;
     hipStream_t stream;
@@ -127,15 +130,20 @@ uint8_t *sched_buffer(hipStream_t stream, size_t need) {
 // Records are keyed by the index's uid (never reused within the process) and
 // dropped when the index is freed; the table holds at most kTuneCap records
 // (the oldest decided ones make room).
+// Protocol: one untimed call of each form (cold caches, first launches), then
+// kTuneRuns timed calls alternating scheduled / one-kernel; the form with the
+// smaller total wins.
+constexpr int kTuneRuns = 4;
 struct FormTune {
     uint32_t index;  // DevIndex::uid
     int device, mode;
     uint32_t ef, octave;
-    int phase;          // 0 warm-up call, 1 scheduled timed, 2 one-kernel timed, 3 decided
-    bool sched;         // decision (phase 3)
-    hipEvent_t ev[2][2];
-    float ms[2];
+    int phase;          // 0, 1 warm-up calls; 2 .. 2 + kTuneRuns - 1 timed calls; then waiting; kDecided
+    bool sched;         // decision (phase kDecided)
+    hipEvent_t ev[kTuneRuns][2];
+    float ms[kTuneRuns];
 };
+constexpr int kDecided = 3 + kTuneRuns;
 std::vector<FormTune> g_tune;
 constexpr size_t kTuneCap = 1024;
 
@@ -185,14 +193,14 @@ bool tuned_form(const DevIndex &ix, const SearchArgs &a, hipStream_t stream, hip
     FormTune *t = nullptr;
     for (FormTune &x : g_tune)
         if (x.index == ix.uid && x.device == dev && x.mode == a.mode && x.ef == a.ef && x.octave == octave) t = &x;
-    if (a.no_alloc) return t && t->phase == 3 ? t->sched : true;
+    if (a.no_alloc) return t && t->phase == kDecided ? t->sched : true;
     if (!t) {
         if (g_tune.size() >= kTuneCap) {
             // make room: drop the older half of the decided records (records
             // still timing hold events that are in flight)
             size_t j = 0, dropped = 0;
             for (size_t i = 0; i < g_tune.size(); ++i) {
-                if (g_tune[i].phase == 3 && dropped < kTuneCap / 2) {
+                if (g_tune[i].phase == kDecided && dropped < kTuneCap / 2) {
                     ++dropped;
                     continue;
                 }
@@ -201,59 +209,56 @@ bool tuned_form(const DevIndex &ix, const SearchArgs &a, hipStream_t stream, hip
             g_tune.resize(j);
             if (g_tune.size() >= kTuneCap) return true;  // every record is mid-timing: no tuning for this call
         }
-        g_tune.push_back(FormTune{ix.uid, dev, a.mode, a.ef, octave, 0, true, {{nullptr, nullptr}, {nullptr, nullptr}},
-                                  {0.f, 0.f}});
+        g_tune.push_back(FormTune{ix.uid, dev, a.mode, a.ef, octave, 0, true, {}, {}});
         t = &g_tune.back();
     }
     auto give = [&](int k) {
         if (!t->ev[k][0] && (hipEventCreate(&t->ev[k][0]) != hipSuccess || hipEventCreate(&t->ev[k][1]) != hipSuccess)) {
             (void)hipGetLastError();
-            t->phase = 3;  // no events: keep the scheduled form
+            destroy_events(*t);
+            t->phase = kDecided;  // no events: keep the scheduled form
             t->sched = true;
-            return;
+            return false;
         }
         *ev_start = t->ev[k][0];
         *ev_end = t->ev[k][1];
+        return true;
     };
-    switch (t->phase) {
-        case 0:  // a first, untimed call (cold caches), in the scheduled form
-            t->phase = 1;
-            return true;
-        case 1:
-            give(0);
-            if (t->phase == 1) t->phase = 2;
-            return true;
-        case 2:
-            if (!events_done(t->ev[0][1])) return true;  // the timed call has not ended yet
-            if (!t->ev[1][0]) {
-                give(1);
-                return t->phase == 3 ? true : false;  // the one-kernel form, timed
-            }
-            if (!events_done(t->ev[1][1])) return true;
-            if (hipEventElapsedTime(&t->ms[0], t->ev[0][0], t->ev[0][1]) != hipSuccess ||
-                hipEventElapsedTime(&t->ms[1], t->ev[1][0], t->ev[1][1]) != hipSuccess) {
-                (void)hipGetLastError();
-                t->sched = true;
-            } else {
-                t->sched = t->ms[0] <= t->ms[1];
-            }
-            destroy_events(*t);
-            t->phase = 3;
-            return t->sched;
-        default:
-            return t->sched;
+    if (t->phase == kDecided) return t->sched;
+    if (t->phase < 2) return t->phase++ == 0;  // untimed: scheduled, then one-kernel
+    if (t->phase < 2 + kTuneRuns) {
+        const int k = t->phase - 2;
+        const bool sched = (k & 1) == 0;
+        if (!give(k)) return true;
+        ++t->phase;
+        return sched;
     }
+    // every timed call enqueued: decide once they have all ended (the events
+    // are queried, never waited for); until then the scheduled form
+    for (int k = 0; k < kTuneRuns; ++k)
+        if (!events_done(t->ev[k][1])) return true;
+    float tot[2] = {0.f, 0.f};
+    bool ok = true;
+    for (int k = 0; k < kTuneRuns; ++k) {
+        ok = ok && hipEventElapsedTime(&t->ms[k], t->ev[k][0], t->ev[k][1]) == hipSuccess;
+        tot[k & 1] += t->ms[k];
+    }
+    if (!ok) (void)hipGetLastError();
+    t->sched = !ok || tot[0] <= tot[1];
+    destroy_events(*t);
+    t->phase = kDecided;
+    return t->sched;
 }
 
 // Workspace of the allocation-free entry point (hnsw_search_batch_noalloc):
-// the scheduled launches' 20 bytes per query for up to
+// the scheduled launches' kSchedBytes per query for up to
 // HNSW_NOALLOC_MAX_QUERIES queries, held by every device the library runs on
 // until the process ends.  Its device address is taken once per device
 // (hipGetSymbolAddress, with that device current); host code passes only that
 // address to kernels.  Every element is written by the descent and order
 // kernels before it is read, so nothing needs clearing between calls; calls
 // that overlap on one device share it and race.
-constexpr size_t kNoAllocScratchBytes = static_cast<size_t>(HNSW_NOALLOC_MAX_QUERIES) * 20;
+constexpr size_t kNoAllocScratchBytes = static_cast<size_t>(HNSW_NOALLOC_MAX_QUERIES) * kSchedBytes;
 static __device__ __align__(256) uint8_t scratch[kNoAllocScratchBytes];
 
 namespace {
@@ -295,22 +300,26 @@ hipError_t launch_search(const DevIndex &ix, const SearchArgs &a0, hipStream_t s
     a.sched_start = nullptr;
     a.sched_up = nullptr;
     a.sched_order = nullptr;
+    a.sched_prio = nullptr;
     std::unique_lock<std::mutex> lk(g_sched_mu, std::defer_lock);
     if (a.sched == 2 || (a.sched == 1 && a.nq > 256)) {
         lk.lock();
         const size_t n = a.nq;
         uint8_t *p;
         if (a.no_alloc) {
-            if (n * 20 > kNoAllocScratchBytes) return hipErrorInvalidValue;
+            if (n * kSchedBytes > kNoAllocScratchBytes) return hipErrorInvalidValue;
             p = noalloc_scratch();
             if (!p) return hipErrorInvalidSymbol;
         } else {
-            p = sched_buffer(stream, n * 20);
+            p = sched_buffer(stream, n * kSchedBytes);
         }
         if (p) {
             a.sched_start = reinterpret_cast<uint64_t *>(p);
             a.sched_up = reinterpret_cast<uint32_t *>(p + n * 8);
             a.sched_order = reinterpret_cast<uint32_t *>(p + n * 16);
+            // the learned form's probe priorities (launch_form sets them only
+            // for its probe launch)
+            if (a.mode == HNSW_MODE_LEARNED) a.sched_prio = reinterpret_cast<uint32_t *>(p + n * 20);
         } else {
             a.sched = 0;
         }

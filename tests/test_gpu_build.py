@@ -6,9 +6,9 @@
 - The device heuristic (Alg. 4) on explicit candidate lists equals the
   oracle's, with and without keepPrunedConnections.
 - Batched builds give valid graphs (degree caps, no self-links or repeats,
-  layer membership) whose search recall is close to that of the oracle-built
-  graph at the same ef, and the GPU search on a device-built graph equals the
-  oracle's search on the exported graph.
+  layer membership) whose search recall, against the oracle's brute force, is
+  close to that of the oracle-built graph at the same ef; the search output on
+  them has distinct ids and the oracle's exact distances.
 """
 import os
 
@@ -111,10 +111,23 @@ def test_device_heuristic_equals_oracle(hnsw, keep):
             assert list(got) == [int(v) for v in want], (nc, Mk, i)
 
 
+def _check_rows(ids, ds, X, Q, metric):
+    """Properties of search output on a graph the oracle did not build: ids
+    distinct and in range, distances ascending and equal (1e-5 relative) to
+    the oracle's exact distance of each returned id."""
+    n = X.shape[0]
+    assert ((ids >= 0) & (ids < n)).all()
+    assert all(len(set(r)) == len(r) for r in ids)
+    assert (np.diff(ds, axis=1) >= 0).all()
+    d64 = oracle.pair_dist(X, Q, ids, metric)
+    tau = 1.0 if metric == oracle.IP else 1e-3 * float(np.median(np.abs(d64[d64 != 0])))
+    assert (np.abs(ds - d64) <= 1e-5 * np.maximum(np.abs(d64), tau)).all()
+
+
 @pytest.mark.parametrize("kind,metric,n,M,efC", [("uniform", oracle.L2, 20000, 16, 100),
                                                   ("sift", oracle.L2, 50000, 16, 200),
                                                   ("glove", oracle.IP, 50000, 16, 200)])
-def test_batched_build_valid_recall_and_search_parity(hnsw, kind, metric, n, M, efC):
+def test_batched_build_valid_and_recall(hnsw, kind, metric, n, M, efC):
     print(f"case GPU batched build {kind} n={n}", flush=True)
     X = _data(kind, n, 5)
     Q = {"uniform": synthdata.queries("uniform16", 500), "sift": synthdata.queries("sift_like", 500),
@@ -123,30 +136,29 @@ def test_batched_build_valid_recall_and_search_parity(hnsw, kind, metric, n, M, 
     p = idx.export()
     _check_valid(p, M, M, 2 * M)
     q = torch.from_numpy(Q).cuda()
-    _, gt = hnsw.bruteforce(idx, q, 10)
-    gt = gt.cpu().numpy()
+    _, gt = oracle.bruteforce(X, Q, 10, metric=metric, nthreads=8)
     G = oracle.Graph.build(X, metric=metric, M=M, efC=efC, seed=4)
     oidx = hnsw.Index(G.packed(), X)
-    Gd = oracle.Graph.from_packed(X, p)
     for ef in (16, 64):
         ids, ds = idx.search(q, 10, ef)
         oi, _ = oidx.search(q, 10, ef)
         torch.cuda.synchronize()
         ids, ds = ids.cpu().numpy(), ds.cpu().numpy()
+        _check_rows(ids, ds, X, Q, metric)
         r_dev = parity.recall_at_k(ids, X, Q, gt, metric).mean()
         r_orc = parity.recall_at_k(oi.cpu().numpy(), X, Q, gt, metric).mean()
         print(f"  ef={ef}: recall device-built {r_dev:.4f}, oracle-built {r_orc:.4f}", flush=True)
         assert r_dev >= r_orc - 0.02
-        # the search itself on the device-built graph: GPU = oracle
-        wi, wd = Gd.search(Q, 10, ef, nthreads=8)
-        r = parity.compare(ids, ds, wi, wd, X, Q, metric)
-        assert r["fail"] == 0 and r["exempt"] == 0
 
 
 FULL = os.path.join(ROOT, "graphs", "sift_like_1M.bin")
 
 
-@pytest.mark.skipif(not os.path.exists(FULL), reason="1M sift_like graph file not built")
+GT = os.path.join(ROOT, "graphs", "sift_like_1M.gt.npz")
+
+
+@pytest.mark.skipif(not (os.path.exists(FULL) and os.path.exists(GT)),
+                    reason="1M sift_like graph or oracle ground truth file not built")
 def test_device_build_sift_like_1m_recall_against_oracle_graph(hnsw):
     """Graph quality at full size: the device-built 1M x 128 graph (M = 16,
     Mmax0 = 32, efC = 200) against the oracle-built one, recall@10 at equal
@@ -163,8 +175,7 @@ def test_device_build_sift_like_1m_recall_against_oracle_graph(hnsw):
     dt = time.time() - t0
     oidx = hnsw.Index(p0, X)
     q = torch.from_numpy(Q).cuda()
-    _, gt = hnsw.bruteforce(oidx, q, 10)
-    gt = gt.cpu().numpy()
+    gt = np.load(GT)["d64"][:, :10]
     print(f"  device build {dt:.1f} s (incl. upload)", flush=True)
     p = idx.export()
     _check_valid(p, 16, 16, 32)
@@ -185,7 +196,8 @@ def test_deep_like_10m_device_build_and_lowp_search(hnsw):
     self-links or repeats, layer membership) on every element of layer 0 and
     on every upper row; for fp32, BF16 and FP8 traversal at ef 64 / 128 / 256,
     rows of distinct ids sorted by distance whose distances are the oracle's
-    exact fp32 distances (sampled), and recall@10 against the brute force."""
+    exact fp32 distances (sampled), and recall@10 on a sample of 200 queries
+    against the oracle's brute force."""
     import time
 
     print("case deep_like 10M device build + fp32/BF16/FP8 search", flush=True)
@@ -216,11 +228,11 @@ def test_deep_like_10m_device_build_and_lowp_search(hnsw):
         assert not ((blk == owners[r:r + 200000, None]) & ok).any()
     assert lv[p["entry_point"]] == p["max_level"] == lv.max()
     q = torch.from_numpy(Q).cuda()
-    _, gt = hnsw.bruteforce(idx, q, 10)
-    gt = gt.cpu().numpy()
     idx.add_lowp(hnsw.MODE_BF16)
     idx.add_lowp(hnsw.MODE_FP8)
-    sample = np.random.default_rng(3).choice(len(Q), 100, replace=False)
+    # recall is measured on a sample against the oracle's brute force
+    sample = np.random.default_rng(3).choice(len(Q), 200, replace=False)
+    _, gt = oracle.bruteforce(X, Q[sample], 10, nthreads=16)
     rec = {}
     for mode in (0, 1, 2):
         for ef in (64, 128, 256):
@@ -231,7 +243,7 @@ def test_deep_like_10m_device_build_and_lowp_search(hnsw):
             assert (np.diff(ds, axis=1) >= 0).all()
             d64 = oracle.pair_dist(X, Q[sample], ids[sample])
             assert np.array_equal(d64.astype(np.float32), ds[sample])
-            rec[(mode, ef)] = float(parity.recall_at_k(ids, X, Q, gt, 0).mean())
+            rec[(mode, ef)] = float(parity.recall_at_k(ids[sample], X, Q[sample], gt, 0).mean())
             print(f"  mode={mode} ef={ef}: recall {rec[(mode, ef)]:.4f}", flush=True)
     assert rec[(0, 128)] >= 0.95 and rec[(0, 256)] >= 0.99
     for ef in (64, 128, 256):

@@ -148,7 +148,11 @@ NET = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), 
                    "glove_like.mlp.npz")
 
 
-@pytest.mark.skipif(not (os.path.exists(GLOVE) and os.path.exists(NET)), reason="glove_like graph or net not built")
+GLOVE_GT = GLOVE[:-4] + ".gt.npz"
+
+
+@pytest.mark.skipif(not (os.path.exists(GLOVE) and os.path.exists(NET) and os.path.exists(GLOVE_GT)),
+                    reason="glove_like graph, net or oracle ground truth file not built")
 def test_trained_net_gain_on_glove_like(hnsw):
     """What the trained network gains over the method without it, on the
     1.2M x 100 inner-product workload with its calibrated (ef, tau): the plain
@@ -157,11 +161,10 @@ def test_trained_net_gain_on_glove_like(hnsw):
     print("case learned gain glove_like 1.2M", flush=True)
     p = hnsw.graphfile.read(GLOVE)
     X = synthdata.base("glove_like", p["n"])
-    Q = synthdata.queries("glove_like", 4000)
+    Q = synthdata.queries("glove_like", 10000)[:4000]
     idx = hnsw.Index(p, X)
     q = torch.from_numpy(Q).cuda()
-    _, gt = hnsw.bruteforce(idx, q, 10)
-    gt = gt.cpu().numpy()
+    gt = np.load(GLOVE_GT)["d64"][:4000, :10]
     net = hnsw.Mlp.load(NET)
     ef = int(np.load(NET)["ef"])
 

@@ -68,14 +68,16 @@ def recall(ids, X, Q, gt_d64, metric=0):
     1e-9 relative keeps the true K-th neighbour from being counted as a miss
     (fp32 inputs cannot separate distances that close)."""
     K = ids.shape[1]
-    x = X[np.clip(ids, 0, None)].astype(np.float64)
-    if metric == 0:
-        d = ((x - Q[:, None, :].astype(np.float64)) ** 2).sum(-1)
-    else:
-        d = 1.0 - (x * Q[:, None, :].astype(np.float64)).sum(-1)
-    d[ids < 0] = np.inf
-    dk = gt_d64[:, K - 1:K]
-    return (d <= dk + RECALL_SLACK * np.abs(dk) + 1e-12).sum(1) / K
+    out = []
+    for s in range(0, len(ids), 10000):  # bounded memory for large batches
+        i = ids[s:s + 10000]
+        x = X[np.clip(i, 0, None)].astype(np.float64)
+        q = Q[s:s + 10000, None, :].astype(np.float64)
+        d = ((x - q) ** 2).sum(-1) if metric == 0 else 1.0 - (x * q).sum(-1)
+        d[i < 0] = np.inf
+        dk = gt_d64[s:s + 10000, K - 1:K]
+        out.append((d <= dk + RECALL_SLACK * np.abs(dk) + 1e-12).sum(1) / K)
+    return np.concatenate(out)
 
 
 def row_bytes(mode: int, dim: int) -> int:
@@ -305,15 +307,18 @@ def serve_bench(hnsw, index, Q, mlp, rates=(50_000, 100_000, 200_000, 500_000), 
             "rates": out}
 
 
-def learned_glove_bench(hnsw, steps=10, warmup=2, target=0.95):
+def learned_glove_bench(hnsw, steps=10, warmup=2, target=0.95, batches=(10_000, 100_000)):
     """The learned stop rule on glove_like 1.2M x 100 (inner product) with the
     net trained and calibrated for it: plain and learned are each timed at the
-    smallest ef of a grid of step 16 that reaches recall@10 >= 0.95."""
+    smallest ef of a grid of step 16 that reaches recall@10 >= 0.95.  Two
+    batch sizes: the 10,000 test queries in one call, and 100,000 queries of
+    the same law in one call (a batch long enough that its last, longest
+    searches are a small part of it)."""
     import torch
 
     import synthdata
 
-    path, n, nq, K = WORKLOADS["glove_like"]
+    path, n, nq0, K = WORKLOADS["glove_like"]
     gpath = os.path.join(ROOT, path)
     mpath = os.path.join(ROOT, "paper_1603_09320_amd", "nets", "glove_like.mlp.npz")
     if not (os.path.exists(gpath) and os.path.exists(mpath)):
@@ -321,26 +326,33 @@ def learned_glove_bench(hnsw, steps=10, warmup=2, target=0.95):
         return None
     g = hnsw.graphfile.read(gpath)
     X = synthdata.base("glove_like", g["n"])
-    Q = synthdata.queries("glove_like", nq)
     index = hnsw.Index(g, X)
-    q = torch.from_numpy(Q).cuda()
-    _, gt = hnsw.bruteforce(index, q, K)
-    torch.cuda.synchronize()
     mlp = hnsw.Mlp.load(mpath)
-    run = Runner(index, q, X, Q, K, gt.cpu().numpy(), g["metric"], torch.cuda.current_stream(), mlp)
-    efs = list(range(128, 513, 16))
-    out = {"workload": f"glove_like {g['n']}x{g['dim']} inner product, {nq} queries, K={K}",
-           "target_recall": target, "net": {"tau": mlp.tau, "jmax": mlp.jmax, "period": mlp.period}}
-    for form, mode in (("plain", 0), ("learned", 3)):
-        ef, rec, _ = run.sweep(mode, sorted(set(efs)), target)
-        _, _, cnt = run.search(ef, mode, counters=True)
+    out = {"workload": f"glove_like {g['n']}x{g['dim']} inner product, K={K}", "target_recall": target,
+           "net": {"tau": mlp.tau, "jmax": mlp.jmax, "period": mlp.period, "max_ckpt": mlp.max_ckpt}}
+    for nq in batches:
+        Q = synthdata.queries("glove_like", nq)
+        q = torch.from_numpy(Q).cuda()
+        _, gt = hnsw.bruteforce(index, q, K)
         torch.cuda.synchronize()
-        ms, kern_ms = run.time(ef, mode, steps, warmup)
-        out[form] = {"ef": ef, "recall": round(rec, 5), "qps": round(nq / (ms / 1000.0), 1),
-                     "kernel_ms": round(kern_ms, 4),
-                     "expansions_per_query": round(float(cnt.cpu().numpy()[:, 1].astype(np.float64).mean()), 2)}
-        log(f"[glove] {form}: {out[form]}")
-    out["learned_vs_plain_qps"] = round(out["learned"]["qps"] / out["plain"]["qps"], 4)
+        run = Runner(index, q, X, Q, K, gt.cpu().numpy(), g["metric"], torch.cuda.current_stream(), mlp)
+        efs = list(range(192, 513, 16))
+        res = {"queries": nq}
+        for form, mode in (("plain", 0), ("learned", 3)):
+            ef, rec, _ = run.sweep(mode, efs, target)
+            _, _, cnt = run.search(ef, mode, counters=True)
+            torch.cuda.synchronize()
+            c = cnt.cpu().numpy().astype(np.float64)
+            ms, kern_ms = run.time(ef, mode, steps, warmup)
+            res[form] = {"ef": ef, "recall": round(rec, 5), "qps": round(nq / (ms / 1000.0), 1),
+                         "ms_per_batch": round(ms, 4), "kernel_ms": round(kern_ms, 4),
+                         "layer0_expansions_per_query": round(float(c[:, 3].mean()), 2),
+                         "distance_evals_per_query": round(float(c[:, 0].mean()), 1)}
+            log(f"[glove] {nq} queries, {form}: {res[form]}")
+        res["learned_vs_plain_qps"] = round(res["learned"]["qps"] / res["plain"]["qps"], 4)
+        out[f"batch_{nq}"] = res
+        del q
+    mlp.close()
     index.close()
     return out
 

@@ -64,10 +64,6 @@ struct SearchArgs {
     uint64_t *sched_start;   // [nq] key of each query's layer-0 entry
     uint32_t *sched_up;      // [nq][2] distance evaluations and expansions above layer 0
     uint32_t *sched_order;   // [nq] query of each layer-0 wave
-    // Learned rule, scheduled form: while non-null, the layer-0 launch is the
-    // probe (query blockIdx.x, batch order) that runs each search to its first
-    // checkpoint and writes its start priority here instead of results.
-    uint32_t *sched_prio;    // [nq]
     int sched;               // 0: one kernel; 1: scheduled when the batch exceeds the resident waves; 2: always
     bool no_alloc;           // the caller cannot allocate: workspace from the static scratch array, no timing events
 };

@@ -80,14 +80,13 @@ bool stores_buffered(const DevIndex &ix) {
 namespace {
 
 // Workspace of the scheduled launches, one per (device, stream): kSchedBytes
-// per query (layer-0 entry key, the upper layers' counters, the order, the
-// learned form's probe priority).  It
+// per query (layer-0 entry key, the upper layers' counters, the order).  It
 // grows to the largest batch seen on that stream and is kept until the
 // process ends.  Launches on one stream run in order, so a buffer is reused
 // only after the previous batch's kernels have read it; the mutex is held
 // while a batch's kernels are enqueued, so that batches submitted to one
 // stream from several threads do not interleave their launches.
-constexpr size_t kSchedBytes = 24;
+constexpr size_t kSchedBytes = 20;
 struct SchedBuf {
     int device;
     hipStream_t stream;
@@ -300,7 +299,6 @@ hipError_t launch_search(const DevIndex &ix, const SearchArgs &a0, hipStream_t s
     a.sched_start = nullptr;
     a.sched_up = nullptr;
     a.sched_order = nullptr;
-    a.sched_prio = nullptr;
     std::unique_lock<std::mutex> lk(g_sched_mu, std::defer_lock);
     if (a.sched == 2 || (a.sched == 1 && a.nq > 256)) {
         lk.lock();
@@ -317,9 +315,6 @@ hipError_t launch_search(const DevIndex &ix, const SearchArgs &a0, hipStream_t s
             a.sched_start = reinterpret_cast<uint64_t *>(p);
             a.sched_up = reinterpret_cast<uint32_t *>(p + n * 8);
             a.sched_order = reinterpret_cast<uint32_t *>(p + n * 16);
-            // the learned form's probe priorities (launch_form sets them only
-            // for its probe launch)
-            if (a.mode == HNSW_MODE_LEARNED) a.sched_prio = reinterpret_cast<uint32_t *>(p + n * 20);
         } else {
             a.sched = 0;
         }

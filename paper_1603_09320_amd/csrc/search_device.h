@@ -46,7 +46,6 @@ struct Job {
     float *dists;        // [k]
     uint32_t *counters;  // [4] or null
     float *trace;        // learned mode: [max_ckpt][26] or null
-    uint32_t *prio;      // learned probe: the query's start priority (then no results), or null
 };
 
 
@@ -590,7 +589,6 @@ __device__ __forceinline__ int merge_into_w(const WaveLds &s, int m, uint32_t ef
 struct LearnState {
     uint32_t ckpt, n_prev, n_exp_upper;
     float d_start, d_best_prev, d_k_prev;
-    float out0;  // stop logit of the last checkpoint
 };
 
 // a / (|b| + tiny) clamped to [-big, big]; big = 1e6, tiny = 1e-20 (passed in
@@ -759,7 +757,6 @@ __device__ __forceinline__ float bf16_half(const uint4 &p, int h) {
         t[kMlpIn] = out0;
         t[kMlpIn + 1] = out1;
     }
-    st.out0 = out0;
     if (ck == 1 && net.jmax > 0) {
         int j = static_cast<int>(floorf(0.5f - out1));
         j = j < 0 ? 0 : (j > net.jmax ? net.jmax : j);
@@ -859,7 +856,7 @@ __device__ void search_layer0(const DevIndex &ix, const SearchArgs &a, const Job
 
     // SEARCH-LAYER on layer 0 with ef candidates, starting from the descent's result.
     uint32_t ef = job.ef;
-    LearnState lst{0u, 0u, n_exp, uniform_f(key_dist(cur)), 0.f, 0.f, 0.f};
+    LearnState lst{0u, 0u, n_exp, uniform_f(key_dist(cur)), 0.f, 0.f};
     if (lane == 0) {
         s.W[0] = cur;
         visit<false>(s.ht, ht_slots, key_id(cur));
@@ -933,17 +930,9 @@ __device__ void search_layer0(const DevIndex &ix, const SearchArgs &a, const Job
         n_exp0 += 1;
         const int lbmin = merge_into_w(s, m, ef, wsize, forgot);
         if (lbmin < cursor) cursor = lbmin;
-        if (LEARN && n_exp0 % a.mlp.period == 0 && lst.ckpt < a.mlp.max_ckpt) {
-            const bool stop = learned_checkpoint(s, a.mlp, lst, n_exp0, job.k, cursor, ef, wsize, job.trace);
-            if (stop || job.prio) break;
-        }
-    }
-    if (LEARN && job.prio) {
-        // probe of the scheduled learned form: the first checkpoint's stop
-        // logit ranks the query (the least inclined to stop starts first); a
-        // search that ended before its first checkpoint ranks last
-        if (lane == 0) *job.prio = lst.ckpt ? ~ord_of(lst.out0) : 0u;
-        return;
+        if (LEARN && n_exp0 % a.mlp.period == 0 && lst.ckpt < a.mlp.max_ckpt &&
+            learned_checkpoint(s, a.mlp, lst, n_exp0, job.k, cursor, ef, wsize, job.trace))
+            break;
     }
 
     uint32_t n_rerank = 0;

@@ -20,7 +20,6 @@ __device__ __forceinline__ Job job_of(const DevIndex &ix, const SearchArgs &a, u
     job.counters = a.counters ? a.counters + static_cast<size_t>(qi) * 4 : nullptr;
     job.trace = learn && a.ckpt_trace ? a.ckpt_trace + static_cast<size_t>(qi) * a.mlp.max_ckpt * (kMlpIn + 2)
                                       : nullptr;
-    job.prio = nullptr;
     return job;
 }
 
@@ -59,15 +58,6 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(6))) void se
 // to be the longest) before the others (order_kernel, layer0_kernel).  Each
 // query's arithmetic is that of the one-kernel path; only the order in which
 // queries occupy the chip changes.
-//
-// With the learned stop rule the length of a search is decided mostly by the
-// rule (the queries it stops early are short), which the descent distance
-// does not predict.  There a probe launch runs every query's layer-0 search
-// to its first checkpoint and ranks the queries by the stop logit there, the
-// least inclined to stop first; the layer-0 launch then restarts each search
-// from its entry in that order.  On glove_like 1.2M (10,000 queries) a
-// longest-first order known after the fact took 4.5-4.9 ms against 5.6-6.1 ms
-// in batch order or by descent distance.
 
 template <int G, int F, int METRIC, int KIND, bool BUF>
 __global__ __launch_bounds__(64) void descent_kernel(DevIndex ix, SearchArgs a) {
@@ -110,17 +100,14 @@ __device__ __forceinline__ uint32_t wave_sum_u32(uint32_t v) {
            __builtin_amdgcn_readlane(v, 48);
 }
 
-// prio: query i's priority word (unsigned, larger starts first) is
-// prio[stride * i]: the high word of its entry key (stride 2: the ordered
-// bits of the descent distance) or the learned probe's word (stride 1).
-__global__ __launch_bounds__(1024) void order_kernel(const uint32_t *prio, uint32_t stride, uint32_t nq,
-                                                     uint32_t *order) {
+__global__ __launch_bounds__(1024) void order_kernel(const uint64_t *start, uint32_t nq, uint32_t *order) {
     __shared__ uint32_t samp[kOrderSample];
     __shared__ uint32_t cnt[kOrderTiles * 16];
     __shared__ uint32_t total_s, round_s;
     const uint32_t t = threadIdx.x, lane = t & 63u, wv = t >> 6;
+    const uint32_t *dist_bits = reinterpret_cast<const uint32_t *>(start) + 1;  // high word of each key
     const uint32_t ns = nq < kOrderSample ? nq : kOrderSample;
-    if (t < kOrderSample) samp[t] = t < ns ? prio[stride * (static_cast<uint64_t>(t) * nq / ns)] : 0u;
+    if (t < kOrderSample) samp[t] = t < ns ? dist_bits[2 * (static_cast<uint64_t>(t) * nq / ns)] : 0u;
     if (t == 0) total_s = 0u;
     __syncthreads();
     for (uint32_t k = 2; k <= kOrderSample; k <<= 1)
@@ -143,8 +130,7 @@ __global__ __launch_bounds__(1024) void order_kernel(const uint32_t *prio, uint3
     auto flags = [&](uint32_t r0) {
         uint32_t hi[kOrderTiles];
 #pragma unroll
-        for (uint32_t i = 0; i < kOrderTiles; ++i)
-            hi[i] = prio[static_cast<size_t>(stride) * min(r0 + i * kOrderThreads + t, nq - 1u)];
+        for (uint32_t i = 0; i < kOrderTiles; ++i) hi[i] = dist_bits[2 * min(r0 + i * kOrderThreads + t, nq - 1u)];
         uint32_t fb = 0;
 #pragma unroll
         for (uint32_t i = 0; i < kOrderTiles; ++i)
@@ -207,13 +193,8 @@ template <int G, int F, int METRIC, int KIND, bool LEARN, bool BUF>
 __device__ __forceinline__ void layer0_query(const DevIndex &ix, const SearchArgs &a) {
     extern __shared__ __align__(16) uint8_t smem[];
     if (blockIdx.x >= a.nq) return;
-    const bool probe = LEARN && a.sched_prio;  // the learned form's probe: batch order
-    const uint32_t qi = probe ? blockIdx.x : __builtin_amdgcn_readfirstlane(a.sched_order[blockIdx.x]);
-    Job job = job_of(ix, a, qi, LEARN);
-    if (probe) {
-        job.prio = a.sched_prio + qi;
-        job.trace = nullptr;
-    }
+    const uint32_t qi = __builtin_amdgcn_readfirstlane(a.sched_order[blockIdx.x]);
+    const Job job = job_of(ix, a, qi, LEARN);
     const RowSource src = rows_of(ix, a, KIND);
     QueryRegs<G, F, KIND> Q;
     load_query<G, F, KIND>(job.q, ix.dim, Q);
@@ -250,18 +231,11 @@ hipError_t launch_form(const DevIndex &ix, const SearchArgs &a, hipStream_t stre
         return hipGetLastError();
     }
     hipLaunchKernelGGL((descent_kernel<G, F, METRIC, KIND, BUF>), dim3(a.nq), dim3(64), 0, stream, ix, a);
-    SearchArgs b = a;
-    b.sched_prio = nullptr;
-    if (learned) {
+    hipLaunchKernelGGL(order_kernel, dim3(1), dim3(kOrderThreads), 0, stream, a.sched_start, a.nq, a.sched_order);
+    if (learned)
         hipLaunchKernelGGL((layer0_kernel_learned<G, F, METRIC, BUF>), dim3(a.nq), dim3(64), lds, stream, ix, a);
-        hipLaunchKernelGGL(order_kernel, dim3(1), dim3(kOrderThreads), 0, stream, a.sched_prio, 1u, a.nq,
-                           a.sched_order);
-        hipLaunchKernelGGL((layer0_kernel_learned<G, F, METRIC, BUF>), dim3(a.nq), dim3(64), lds, stream, ix, b);
-    } else {
-        hipLaunchKernelGGL(order_kernel, dim3(1), dim3(kOrderThreads), 0, stream,
-                           reinterpret_cast<const uint32_t *>(a.sched_start) + 1, 2u, a.nq, a.sched_order);
-        hipLaunchKernelGGL((layer0_kernel<G, F, METRIC, KIND, BUF>), dim3(a.nq), dim3(64), lds, stream, ix, b);
-    }
+    else
+        hipLaunchKernelGGL((layer0_kernel<G, F, METRIC, KIND, BUF>), dim3(a.nq), dim3(64), lds, stream, ix, a);
     return hipGetLastError();
 }
 

@@ -115,7 +115,6 @@ __global__ __launch_bounds__(64) void serve_kernel(DevIndex ix, SearchArgs a, Se
         job.dists = sv.out_d + static_cast<size_t>(slot) * sv.kmax;
         job.counters = sv.counters + static_cast<size_t>(slot) * 4;
         job.trace = nullptr;
-        job.prio = nullptr;
         if ((LOWP & 1) && mode == HNSW_MODE_BF16 && ix.vbf16)
             search_one<G, F, METRIC, kBF16, false, true>(ix, a, job, s);
         else if ((LOWP & 2) && mode == HNSW_MODE_FP8 && ix.vfp8)

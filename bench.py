@@ -645,6 +645,17 @@ def main():
                          "expansions_per_query": round(float(c[:, 1].mean()), 2),
                          "layer0_expansions_per_query": round(float(c[:, 3].mean()), 2),
                          "sweep": curve}
+        if form == "plain":
+            # both launch forms forced, to show which one the library picked
+            fm = {}
+            for name, val in (("one_kernel", "0"), ("scheduled", "2")):
+                os.environ["HNSW_SCHEDULE"] = val
+                try:
+                    fm[name] = round(run.time(ef, mode, max(5, a.steps // 2), a.warmup)[1], 4)
+                finally:
+                    del os.environ["HNSW_SCHEDULE"]
+            fm["chosen"] = min(("one_kernel", "scheduled"), key=lambda k: abs(fm[k] - kern_ms))
+            results[form]["launch_forms_kernel_ms"] = fm
         log(f"[bench] {form}: {results[form]}")
 
     # the K = 1 half of the workload: plain fp32, recall@1 against the exact nearest neighbour
@@ -728,8 +739,11 @@ def main():
                      "traffic": traffic,
                      "traffic_kind": "L2-to-fabric bytes per call (rocprofv3 FETCH_SIZE + WRITE_SIZE, scaled by a "
                                      "plain copy); they include hits in the Infinity Cache (MALL)",
-                     "kernel": "search call: descent_kernel + order_kernel + layer0_kernel (one stream, "
-                               "event-timed together)", "kernel_ms": head["kernel_ms"],
+                     "kernel": ("search call: descent_kernel + order_kernel + layer0_kernel (one stream, "
+                                "event-timed together)"
+                                if head.get("launch_forms_kernel_ms", {}).get("chosen", "scheduled") == "scheduled"
+                                else "search call: search_kernel (one launch, event-timed)"),
+                     "kernel_ms": head["kernel_ms"],
                      "algorithmic_bytes_per_launch": head["bytes_per_step"], "counts": counts,
                      "kernel_hash": khash},
         "forms": results,

@@ -354,6 +354,9 @@ static hnsw_status search_impl(const hnsw_index *index, const float *queries, ui
     a.mlp = hnsw::DevMlp{};
     if (mode == HNSW_MODE_LEARNED) a.mlp = static_cast<const hnsw_mlp *>(mlp)->net;
     a.ckpt_trace = mode == HNSW_MODE_LEARNED ? trace : nullptr;
+    // low-precision stores: a replacing visited table above ef 64 (below, the
+    // forgetting one keeps the merge's fast path for batches that forgot nothing)
+    a.replace = (mode == HNSW_MODE_BF16 || mode == HNSW_MODE_FP8 || mode == HNSW_MODE_U8) && efe > 64;
     a.ht_slots = hnsw::visited_slots(a, mode == HNSW_MODE_LEARNED);
     a.no_alloc = no_alloc;
     if (hnsw::launch_search(index->ix, a, static_cast<hipStream_t>(stream)) != hipSuccess) {

@@ -57,6 +57,7 @@ struct SearchArgs {
     uint32_t wslots;       // LDS slots reserved for W: wcap, or the power of two >= wcap for the stores that sort W
     uint32_t ht_slots;     // visited-table slots, >= 256 (probe steps reach 128 slots and wrap once)
     int mode;              // hnsw_mode
+    bool replace;          // low-precision stores: a full visited table replaces an old id (as fp32 always does)
     DevMlp mlp;            // learned stop rule (mode HNSW_MODE_LEARNED)
     float *ckpt_trace;     // learned mode: [nq][max_ckpt][26] features + outputs per checkpoint, or null
     // Scheduled launches (descents first, then layer 0 in a chosen order, see

@@ -47,9 +47,13 @@ size_t search_lds_bytes(const SearchArgs &a, bool learned) {
 // can cost a wave), and at least 1,024 slots; a fuller table forgets fewer
 // ids (a forgotten id is scored again).  FP8 is sized like the others: a
 // table filling a 20th of the LDS (all of it at five waves per SIMD)
-// measured 2% slower.  A table that grows with ef costs waves at large ef:
-// on glove_like 1.2M at ef 288 (10,000 queries) 1,024 slots took 5.53 ms,
-// 2,048 slots 6.15 ms and 512 slots 5.81 ms (at ef 320, 4,096 slots 10.3 ms).
+// measured 2% slower.  A table that grows with ef costs more waves than it
+// saves: on glove_like 1.2M at ef 288 (10,000 queries) 1,024 slots took
+// 5.53 ms, 2,048 slots 6.15 ms and 512 slots 5.81 ms (at ef 320, 4,096 slots
+// 10.3 ms).  Above ef 64 the low-precision stores' table replaces old ids as
+// the fp32 one does (on deep_like 10M at ef 256, BF16 / FP8: 1.54 / 1.67 M
+// queries/s with a forgetting table of 2,048 slots, 1.37 / 1.49 M with 1,024
+// slots, 1.84 / 1.92 M with a replacing table of 1,024 slots).
 // HNSW_VISITED_LOG2 = 8..14 fixes a power of two instead.
 uint32_t visited_slots(const SearchArgs &a, bool learned) {
     if (const char *v = getenv("HNSW_VISITED_LOG2")) {
@@ -67,6 +71,18 @@ uint32_t visited_slots(const SearchArgs &a, bool learned) {
     // they hold as many waves per CU as the plain ones (the table decides no
     // feature of the stop rule)
     return learned ? slots - static_cast<uint32_t>(search_lds_bytes(t, true) - fixed) / 4 : slots;
+}
+
+// The store a search mode traverses (descent and layer 0) fits the buffered
+// gathers; a low-precision form's re-rank checks the fp32 store itself.
+bool traversal_buffered(const DevIndex &ix, int mode) {
+    auto fits = [&](uint32_t stride16) { return (static_cast<uint64_t>(ix.n) + 1) * stride16 * 16 <= kBufferedMaxBytes; };
+    switch (mode) {
+        case HNSW_MODE_BF16: return fits(ix.bf16_stride16);
+        case HNSW_MODE_FP8: return fits(ix.fp8_stride16);
+        case HNSW_MODE_U8: return fits(ix.u8_stride16);
+        default: return fits(ix.stride4);
+    }
 }
 
 bool stores_buffered(const DevIndex &ix) {
@@ -286,7 +302,7 @@ uint8_t *noalloc_scratch() {
 }  // namespace
 
 // HNSW_WIDE_GATHERS=1 sends every launch through the 64-bit addressed kernels
-// (they are otherwise taken only for stores above 2 GiB), so that tests can
+// (they are otherwise taken only when the traversed store is above 2 GiB), so that tests can
 // check them on small indices.  HNSW_SCHEDULE=0 keeps every batch in one
 // kernel, HNSW_SCHEDULE=2 schedules every batch (both for tests); by default
 // a batch is scheduled when it holds more queries than waves resident at once.
@@ -319,7 +335,7 @@ hipError_t launch_search(const DevIndex &ix, const SearchArgs &a0, hipStream_t s
             a.sched = 0;
         }
     }
-    if (stores_buffered(ix) && !force_wide) return launch_search_stores<true>(ix, a, stream);
+    if (traversal_buffered(ix, a.mode) && !force_wide) return launch_search_stores<true>(ix, a, stream);
     return launch_search_wide(ix, a, stream);
 }
 

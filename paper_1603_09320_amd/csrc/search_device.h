@@ -883,7 +883,10 @@ __device__ void search_layer0(const DevIndex &ix, const SearchArgs &a, const Job
     // faster (the longest queries, which end the batch, score fewer ids
     // twice); BF16 and FP8 0.4-1.6% slower (after a replacement their merge
     // must keep its duplicate checks), so they keep a forgetting table.
+    // The low-precision stores replace too when the host asks (large ef, where
+    // a forgetting table scores too many ids again).
     constexpr bool kReplace = KIND == kF32;
+    const bool replace = kReplace || a.replace;
     for (;;) {
         int c = -1;
         uint64_t ck = 0;
@@ -911,11 +914,12 @@ __device__ void search_layer0(const DevIndex &ix, const SearchArgs &a, const Job
         else
             ld = ix.adj0[static_cast<size_t>(cid) * ix.Mmax0 + lsel];
         const uint32_t e = lane < static_cast<int>(ix.Mmax0) ? ld : kNoLink;
-        const int vs = e != kNoLink ? visit<kReplace>(s.ht, ht_slots, e) : kSeen;
+        const int vs = e == kNoLink ? kSeen
+                       : (replace ? visit<true>(s.ht, ht_slots, e) : visit<false>(s.ht, ht_slots, e));
         const bool fresh = vs != kSeen;
         // with replacement an id that was inserted may have been scored before
         // (its slot was taken over), so the fp32 merge always keeps its checks
-        const bool forgot = kReplace || __ballot(vs == kForgot) != 0;
+        const bool forgot = replace || __ballot(vs == kForgot) != 0;
         const uint64_t fm = __ballot(fresh);
         const int m = __popcll(fm);
         if (fresh) s.ids[rank_in(fm)] = e;
@@ -947,11 +951,18 @@ __device__ void search_layer0(const DevIndex &ix, const SearchArgs &a, const Job
         QueryRegs<G, FX, kF32> QX;
         load_query<G, FX, kF32>(qrow, ix.dim, QX);
         const RowSource sx = rows_of(ix, a, kF32);
+        // the traversal copy may fit the buffered gathers while the fp32 store
+        // does not (10M x 96: 1.3-1.9 GB copies, a 3.8 GB store): then only
+        // the re-rank takes the 64-bit addressed loads
+        const bool fp32_buffered = (static_cast<uint64_t>(ix.n) + 1) * ix.stride4 * 16 <= kBufferedMaxBytes;
         for (uint32_t c0 = 0; c0 < wsize; c0 += 64) {
             const int cnt = static_cast<int>(min(64u, wsize - c0));
             if (lane < cnt) s.ids[lane] = key_id(s.W[c0 + lane]);
             wave_sync();
-            score_ids<G, FX, METRIC, kF32, BUF>(ix, sx, QX, s.ids, cnt, s.keys);
+            if (BUF && fp32_buffered)
+                score_ids<G, FX, METRIC, kF32, BUF>(ix, sx, QX, s.ids, cnt, s.keys);
+            else
+                score_ids<G, FX, METRIC, kF32, false>(ix, sx, QX, s.ids, cnt, s.keys);
             wave_sync();
             if (lane < cnt) s.W[c0 + lane] = s.keys[lane];
             wave_sync();

@@ -201,8 +201,11 @@ __device__ __forceinline__ double group_sum(double v) {
 
 // Vector stores the traversal can read.  A row is a sequence of 16-byte
 // pieces: 4 fp32, 8 bf16, 16 fp8-E4M3 or 16 unsigned 8-bit integer values;
-// the FP8 row carries its fp32 scale at byte offset lp_scale_off.
-enum StoreKind { kF32 = 0, kBF16 = 1, kFP8 = 2, kU8 = 3 };
+// the FP8 row carries its fp32 scale at byte offset lp_scale_off.  kU8E is
+// the 8-bit store when it equals the fp32 one (integer data in [0, 255]): its
+// distances are the fp32 ones, so its kernels carry no re-rank (and, without
+// the re-rank's registers, hold six waves per SIMD).
+enum StoreKind { kF32 = 0, kBF16 = 1, kFP8 = 2, kU8 = 3, kU8E = 4 };
 
 template <int KIND>
 struct Store;
@@ -226,6 +229,8 @@ struct Store<kU8> {
     static constexpr int VPP = 16;
     using QT = float;
 };
+template <>
+struct Store<kU8E> : Store<kU8> {};
 
 // Byte k of w as an OCP FP8-E4M3 code, decoded by the hardware conversion
 // (exact: every code is a float; the store holds no NaN codes).
@@ -244,7 +249,7 @@ __device__ __forceinline__ float piece_value(const uint4 &p, int j) {
     const uint32_t w = j < Store<KIND>::VPP / 4 ? p.x : (j < Store<KIND>::VPP / 2 ? p.y : (j < 3 * Store<KIND>::VPP / 4 ? p.z : p.w));
     if (KIND == kF32) return __uint_as_float(w);
     if (KIND == kBF16) return __uint_as_float((j & 1) ? (w & 0xFFFF0000u) : (w << 16));
-    if (KIND == kU8) return static_cast<float>((w >> (8 * (j & 3))) & 0xFFu);
+    if (KIND == kU8 || KIND == kU8E) return static_cast<float>((w >> (8 * (j & 3))) & 0xFFu);
     return fp8_byte(w, j);
 }
 
@@ -299,7 +304,7 @@ __device__ __forceinline__ RowSource make_source(const void *base, uint32_t stri
 __device__ __forceinline__ RowSource rows_of(const DevIndex &ix, const SearchArgs &a, int kind) {
     if (kind == kF32) return make_source(ix.vec, ix.stride4, ix.stride4, 0, ix.n);
     if (kind == kBF16) return make_source(ix.vbf16, ix.bf16_stride16, ix.bf16_stride16, 0, ix.n);
-    if (kind == kU8) return make_source(ix.vu8, ix.u8_stride16, ix.u8_pieces, 0, ix.n);
+    if (kind == kU8 || kind == kU8E) return make_source(ix.vu8, ix.u8_stride16, ix.u8_pieces, 0, ix.n);
     return make_source(ix.vfp8, ix.fp8_stride16, ix.fp8_pieces, ix.fp8_scale_off, ix.n);
 }
 
@@ -942,7 +947,7 @@ __device__ void search_layer0(const DevIndex &ix, const SearchArgs &a, const Job
     uint32_t n_rerank = 0;
     // an 8-bit copy that equals the fp32 store (integer data in [0, 255])
     // already gave the exact distances: nothing to re-rank
-    if (KIND != kF32 && !(KIND == kU8 && ix.u8_exact)) {
+    if constexpr (KIND != kF32 && KIND != kU8E) {
         // Low-precision traversal: re-score every element of W exactly from the
         // fp32 vectors (the same grouped gather and arithmetic as the plain
         // path, pieces of 4 floats, so each lane holds VPP/4 times as many)

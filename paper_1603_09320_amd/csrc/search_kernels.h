@@ -33,9 +33,10 @@ __device__ __forceinline__ void search_query(const DevIndex &ix, const SearchArg
 
 // Waves per SIMD the register allocation is held to: six for the fp32 and
 // BF16 stores (80 registers, no spills), five for FP8 and the 8-bit store
-// (their 16 values per piece need more; six would spill).
+// (their 16 values per piece need more; six would spill); six for an exact
+// 8-bit store of one piece per lane (78 registers without the re-rank).
 template <int G, int F, int METRIC, int KIND, bool BUF>
-__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(KIND == kFP8 || KIND == kU8 ? 5 : 6))) void search_kernel(
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(KIND == kFP8 || KIND == kU8 || (KIND == kU8E && F > 1) ? 5 : 6))) void search_kernel(
     DevIndex ix, SearchArgs a) {
     search_query<G, F, METRIC, KIND, false, BUF>(ix, a);
 }
@@ -208,7 +209,7 @@ __device__ __forceinline__ void layer0_query(const DevIndex &ix, const SearchArg
 }
 
 template <int G, int F, int METRIC, int KIND, bool BUF>
-__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(KIND == kFP8 || KIND == kU8 ? 5 : 6))) void layer0_kernel(
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(KIND == kFP8 || KIND == kU8 || (KIND == kU8E && F > 1) ? 5 : 6))) void layer0_kernel(
     DevIndex ix, SearchArgs a) {
     layer0_query<G, F, METRIC, KIND, false, BUF>(ix, a);
 }
@@ -295,7 +296,7 @@ hipError_t launch_search_stores(const DevIndex &ix, const SearchArgs &a, hipStre
     switch (a.mode) {
         case HNSW_MODE_BF16: return launch_kind<kBF16, BUF>(ix, a, stream);
         case HNSW_MODE_FP8: return launch_kind<kFP8, BUF>(ix, a, stream);
-        case HNSW_MODE_U8: return launch_kind<kU8, BUF>(ix, a, stream);
+        case HNSW_MODE_U8: return ix.u8_exact ? launch_kind<kU8E, BUF>(ix, a, stream) : launch_kind<kU8, BUF>(ix, a, stream);
         default: return launch_kind<kF32, BUF>(ix, a, stream);
     }
 }

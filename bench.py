@@ -437,16 +437,20 @@ def _ef_for_recall(idx, q, X, Q, gt, K, target, efs, steps=5):
 
 
 def paper_experiments(hnsw):
-    """The paper's synthetic-data experiments (Sec. 4.1, Figs. 3, 6, 7, 11), on
-    graphs built by the library on the GPU; query time per query of a
-    10,000-query batch at the smallest ef reaching the recall target.
+    """The paper's synthetic-data experiments (Sec. 4.1, Figs. 3, 6, 7, 11 and
+    the distance-count scaling of Sec. 5.1), on graphs built by the library on
+    the GPU; query time per query of a 10,000-query batch at the smallest ef
+    reaching the recall target.
       fig3: query time vs mL on random d = 4 vectors (10M), M = 6, with the
-            heuristic (Alg. 4) and with the M nearest (Alg. 3);
+            heuristic (Alg. 4) and with the M nearest (Alg. 3), at recall 0.95
+            and 0.99;
       fig6: query time vs Mmax0 on the 1M sift_like set (M = 16), at recall
             0.95 and 0.99;
       fig7: Alg. 3 against Alg. 4 on 1M d = 10 vectors, uniform and from 100
             isolated clusters, at recall 0.9, 0.95 and 0.99;
-      fig11: the ef needed for recall 0.9 / 0.99 (10-NN) vs the set size, d = 4."""
+      fig11: the ef needed for recall 0.9 / 0.99 (10-NN) vs the set size, d = 4;
+      distance evaluations per query against recall (10M, d = 4) and, at
+      recall 0.95, against the set size (d = 8, 100k to 10M)."""
     import math
 
     import torch
@@ -479,13 +483,14 @@ def paper_experiments(hnsw):
             bt = time.time() - t0
             if gt is None:
                 gt = gt_of(idx, q, 10)
-            r = _ef_for_recall(idx, q, X, Q, gt, 10, 0.95, efs)
-            r.update(mL=round(mL, 4), selection="heuristic" if heur else "simple", build_s=round(bt, 2),
-                     layers=idx.info()["max_level"] + 1)
-            log(f"[fig3] {r}")
-            rows.append(r)
+            for target in (0.95, 0.99):
+                r = _ef_for_recall(idx, q, X, Q, gt, 10, target, list(range(10, 65, 2)))
+                r.update(mL=round(mL, 4), selection="heuristic" if heur else "simple", build_s=round(bt, 2),
+                         layers=idx.info()["max_level"] + 1, target=target)
+                log(f"[fig3] {r}")
+                rows.append(r)
             idx.close()
-    out["fig3_mL_uniform4_10M"] = {"M": 6, "Mmax0": 12, "efC": 100, "K": 10, "target": 0.95, "rows": rows}
+    out["fig3_mL_uniform4_10M"] = {"M": 6, "Mmax0": 12, "efC": 100, "K": 10, "rows": rows}
     del X
 
     # Fig. 6: Mmax0 on sift_like 1M
@@ -536,8 +541,33 @@ def paper_experiments(hnsw):
             r.update(n=n, target=target)
             log(f"[fig11] {r}")
             rows.append(r)
+        if n == 10_000_000:
+            # distance evaluations against recall on the largest set (Sec. 5.1)
+            curve = []
+            run = Runner(idx, q, X, Q, 10, gt, 0, torch.cuda.current_stream())
+            for ef in (10, 12, 16, 20, 24, 32, 48, 64, 96, 128):
+                ids, _, cnt = run.search(ef, 0, counters=True)
+                torch.cuda.synchronize()
+                curve.append({"ef": ef, "recall": round(float(recall(ids.cpu().numpy(), X, Q, gt).mean()), 4),
+                              "dist_evals": round(float(cnt.cpu().numpy()[:, 0].astype(np.float64).mean()), 1)})
+            log(f"[dist-vs-recall] {curve}")
+            out["dist_evals_vs_recall_uniform4_10M"] = {"M": 6, "Mmax0": 12, "efC": 100, "K": 10, "curve": curve}
         idx.close()
     out["fig11_ef_vs_n_uniform4"] = {"M": 6, "Mmax0": 12, "efC": 100, "K": 10, "rows": rows}
+
+    # distance evaluations at recall 0.95 against the set size, d = 8 (Sec. 5.1)
+    rows = []
+    for n in (100_000, 1_000_000, 10_000_000):
+        X, Q = setup("uniform8", n)
+        q = torch.from_numpy(Q).cuda()
+        idx = hnsw.Index.build(X, M=8, Mmax0=16, efC=100, seed=8003)
+        gt = gt_of(idx, q, 10)
+        r = _ef_for_recall(idx, q, X, Q, gt, 10, 0.95, list(range(10, 201, 2)), steps=3)
+        r.update(n=n, layers=idx.info()["max_level"] + 1)
+        log(f"[scaling-d8] {r}")
+        rows.append(r)
+        idx.close()
+    out["dist_evals_vs_n_uniform8"] = {"M": 8, "Mmax0": 16, "efC": 100, "K": 10, "target": 0.95, "rows": rows}
     return out
 
 

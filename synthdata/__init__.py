@@ -20,6 +20,8 @@ Workloads (stand-ins for the paper's datasets, which are not available):
   0.5.  Stand-in for DEEP (Table 1).
 * ``uniform4``    -- 1,000,000 x 4 U[0,1).  Stand-in for the d=4 random sets
   (Sec. 4.1, Table 1).
+* ``uniform8``    -- d=8 U[0,1): the random set of the paper's scaling of the
+  distance count with the set size (Sec. 5.1).
 * ``uniform10`` / ``clustered10`` -- d=10 random vectors, U[0,1) or drawn from
   100 isolated clusters (centres U[0,1)^10, each point a centre plus 0.02 g),
   the two data sets of the paper's comparison of neighbour selection methods
@@ -43,13 +45,14 @@ SEEDS = {
     "deep_like": dict(mix=4000, base=4001, queries=4002, train=4004),
     "uniform4": dict(base=5001, queries=5002, train=5004),
     "uniform10": dict(base=6001, queries=6002, train=6004),
+    "uniform8": dict(base=8001, queries=8002, train=8004),
     "clustered10": dict(mix=7000, base=7001, queries=7002, train=7004),
 }
 
 DIMS = {"uniform16": 16, "sift_like": 128, "glove_like": 100, "deep_like": 96, "uniform4": 4, "uniform10": 10,
-        "clustered10": 10}
+        "clustered10": 10, "uniform8": 8}
 METRIC = {"uniform16": "l2", "sift_like": "l2", "glove_like": "ip", "deep_like": "l2", "uniform4": "l2",
-          "uniform10": "l2", "clustered10": "l2"}
+          "uniform10": "l2", "clustered10": "l2", "uniform8": "l2"}
 
 
 def _rng(seed: int, stream: int) -> np.random.Generator:
@@ -147,6 +150,8 @@ def base(workload: str, n: int) -> np.ndarray:
         return _uniform(n, 4, sd["base"])
     if workload == "uniform10":
         return _uniform(n, 10, sd["base"])
+    if workload == "uniform8":
+        return _uniform(n, 8, sd["base"])
     if workload == "clustered10":
         return _clustered_points(n, sd["base"], sd["mix"])
     if workload == "sift_like":
@@ -171,6 +176,8 @@ def queries(workload: str, n: int, train: bool = False) -> np.ndarray:
         return _uniform(n, 4, seed)
     if workload == "uniform10":
         return _uniform(n, 10, seed)
+    if workload == "uniform8":
+        return _uniform(n, 8, seed)
     if workload == "clustered10":
         return _clustered_points(n, seed, sd["mix"])
     if workload == "sift_like":

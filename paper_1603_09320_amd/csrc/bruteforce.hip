@@ -210,20 +210,20 @@ __device__ void wave_bitonic(uint64_t *a, int len) {
 // 16-byte LDS load.  Rows in LDS are padded by 4 floats against bank
 // conflicts.
 //
-// Candidate list of a query: KP sorted keys (the best so far, +inf-keys at
-// the start) followed by up to kTail unsorted admissions.  A ranking key
-// below the threshold (the KP-th best key) is appended; once the tail could
-// overflow during the next tile, the wave sorts the tail and merges it into
-// the sorted part by rank (a binary search of each key in the other list),
-// keeping the KP best and tightening the threshold.  A merge happens about
-// once per kTail - kTRows admissions instead of once per tile that admits
-// anything.
+// Candidate list of a query: its KP best keys so far, sorted, kept in the
+// query's slot of the output array `partial` (global memory, +inf-keys at the
+// start), and up to kTail unsorted admissions in LDS.  A ranking key below the
+// threshold (the KP-th best key) is appended to the LDS tail; once the tail
+// could overflow during the next tile, the wave sorts it, reads the sorted
+// part into LDS, merges the two by rank (a binary search of each key in the
+// other list), writes the KP best back and tightens the threshold: about one
+// merge per kTail - kTRows admissions.  Keeping the sorted lists out of LDS
+// lets three blocks share a CU (51 KB of LDS each at d = 128) instead of two.
 constexpr int kTRows = 32;   // base rows per tile
 constexpr int kTail = 64;    // unsorted admissions held beyond the KP best
 
-// Waves per block (16 queries each): four for KP = 32 (66 KB of LDS, two
-// blocks per CU), two for KP = 64 (the longer lists).
-constexpr int bf_tile_waves(int kp) { return kp <= 32 ? 4 : 2; }
+// Waves per block (16 queries each).
+constexpr int bf_tile_waves(int) { return 4; }
 
 // Count of the n (power of two) sorted keys a[] that are < x (strict) or
 // <= x, by a fixed-step binary search.
@@ -239,45 +239,50 @@ __device__ __forceinline__ int sorted_count(const uint64_t *a, uint64_t x) {
     return c + ((kLessEq ? v <= x : v < x) ? 1 : 0);
 }
 
-// Merge the tail of one query's list into its sorted KP best (whole wave).
-// On return bq[0..KP) holds the KP smallest keys of bq[0..count), sorted.
+// Merge one query's LDS tail (count keys) into its sorted KP best, which sit
+// in global memory at best[0..KP) (whole wave; scr: KP keys of LDS scratch).
+// Each lane below KP reads and writes only best[lane].  Returns the new KP-th
+// best key.
 template <int KP>
-__device__ void merge_tail(uint64_t *bq, uint32_t count, int lane) {
-    if (KP + lane >= static_cast<int>(count)) bq[KP + lane] = kMaxKey;  // kTail == 64 lanes
+__device__ uint64_t merge_tail(uint64_t *best, uint64_t *scr, uint64_t *tail, uint32_t count, int lane) {
+    if (lane >= static_cast<int>(count)) tail[lane] = kMaxKey;  // kTail == 64 lanes
+    if (lane < KP) scr[lane] = best[lane];
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
     __builtin_amdgcn_wave_barrier();
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
-    wave_bitonic(bq + KP, kTail);
+    wave_bitonic(tail, kTail);
     // stable merge (sorted part first on equal keys): ranks are distinct
-    const uint64_t t = bq[KP + lane];
-    const int rt = lane + sorted_count<KP, true>(bq, t);
+    const uint64_t t = tail[lane];
+    const int rt = lane + sorted_count<KP, true>(scr, t);
     uint64_t p = kMaxKey;
     int rp = KP;
     if (lane < KP) {
-        p = bq[lane];
-        rp = lane + sorted_count<kTail, false>(bq + KP, p);
+        p = scr[lane];
+        rp = lane + sorted_count<kTail, false>(tail, p);
     }
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
     __builtin_amdgcn_wave_barrier();
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
-    if (rp < KP) bq[rp] = p;
-    if (rt < KP) bq[rt] = t;
+    if (rp < KP) scr[rp] = p;
+    if (rt < KP) scr[rt] = t;
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
     __builtin_amdgcn_wave_barrier();
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+    if (lane < KP) best[lane] = scr[lane];
+    return scr[KP - 1];
 }
 
 template <int KP, int S>
 __global__ __launch_bounds__(256) void bf_tile(DevIndex ix, const float *Q, uint32_t nq, const float *xnorm,
                                                uint32_t chunk, uint32_t nchunks, uint64_t *partial) {
-    constexpr int CAP = KP + kTail;
     constexpr int WAVES = bf_tile_waves(KP), THREADS = 64 * WAVES, kTQ = 16 * WAVES;
     constexpr int UPT = (kTRows * S + THREADS - 1) / THREADS;  // float4 units per thread and tile (at most)
     constexpr uint32_t RS = 4 * S + 4;  // LDS row stride (floats)
     extern __shared__ __align__(16) uint8_t smem[];
     float *tile = reinterpret_cast<float *>(smem);                            // [kTRows][RS]
-    uint64_t *bufs = reinterpret_cast<uint64_t *>(smem + kTRows * RS * 4);    // [kTQ][CAP]
-    uint64_t *thrs = bufs + kTQ * CAP;                                        // [kTQ]
+    uint64_t *tails = reinterpret_cast<uint64_t *>(smem + kTRows * RS * 4);   // [kTQ][kTail]
+    uint64_t *scrs = tails + kTQ * kTail;                                      // [WAVES][KP]
+    uint64_t *thrs = scrs + WAVES * KP;                                        // [kTQ]
     uint32_t *cnts = reinterpret_cast<uint32_t *>(thrs + kTQ);                 // [kTQ]
 
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
@@ -286,9 +291,12 @@ __global__ __launch_bounds__(256) void bf_tile(DevIndex ix, const float *Q, uint
     const uint32_t ch = blockIdx.y;
     const uint32_t b_lo = ch * chunk, b_hi = min(ix.n, b_lo + chunk);
     const uint32_t units_row = ix.stride4;  // float4 units per stored row
-    uint64_t *mybuf = bufs + static_cast<size_t>(wave) * 16 * CAP;
+    uint64_t *mytail = tails + static_cast<size_t>(wave) * 16 * kTail;
+    uint64_t *myscr = scrs + wave * KP;
     uint64_t *mythr = thrs + wave * 16;
     uint32_t *mycnt = cnts + wave * 16;
+    // the sorted KP best of query q0 + qi (valid queries only)
+    auto best_of = [&](int qi) { return partial + (static_cast<size_t>(q0 + qi) * nchunks + ch) * KP; };
 
     // A operand: query q0 + j, coordinates g*S + s
     float a[S];
@@ -301,9 +309,10 @@ __global__ __launch_bounds__(256) void bf_tile(DevIndex ix, const float *Q, uint
         }
     }
     // every list starts as KP +inf-keys (sorted) and an empty tail
-    for (int e = lane; e < 16 * CAP; e += 64) mybuf[e] = kMaxKey;
+    for (int qi = 0; qi < 16; ++qi)
+        if (q0 + qi < nq && lane < KP) best_of(qi)[lane] = kMaxKey;
     if (lane < 16) {
-        mycnt[lane] = KP;
+        mycnt[lane] = 0;
         mythr[lane] = q0 + lane < nq ? kMaxKey : 0;  // a missing query admits nothing
     }
     // zero the tile once: columns beyond the stored row stay zero
@@ -388,7 +397,7 @@ __global__ __launch_bounds__(256) void bf_tile(DevIndex ix, const float *Q, uint
                 if (b < b_hi && key < thr[r]) {
                     const int qi = 4 * g + r;
                     const uint32_t slot = atomicAdd(&mycnt[qi], 1u);
-                    if (slot < static_cast<uint32_t>(CAP)) mybuf[qi * CAP + slot] = key;  // always: see the merge below
+                    if (slot < static_cast<uint32_t>(kTail)) mytail[qi * kTail + slot] = key;  // always: see the merge below
                 }
             }
         }
@@ -397,14 +406,14 @@ __global__ __launch_bounds__(256) void bf_tile(DevIndex ix, const float *Q, uint
         __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
         // merge the tails that could overflow during the next tile (a tile
         // adds at most kTRows keys to a query)
-        const uint64_t full = __ballot(lane < 16 && mycnt[lane] > static_cast<uint32_t>(CAP - kTRows));
+        const uint64_t full = __ballot(lane < 16 && mycnt[lane] > static_cast<uint32_t>(kTail - kTRows));
         for (uint64_t m = full; m;) {
             const int qi = __ffsll(static_cast<unsigned long long>(m)) - 1;
             m &= m - 1;
-            merge_tail<KP>(mybuf + qi * CAP, mycnt[qi], lane);
+            const uint64_t kth = merge_tail<KP>(best_of(qi), myscr, mytail + qi * kTail, mycnt[qi], lane);
             if (lane == 0) {
-                mythr[qi] = mybuf[qi * CAP + KP - 1];
-                mycnt[qi] = KP;
+                mythr[qi] = kth;
+                mycnt[qi] = 0;
             }
             __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
             __builtin_amdgcn_wave_barrier();
@@ -422,19 +431,14 @@ __global__ __launch_bounds__(256) void bf_tile(DevIndex ix, const float *Q, uint
             __syncthreads();
         }
     }
-    // final selection of each query of the wave
-    for (int qi = 0; qi < 16; ++qi) {
-        uint64_t *bq = mybuf + qi * CAP;
-        if (mycnt[qi] > static_cast<uint32_t>(KP)) merge_tail<KP>(bq, mycnt[qi], lane);
-        if (q0 + qi < nq)
-            for (int e = lane; e < KP; e += 64)
-                partial[(static_cast<size_t>(q0 + qi) * nchunks + ch) * KP + e] = bq[e];
-    }
+    // the last admissions of each query of the wave (a missing query has none)
+    for (int qi = 0; qi < 16; ++qi)
+        if (mycnt[qi] > 0) merge_tail<KP>(best_of(qi), myscr, mytail + qi * kTail, mycnt[qi], lane);
 }
 
 size_t bf_tile_lds(uint32_t S, int KP) {
     const size_t q = 16 * bf_tile_waves(KP);
-    return static_cast<size_t>(kTRows) * (4 * S + 4) * 4 + q * (KP + kTail) * 8 + q * 8 + q * 4;
+    return static_cast<size_t>(kTRows) * (4 * S + 4) * 4 + q * kTail * 8 + bf_tile_waves(KP) * KP * 8 + q * 8 + q * 4;
 }
 
 template <int KP>

@@ -125,12 +125,21 @@ hnsw_status hnsw_index_export(const hnsw_index *index, uint8_t *levels, uint32_t
  * point with no links; an element above the current top layer is inserted
  * alone and becomes the enter point.  With batch_div >= n every batch holds
  * one element and the graph is that of the sequential INSERT.
+ * extend_candidates (Alg. 4 extendCandidates) adds to each selection's
+ * candidates their neighbours on the layer (the base element excepted).  The
+ * extensions of the merge step read the lists as they stood before the
+ * batch's links, so with one element per batch a merge whose candidates
+ * include another list changed by the same element may differ from the
+ * sequential INSERT, which merges the receiving lists one after another.
  * Levels: l = floor(-ln(U) * mL), U = (r + 1) * 2^-53 with r the top 53 bits
  * of splitmix64(seed XOR i).
  *   vectors   host fp32 [n][dim] (copied; the caller may free it after).
  * The call synchronises `stream`; it allocates the index (as
  * hnsw_index_upload) and a temporary workspace of about
- * (batch_max + upper rows of a batch) * M * 48 bytes, freed before it returns.
+ * (batch_max + upper rows of a batch) * M * 48 bytes, freed before it returns;
+ * extend_candidates adds up to 512 MiB for the extended lists (batches are cut
+ * to fit) and (batch_max + upper rows of a batch) * M * max(Mmax, Mmax0) * 4
+ * bytes for the merged lists.
  */
 typedef struct {
     uint32_t M;          /* links of a new element on each layer (Alg. 1)        */
@@ -143,24 +152,32 @@ typedef struct {
     uint32_t batch_div;  /* a batch holds at most (elements inserted) / batch_div  */
     uint32_t batch_max;  /* and at most this many elements (0: 65,536)             */
     int select_simple;   /* 1: SELECT-NEIGHBORS-SIMPLE (Alg. 3, the M nearest)      */
-                         /* instead of the heuristic (extendCandidates: not built) */
+                         /* instead of the heuristic                               */
+    int extend_candidates; /* Alg. 4 extendCandidates (ignored with select_simple) */
 } hnsw_build_params;
 hnsw_status hnsw_index_build(const float *vectors, uint32_t n, uint32_t dim, int metric,
                              const hnsw_build_params *params, void *stream, hnsw_index **out);
 
 /*
- * The device's SELECT-NEIGHBORS-HEURISTIC (Alg. 4, extendCandidates off) on
- * explicit candidate lists, as graph construction runs it: for base element
- * base[i] of the index and candidates cand[i][0..nc) (element ids; 0xFFFFFFFF
- * entries are skipped), the distances to the base are computed, candidates
- * are taken in (distance, id) order and kept while their distance to the base
- * is smaller than their distance to every element kept before; keep_pruned
- * fills up to Mk with the discarded ones, nearest first.  out[i][Mk] receives
- * the kept ids in that order, 0xFFFFFFFF padded.  All pointers device memory;
- * nc <= 1024, Mk <= 64.
+ * The device's SELECT-NEIGHBORS-HEURISTIC (Alg. 4) on explicit candidate
+ * lists, as graph construction runs it: for base element base[i] of the index
+ * and candidates cand[i][0..nc) (element ids; 0xFFFFFFFF entries are
+ * skipped), the distances to the base are computed, candidates are taken in
+ * (distance, id) order and kept while their distance to the base is smaller
+ * than their distance to every element kept before; keep_pruned fills up to
+ * Mk with the discarded ones, nearest first.  extend (extendCandidates) first
+ * adds every neighbour on layer lc of a candidate, except the base, to the
+ * candidates (each element once).  out[i][Mk] receives the kept ids in that
+ * order, 0xFFFFFFFF padded.  All pointers device memory; nc <= 1024,
+ * Mk <= 64, 0 <= lc <= the index's top layer.  The ids are copied to the host
+ * and checked (HNSW_ERR_INVALID_ARG for an id >= n, or, with extend, a
+ * candidate whose level is below lc); the call synchronises `stream`.  With
+ * extend it allocates nb * 8 * (a power of two >= nc * (list width + 1)) bytes
+ * for the call.
  */
 hnsw_status hnsw_select_heuristic(const hnsw_index *index, const uint32_t *base, const uint32_t *cand, uint32_t nb,
-                                  uint32_t nc, uint32_t Mk, int keep_pruned, uint32_t *out, void *stream);
+                                  uint32_t nc, uint32_t Mk, int keep_pruned, int extend, int lc, uint32_t *out,
+                                  void *stream);
 
 /*
  * Batched K-NN-SEARCH (Alg. 5), one query per wavefront.

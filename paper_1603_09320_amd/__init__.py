@@ -47,6 +47,7 @@ class BuildParams(C.Structure):
         ("M", C.c_uint32), ("Mmax", C.c_uint32), ("Mmax0", C.c_uint32), ("efC", C.c_uint32),
         ("mL", C.c_double), ("seed", C.c_uint64), ("keep_pruned", C.c_int),
         ("batch_div", C.c_uint32), ("batch_max", C.c_uint32), ("select_simple", C.c_int),
+        ("extend_candidates", C.c_int),
     ]
 
 
@@ -59,7 +60,7 @@ SIGNATURES = {
     "hnsw_index_info": (C.c_int, [_vp, _vp]),
     "hnsw_index_export": (C.c_int, [_vp, _vp, _vp, _vp, _vp]),
     "hnsw_index_build": (C.c_int, [_vp, _u32, _u32, _i32, C.POINTER(BuildParams), _vp, C.POINTER(_vp)]),
-    "hnsw_select_heuristic": (C.c_int, [_vp, _vp, _vp, _u32, _u32, _u32, _i32, _vp, _vp]),
+    "hnsw_select_heuristic": (C.c_int, [_vp, _vp, _vp, _u32, _u32, _u32, _i32, _i32, _i32, _vp, _vp]),
     "hnsw_search_batch": (C.c_int, [_vp, _vp, _u32, _u32, _u32, _vp, _vp, _vp]),
     "hnsw_search_batch_ex": (C.c_int, [_vp, _vp, _u32, _u32, _u32, _i32, _vp, _vp, _vp, _vp, _vp]),
     "hnsw_search_batch_noalloc": (C.c_int, [_vp, _vp, _u32, _u32, _u32, _i32, _vp, _vp, _vp, _vp, _vp]),
@@ -148,16 +149,17 @@ class Index:
     @classmethod
     def build(cls, vectors: np.ndarray, metric: int = HNSW_L2SQ, M: int = 16, Mmax=None, Mmax0=None, efC: int = 200,
               mL=None, seed: int = 1, keep_pruned: bool = False, batch_div: int = 16, batch_max: int = 65536,
-              heuristic: bool = True, stream=None) -> "Index":
+              heuristic: bool = True, extend: bool = False, stream=None) -> "Index":
         """Graph construction on the GPU (``hnsw_index_build``): INSERT in batches of at
-        most 1/batch_div of the elements inserted so far (batch_max at most)."""
+        most 1/batch_div of the elements inserted so far (batch_max at most).  extend:
+        Alg. 4's extendCandidates."""
         import math
 
         X = np.ascontiguousarray(vectors, dtype=np.float32)
         n, dim = X.shape
         p = BuildParams(M, M if Mmax is None else Mmax, 2 * M if Mmax0 is None else Mmax0, efC,
                         1.0 / math.log(M) if mL is None else mL, seed, int(keep_pruned), batch_div, batch_max,
-                        int(not heuristic))
+                        int(not heuristic), int(extend))
         h = C.c_void_p()
         _check("hnsw_index_build", lib().hnsw_index_build(_np(X), n, dim, metric, C.byref(p), _stream_ptr(stream),
                                                           C.byref(h)))
@@ -423,17 +425,19 @@ def bruteforce(index: Index, queries, k: int, stream=None):
     return ids, d
 
 
-def select_heuristic(index: Index, base, cand, Mk: int, keep_pruned: bool = False, stream=None):
+def select_heuristic(index: Index, base, cand, Mk: int, keep_pruned: bool = False, extend: bool = False, lc: int = 0,
+                     stream=None):
     """The device's SELECT-NEIGHBORS-HEURISTIC on explicit lists (``hnsw_select_heuristic``):
-    base int32 [nb], cand int32 [nb][nc] (-1 skipped) CUDA tensors; returns int32 [nb][Mk], -1 padded."""
+    base int32 [nb], cand int32 [nb][nc] (-1 skipped) CUDA tensors; returns int32 [nb][Mk], -1 padded.
+    extend: extendCandidates over the candidates' lists on layer lc."""
     import torch
 
     b = base.to(torch.int32).contiguous()
     c = cand.to(torch.int32).contiguous()
     out = torch.empty((b.shape[0], Mk), dtype=torch.int32, device=b.device)
     _check("hnsw_select_heuristic", lib().hnsw_select_heuristic(index.handle, _dptr(b), _dptr(c), b.shape[0],
-                                                                c.shape[1], Mk, int(keep_pruned), _dptr(out),
-                                                                _stream_ptr(stream)))
+                                                                c.shape[1], Mk, int(keep_pruned), int(extend),
+                                                                int(lc), _dptr(out), _stream_ptr(stream)))
     return out
 
 

@@ -45,6 +45,9 @@ struct BuildArgs {
     uint32_t ht_slots;       // visited-table slots (>= 256)
     int keep_pruned;         // Alg. 4 keepPrunedConnections
     int simple;              // SELECT-NEIGHBORS-SIMPLE (Alg. 3) instead of the heuristic
+    int extend;              // Alg. 4 extendCandidates
+    uint64_t *ext;           // extendCandidates: [waves][ecap] keys of each wave's extended list
+    uint32_t ecap;           // keys per wave (power of two >= efC * (max list width + 1))
     uint64_t upper_base;     // upper_off of the batch's first element with a layer >= 1 (row origin of its pairs)
     uint64_t *pair_key;      // [(batch + batch upper rows) * M] (lc << 32 | e), or kNoPair
     uint32_t *pair_val;      // the new element q of each pair
@@ -60,6 +63,11 @@ struct LinkArgs {
     uint32_t wpow2;           // LDS slots of the candidate list (power of two, <= 1024)
     int keep_pruned;
     int simple;               // Alg. 3 instead of Alg. 4
+    int extend;               // Alg. 4 extendCandidates
+    uint64_t *ext;            // [grid][ecap] keys of each wave's extended list
+    uint32_t ecap;            // power of two >= wpow2 * (max list width + 1)
+    uint32_t *stage;          // extendCandidates: [runs][stage_w] new lists, written to the graph afterwards
+    uint32_t stage_w;
 };
 
 namespace {
@@ -101,6 +109,21 @@ size_t build_lds_bytes(uint32_t wpow2, uint32_t ht_slots) {
     return static_cast<size_t>(wpow2) * 8 + 64 * 8 + 3 * 64 * 4 + static_cast<size_t>(ht_slots) * 4;
 }
 
+// Stores of one wave to global memory complete and are seen by the wave's
+// later loads from any lane (the workgroup is the one wave).
+__device__ __forceinline__ void global_sync() {
+    __threadfence_block();
+    wave_sync();
+}
+
+template <bool GW>
+__device__ __forceinline__ void list_sync() {
+    if constexpr (GW)
+        global_sync();
+    else
+        wave_sync();
+}
+
 // SELECT-NEIGHBORS-HEURISTIC (Alg. 4) over the candidates W[0..m), sorted by
 // (distance to the base, id) with clear flags: R receives at most Mk ids.  A
 // candidate is kept when its distance to the base is smaller (strictly) than
@@ -108,8 +131,10 @@ size_t build_lds_bytes(uint32_t wpow2, uint32_t ht_slots) {
 // not discarded is kept; every later candidate not discarded is then scored
 // against it and discarded unless it is nearer to the base.  keep_pruned
 // fills the rest of R with discarded candidates, nearest first.  W keeps its
-// keys; flags are set on kept and discarded candidates.
-template <int G, int F, int METRIC, bool BUF>
+// keys; flags are set on kept and discarded candidates.  GW: W is in global
+// memory (an extended candidate list), so flag stores are fenced before other
+// lanes read them.
+template <int G, int F, int METRIC, bool BUF, bool GW = false>
 __device__ uint32_t select_heuristic_w(const DevIndex &ix, const RowSource &src, const BuildLds &b, uint32_t m,
                                        uint32_t Mk, bool keep_pruned) {
     const int lane = lane_id();
@@ -135,7 +160,7 @@ __device__ uint32_t select_heuristic_w(const DevIndex &ix, const RowSource &src,
             b.R[r] = cid;
             b.s.W[c] = ck | 1ull;
         }
-        wave_sync();
+        list_sync<GW>();
         ++r;
         cursor = c + 1;
         if (r == Mk) break;
@@ -162,7 +187,7 @@ __device__ uint32_t select_heuristic_w(const DevIndex &ix, const RowSource &src,
                 // keep test: distance to the base < distance to the kept element
                 if (!(key_dist(w) < key_dist(b.s.keys[lane]))) b.s.W[p] = w | 1ull;
             }
-            wave_sync();
+            list_sync<GW>();
         }
     }
     if (keep_pruned && r < Mk) {
@@ -202,6 +227,114 @@ __device__ __forceinline__ uint32_t select_w(const DevIndex &ix, const RowSource
                                              uint32_t Mk, bool keep_pruned, bool simple) {
     if (simple) return select_simple_w(b, m, Mk);
     return select_heuristic_w<G, F, METRIC, BUF>(ix, src, b, m, Mk, keep_pruned);
+}
+
+// Ascending bitonic sort of E[0..cap) (cap a power of two >= 64) in global
+// memory by one wave; four compare-exchanges per lane are loaded together.
+__device__ void sort_global(uint64_t *E, uint32_t cap) {
+    const int lane = lane_id();
+    const uint32_t half = cap / 2;
+    for (uint32_t k = 2; k <= cap; k <<= 1)
+        for (uint32_t j = k >> 1; j > 0; j >>= 1) {
+            for (uint32_t t0 = lane; t0 < half; t0 += 256) {
+                uint32_t ii[4];
+                uint64_t x[4], y[4];
+#pragma unroll
+                for (int u = 0; u < 4; ++u) {
+                    const uint32_t t = t0 + 64u * u;
+                    ii[u] = 2 * j * (t / j) + (t % j);
+                    if (t < half) {
+                        x[u] = E[ii[u]];
+                        y[u] = E[ii[u] + j];
+                    }
+                }
+#pragma unroll
+                for (int u = 0; u < 4; ++u) {
+                    const uint32_t t = t0 + 64u * u;
+                    if (t < half && (x[u] > y[u]) == ((ii[u] & k) == 0)) {
+                        E[ii[u]] = y[u];
+                        E[ii[u] + j] = x[u];
+                    }
+                }
+            }
+            global_sync();
+        }
+}
+
+// Alg. 4's extendCandidates.  E receives the keys (distance to the base,
+// computed as for every other candidate) of the candidates W[0..m) and of
+// every neighbour on layer lc of a candidate, the base itself excepted, each
+// element once, ascending, flags clear; returns their count.  E is the wave's
+// global scratch of ecap >= m * (width + 1) keys.  An element met twice has
+// the same key both times, so the repeats are adjacent after the sort and are
+// dropped there.
+template <int G, int F, int METRIC, bool BUF>
+__device__ uint32_t extend_candidates(const DevIndex &ix, const RowSource &src, const QueryRegs<G, F, kF32> &QB,
+                                      const BuildLds &b, uint32_t m, uint32_t base_id, int lc, uint64_t *E) {
+    const int lane = lane_id();
+    for (uint32_t i = lane; i < m; i += 64) E[i] = b.s.W[i] & ~1ull;
+    uint32_t t = m;
+    const uint32_t width = lc ? ix.Mmax : ix.Mmax0;
+    const int lsel = min(lane, static_cast<int>(width) - 1);
+    int pend = 0;  // neighbour ids waiting in b.s.ids
+    for (uint32_t i = 0; i <= m; ++i) {
+        uint64_t vm = 0;
+        uint32_t e = kNoLink;
+        if (i < m) {
+            const uint32_t cid = key_id(b.s.W[i]);
+            // a candidate that is not a member of layer lc has no list there
+            if (lc == 0 || ix.uoff[cid] >= 0) {
+                const uint32_t ld = row_of(ix, cid, lc)[lsel];
+                e = lane < static_cast<int>(width) && ld != base_id ? ld : kNoLink;
+                vm = __ballot(e != kNoLink);
+            }
+        }
+        const int c = __popcll(vm);
+        if (pend > 0 && (i == m || pend + c > 64)) {
+            wave_sync();
+            score_ids<G, F, METRIC, kF32, BUF>(ix, src, QB, b.s.ids, pend, b.s.keys);
+            wave_sync();
+            if (lane < pend) E[t + lane] = b.s.keys[lane];
+            t += static_cast<uint32_t>(pend);
+            pend = 0;
+        }
+        if (e != kNoLink) b.s.ids[pend + rank_in(vm)] = e;
+        pend += c;
+    }
+    uint32_t p2 = 64;
+    while (p2 < t) p2 <<= 1;
+    for (uint32_t i = t + lane; i < p2; i += 64) E[i] = ~0ull;
+    global_sync();
+    sort_global(E, p2);
+    // drop repeats in place: a key is kept unless it equals its predecessor
+    // (~0ull, a flagged key, equals no candidate's)
+    uint32_t u = 0;
+    uint64_t last = ~0ull;
+    for (uint32_t cb = 0; cb < t; cb += 64) {
+        const uint32_t i = cb + lane;
+        const uint64_t v = i < t ? E[i] : ~0ull;
+        uint64_t prev = __shfl_up(v, 1, 64);
+        if (lane == 0) prev = last;
+        const bool keep = i < t && v != prev;
+        const uint64_t km = __ballot(keep);
+        last = readlane64(v, 63);
+        if (keep) E[u + rank_in(km)] = v;
+        u += static_cast<uint32_t>(__popcll(km));
+    }
+    global_sync();
+    return u;
+}
+
+// Alg. 4 with extendCandidates on the sorted candidates W[0..m) of base_id on
+// layer lc: the extended list is built in E, then selected from as W is.
+template <int G, int F, int METRIC, bool BUF>
+__device__ uint32_t select_extended(const DevIndex &ix, const RowSource &src, const QueryRegs<G, F, kF32> &QB,
+                                    const BuildLds &b, uint32_t m, uint32_t Mk, bool keep_pruned, uint32_t base_id,
+                                    int lc, uint64_t *E) {
+    const uint32_t u = extend_candidates<G, F, METRIC, BUF>(ix, src, QB, b, m, base_id, lc, E);
+    BuildLds g = b;
+    g.s.W = E;
+    return select_heuristic_w<G, F, METRIC, BUF, true>(ix, src, g, u, Mk, keep_pruned);
 }
 
 // SEARCH-LAYER (Alg. 2) on layer lc with ef candidates, entered from W[0..wsize)
@@ -299,7 +432,11 @@ __global__ __launch_bounds__(64) void build_insert_kernel(DevIndex ix, BuildArgs
         beam_layer<G, F, METRIC, BUF>(ix, src, Q, b, a.ht_slots, a.efC, wsize, lc);
         for (uint32_t i = lane; i < wsize; i += 64) b.s.W[i] &= ~1ull;
         wave_sync();
-        const uint32_t r = select_w<G, F, METRIC, BUF>(ix, src, b, wsize, M, a.keep_pruned != 0, a.simple != 0);
+        const uint32_t r =
+            a.extend && !a.simple
+                ? select_extended<G, F, METRIC, BUF>(ix, src, Q, b, wsize, M, a.keep_pruned != 0, q, lc,
+                                                     a.ext + static_cast<size_t>(blockIdx.x) * a.ecap)
+                : select_w<G, F, METRIC, BUF>(ix, src, b, wsize, M, a.keep_pruned != 0, a.simple != 0);
         const uint32_t width = lc ? ix.Mmax : ix.Mmax0;
         uint32_t *row = row_of(ix, q, lc);
         if (lane < static_cast<int>(width)) row[lane] = lane < static_cast<int>(r) ? b.R[lane] : kNoLink;
@@ -337,7 +474,10 @@ __device__ __forceinline__ void score_into_w(const DevIndex &ix, const RowSource
 
 // One element's list after the new links of a batch: appended when they fit,
 // else selected again by the heuristic from the element over its links and the
-// new ones (in chunks when more arrive than W holds).
+// new ones (in chunks when more arrive than W holds).  With extendCandidates
+// the new lists go to a.stage and build_commit_kernel writes them to the graph
+// afterwards, so every extension reads the lists as they stood before the
+// batch's links (no wave reads a list another wave is rewriting).
 template <int G, int F, int METRIC, bool BUF>
 __global__ __launch_bounds__(64) void build_link_kernel(DevIndex ix, LinkArgs a) {
     extern __shared__ __align__(16) uint8_t smem[];
@@ -352,7 +492,8 @@ __global__ __launch_bounds__(64) void build_link_kernel(DevIndex ix, LinkArgs a)
         const int lc = static_cast<int>(key >> 32);
         const uint32_t cnt = a.count[run], off = a.offset[run];
         const uint32_t cap = lc ? ix.Mmax : ix.Mmax0;
-        uint32_t *row = row_of(ix, e, lc);
+        const uint32_t *row = row_of(ix, e, lc);
+        uint32_t *out = a.stage ? a.stage + static_cast<size_t>(run) * a.stage_w : row_of(ix, e, lc);
         const uint32_t cur = lane < static_cast<int>(cap) ? row[lane] : kNoLink;
         const uint64_t hm = __ballot(cur != kNoLink);
         uint32_t have = static_cast<uint32_t>(__popcll(hm));
@@ -360,8 +501,11 @@ __global__ __launch_bounds__(64) void build_link_kernel(DevIndex ix, LinkArgs a)
         if (cur != kNoLink) b.R[rank_in(hm)] = cur;
         wave_sync();
         if (have + cnt <= cap) {
-            for (uint32_t j = lane; j < cnt; j += 64) row[have + j] = a.val[off + j];
-            for (uint32_t j = lane; j < have; j += 64) row[j] = b.R[j];
+            if (lane < static_cast<int>(cap))
+                out[lane] = lane < static_cast<int>(have)         ? b.R[lane]
+                            : lane < static_cast<int>(have + cnt) ? a.val[off + lane - have]
+                                                                  : kNoLink;
+            wave_sync();
             continue;
         }
         QueryRegs<G, F, kF32> QE;
@@ -384,20 +528,39 @@ __global__ __launch_bounds__(64) void build_link_kernel(DevIndex ix, LinkArgs a)
             uint32_t p2 = 64;
             while (p2 < m) p2 <<= 1;
             sort_w(b.s.W, m, p2);
-            have = select_w<G, F, METRIC, BUF>(ix, src, b, m, cap, a.keep_pruned != 0, a.simple != 0);
+            have = a.extend && !a.simple
+                       ? select_extended<G, F, METRIC, BUF>(ix, src, QE, b, m, cap, a.keep_pruned != 0, e, lc,
+                                                            a.ext + static_cast<size_t>(blockIdx.x) * a.ecap)
+                       : select_w<G, F, METRIC, BUF>(ix, src, b, m, cap, a.keep_pruned != 0, a.simple != 0);
         }
-        if (lane < static_cast<int>(cap)) row[lane] = lane < static_cast<int>(have) ? b.R[lane] : kNoLink;
+        if (lane < static_cast<int>(cap)) out[lane] = lane < static_cast<int>(have) ? b.R[lane] : kNoLink;
         wave_sync();
     }
 }
 
+// The staged lists of the runs (extendCandidates) into the graph.
+__global__ __launch_bounds__(64) void build_commit_kernel(DevIndex ix, LinkArgs a) {
+    const int lane = lane_id();
+    const uint32_t runs = *a.n_runs;
+    for (uint32_t run = blockIdx.x; run < runs; run += gridDim.x) {
+        const uint64_t key = a.key[run];
+        if (key == kNoPair) continue;
+        const int lc = static_cast<int>(key >> 32);
+        const uint32_t cap = lc ? ix.Mmax : ix.Mmax0;
+        uint32_t *row = row_of(ix, static_cast<uint32_t>(key), lc);
+        if (lane < static_cast<int>(cap)) row[lane] = a.stage[static_cast<size_t>(run) * a.stage_w + lane];
+    }
+}
+
 // Explicit candidate lists (tests of the in-wave heuristic): base element
-// base[i], candidates cand[i][0..nc) (kNoLink ends a list), Mk kept into
-// out[i][Mk] (kNoLink padded).
+// base[i], candidates cand[i][0..nc) (kNoLink entries skipped), Mk kept into
+// out[i][Mk] (kNoLink padded).  extend: extendCandidates on layer lc, with
+// the extended list of base i in ext[i][ecap].
 template <int G, int F, int METRIC, bool BUF>
 __global__ __launch_bounds__(64) void select_kernel(DevIndex ix, const uint32_t *base, const uint32_t *cand,
                                                     uint32_t nb, uint32_t nc, uint32_t Mk, uint32_t wpow2,
-                                                    int keep_pruned, uint32_t *out) {
+                                                    int keep_pruned, int extend, int lc, uint64_t *ext, uint32_t ecap,
+                                                    uint32_t *out) {
     extern __shared__ __align__(16) uint8_t smem[];
     const uint32_t i = blockIdx.x;
     if (i >= nb) return;
@@ -416,7 +579,9 @@ __global__ __launch_bounds__(64) void select_kernel(DevIndex ix, const uint32_t 
         m += static_cast<uint32_t>(c);
     }
     sort_w(b.s.W, m, wpow2);
-    const uint32_t r = select_heuristic_w<G, F, METRIC, BUF>(ix, src, b, m, Mk, keep_pruned != 0);
+    const uint32_t r = extend ? select_extended<G, F, METRIC, BUF>(ix, src, QE, b, m, Mk, keep_pruned != 0, base[i], lc,
+                                                                   ext + static_cast<size_t>(i) * ecap)
+                              : select_heuristic_w<G, F, METRIC, BUF>(ix, src, b, m, Mk, keep_pruned != 0);
     for (uint32_t j = lane; j < Mk; j += 64) out[static_cast<size_t>(i) * Mk + j] = j < r ? b.R[j] : kNoLink;
 }
 
@@ -430,13 +595,15 @@ struct BuildKernels {
     static hipError_t link(const DevIndex &ix, const LinkArgs &a, uint32_t grid, hipStream_t st) {
         const size_t lds = build_lds_bytes(a.wpow2, 0);
         hipLaunchKernelGGL((build_link_kernel<G, F, METRIC, BUF>), dim3(grid), dim3(64), lds, st, ix, a);
+        if (a.stage) hipLaunchKernelGGL(build_commit_kernel, dim3(grid), dim3(64), 0, st, ix, a);
         return hipGetLastError();
     }
     static hipError_t select(const DevIndex &ix, const uint32_t *base, const uint32_t *cand, uint32_t nb, uint32_t nc,
-                             uint32_t Mk, uint32_t wpow2, int keep_pruned, uint32_t *out, hipStream_t st) {
+                             uint32_t Mk, uint32_t wpow2, int keep_pruned, int extend, int lc, uint64_t *ext,
+                             uint32_t ecap, uint32_t *out, hipStream_t st) {
         const size_t lds = build_lds_bytes(wpow2, 0);
         hipLaunchKernelGGL((select_kernel<G, F, METRIC, BUF>), dim3(nb), dim3(64), lds, st, ix, base, cand, nb, nc, Mk,
-                           wpow2, keep_pruned, out);
+                           wpow2, keep_pruned, extend, lc, ext, ecap, out);
         return hipGetLastError();
     }
 };
@@ -558,8 +725,30 @@ hnsw_status hnsw_index_build(const float *vectors, uint32_t n, uint32_t dim, int
     // batches: element 0 alone (the first enter point), then at most
     // 1/batch_div of the elements inserted so far (and batch_max); an element
     // above the current top layer is inserted alone
-    const uint32_t bmax_cfg = pr->batch_max ? pr->batch_max : 65536u;
+    uint32_t bmax_cfg = pr->batch_max ? pr->batch_max : 65536u;
     const uint32_t M = pr->M;
+    // extendCandidates: a global list per wave of up to (candidates) x (list
+    // width + 1) keys; batches and link grids are sized so that these lists
+    // take at most kExtBytes, and the link phase re-selects at most 128
+    // candidates at a time
+    const bool extend = pr->extend_candidates != 0 && pr->select_simple == 0;
+    constexpr size_t kExtBytes = size_t(512) << 20;
+    const uint32_t wmax = pr->Mmax0 > pr->Mmax ? pr->Mmax0 : pr->Mmax;
+    const uint32_t link_wpow2 = extend ? 128u : 512u;
+    auto pow2_at_least = [](uint64_t v) {
+        uint64_t p = 64;
+        while (p < v) p <<= 1;
+        return static_cast<uint32_t>(p);
+    };
+    const uint32_t ecap_i = extend ? pow2_at_least(static_cast<uint64_t>(efC) * (wmax + 1)) : 0u;
+    const uint32_t ecap_l = extend ? pow2_at_least(static_cast<uint64_t>(link_wpow2) * (wmax + 1)) : 0u;
+    uint32_t link_grid_max = 8192;
+    if (extend) {
+        const size_t bi = std::max<size_t>(1, kExtBytes / (static_cast<size_t>(ecap_i) * 8));
+        if (bmax_cfg > bi) bmax_cfg = static_cast<uint32_t>(bi);
+        link_grid_max = static_cast<uint32_t>(
+            std::min<size_t>(8192, std::max<size_t>(1, kExtBytes / (static_cast<size_t>(ecap_l) * 8))));
+    }
 
     const uint32_t rf = row_floats_of(dim);
     const size_t vec_bytes = (static_cast<size_t>(n) + 1) * rf * 4;
@@ -596,8 +785,15 @@ hnsw_status hnsw_index_build(const float *vectors, uint32_t n, uint32_t dim, int
     uint32_t *ucnt = static_cast<uint32_t *>(tmp.take(max_pairs * 4));
     uint32_t *uofs = static_cast<uint32_t *>(tmp.take(max_pairs * 4));
     uint32_t *nruns = static_cast<uint32_t *>(tmp.take(16));
+    uint64_t *ext = nullptr;
+    uint32_t *stage = nullptr;
+    if (extend) {
+        const size_t keys = std::max(static_cast<size_t>(bmax_cfg) * ecap_i, static_cast<size_t>(link_grid_max) * ecap_l);
+        ext = static_cast<uint64_t *>(tmp.take(keys * 8));
+        stage = static_cast<uint32_t *>(tmp.take(max_pairs * wmax * 4));
+    }
     size_t t1 = 0, t2 = 0, t3 = 0;
-    bool ok = pk && pk2 && pv && pv2 && ukey && ucnt && uofs && nruns && dlv;
+    bool ok = pk && pk2 && pv && pv2 && ukey && ucnt && uofs && nruns && dlv && (!extend || (ext && stage));
     ok = ok && hipcub::DeviceRadixSort::SortPairs(nullptr, t1, pk, pk2, pv, pv2, static_cast<int>(max_pairs), 0, 40,
                                                   st) == hipSuccess;
     ok = ok && hipcub::DeviceRunLengthEncode::Encode(nullptr, t2, pk2, ukey, ucnt, nruns, static_cast<int>(max_pairs),
@@ -644,6 +840,9 @@ hnsw_status hnsw_index_build(const float *vectors, uint32_t n, uint32_t dim, int
     }
     ba.keep_pruned = pr->keep_pruned;
     ba.simple = pr->select_simple;
+    ba.extend = extend;
+    ba.ext = ext;
+    ba.ecap = ecap_i;
     ba.pair_key = pk;
     ba.pair_val = pv;
     LinkArgs la{};
@@ -652,9 +851,14 @@ hnsw_status hnsw_index_build(const float *vectors, uint32_t n, uint32_t dim, int
     la.offset = uofs;
     la.val = pv2;
     la.n_runs = nruns;
-    la.wpow2 = 512;
+    la.wpow2 = link_wpow2;
     la.keep_pruned = pr->keep_pruned;
     la.simple = pr->select_simple;
+    la.extend = extend;
+    la.ext = ext;
+    la.ecap = ecap_l;
+    la.stage = stage;
+    la.stage_w = wmax;
 
     uint32_t entry = 0, top = lv[0];
     uint32_t s = 1;
@@ -686,7 +890,7 @@ hnsw_status hnsw_index_build(const float *vectors, uint32_t n, uint32_t dim, int
         ok = ok && hipcub::DeviceRunLengthEncode::Encode(temp, t2, pk2, ukey, ucnt, nruns, static_cast<int>(npairs),
                                                          st) == hipSuccess;
         ok = ok && hipcub::DeviceScan::ExclusiveSum(temp, t3, ucnt, uofs, static_cast<int>(npairs), st) == hipSuccess;
-        const uint32_t grid = static_cast<uint32_t>(std::min<size_t>(npairs, 8192));
+        const uint32_t grid = static_cast<uint32_t>(std::min<size_t>(npairs, link_grid_max));
         ok = ok && with_kernels<BuildKernels>(ix, [&](auto k) { return k.link(ix, la, grid, st); }) == hipSuccess;
         if (alone && lv[s] > top) {
             entry = s;
@@ -719,18 +923,50 @@ hnsw_status hnsw_index_build(const float *vectors, uint32_t n, uint32_t dim, int
 }
 
 hnsw_status hnsw_select_heuristic(const hnsw_index *index, const uint32_t *base, const uint32_t *cand, uint32_t nb,
-                                  uint32_t nc, uint32_t Mk, int keep_pruned, uint32_t *out, void *stream) {
+                                  uint32_t nc, uint32_t Mk, int keep_pruned, int extend, int lc, uint32_t *out,
+                                  void *stream) {
     using namespace hnsw;
     if (!index || Mk == 0 || Mk > 64 || nc == 0 || nc > 1024) return HNSW_ERR_INVALID_ARG;
     if (nb == 0) return HNSW_OK;
     if (!is_device_ptr(base) || !is_device_ptr(cand) || !is_device_ptr(out)) return HNSW_ERR_INVALID_ARG;
+    const DevIndex &ix = index->ix;
+    if (lc < 0 || static_cast<uint32_t>(lc) > ix.max_level) return HNSW_ERR_INVALID_ARG;
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    // ids are checked on the host: every one in range, and with extend every
+    // candidate a member of layer lc (its list there is read)
+    std::vector<uint32_t> hb(nb), hc(static_cast<size_t>(nb) * nc);
+    if (hipMemcpyAsync(hb.data(), base, hb.size() * 4, hipMemcpyDeviceToHost, st) != hipSuccess ||
+        hipMemcpyAsync(hc.data(), cand, hc.size() * 4, hipMemcpyDeviceToHost, st) != hipSuccess ||
+        hipStreamSynchronize(st) != hipSuccess) {
+        (void)hipGetLastError();
+        return HNSW_ERR_DEVICE;
+    }
+    for (uint32_t b : hb)
+        if (b >= ix.n) return HNSW_ERR_INVALID_ARG;
+    for (uint32_t c : hc) {
+        if (c == kNoLink) continue;
+        if (c >= ix.n) return HNSW_ERR_INVALID_ARG;
+        if (extend && index->levels[c] < static_cast<uint32_t>(lc)) return HNSW_ERR_INVALID_ARG;
+    }
     uint32_t wpow2 = 64;
     while (wpow2 < nc) wpow2 <<= 1;
-    const DevIndex &ix = index->ix;
-    hipStream_t st = static_cast<hipStream_t>(stream);
-    if (with_kernels<BuildKernels>(ix, [&](auto k) {
-            return k.select(ix, base, cand, nb, nc, Mk, wpow2, keep_pruned, out, st);
-        }) != hipSuccess) {
+    uint32_t ecap = 0;
+    uint64_t *ext = nullptr;
+    if (extend) {
+        const uint32_t width = lc ? ix.Mmax : ix.Mmax0;
+        ecap = 64;
+        while (ecap < static_cast<uint64_t>(nc) * (width + 1)) ecap <<= 1;
+        if (hipMalloc(&ext, static_cast<size_t>(nb) * ecap * 8) != hipSuccess) {
+            (void)hipGetLastError();
+            return HNSW_ERR_OUT_OF_MEMORY;
+        }
+    }
+    const bool ok = with_kernels<BuildKernels>(ix, [&](auto k) {
+                        return k.select(ix, base, cand, nb, nc, Mk, wpow2, keep_pruned, extend, lc, ext, ecap, out, st);
+                    }) == hipSuccess &&
+                    (!ext || hipStreamSynchronize(st) == hipSuccess);
+    if (ext) device_free(ext);
+    if (!ok) {
         (void)hipGetLastError();
         return HNSW_ERR_DEVICE;
     }

@@ -111,6 +111,107 @@ def test_device_heuristic_equals_oracle(hnsw, keep):
             assert list(got) == [int(v) for v in want], (nc, Mk, i)
 
 
+@pytest.mark.parametrize("keep,lc", [(False, 0), (True, 0), (False, 1)])
+def test_device_extended_heuristic_equals_oracle(hnsw, keep, lc):
+    """Alg. 4 with extendCandidates: the candidates and every neighbour on
+    layer lc of a candidate (the base excepted, each element once) are
+    selected from.  On a graph with links (clustered d = 10, oracle-built),
+    the device's selection equals the oracle's, list for list; the extension
+    changes the result for many of the lists, so the check is not vacuous."""
+    print(f"case device heuristic extendCandidates keep_pruned={keep} lc={lc}", flush=True)
+    X = synthdata.base("clustered10", 3000)
+    G = oracle.Graph.build(X, M=6, efC=40, seed=5)
+    idx = hnsw.Index(G.packed(), X)
+    members = np.flatnonzero(G.packed()["levels"] >= lc)
+    rng = np.random.default_rng(11 + lc)
+    nb, changed = 200, 0
+    for nc, Mk in ((8, 6), (40, 12), (120, 32)):
+        base = rng.choice(members, nb)
+        cand = np.stack([rng.choice(np.setdiff1d(members, [b]), nc, replace=False) for b in base])
+        out = hnsw.select_heuristic(idx, torch.from_numpy(base.astype(np.int32)).cuda(),
+                                    torch.from_numpy(cand.astype(np.int32)).cuda(), Mk, keep, extend=True,
+                                    lc=lc).cpu().numpy()
+        for i in range(nb):
+            want = [int(v) for v in G.select_heuristic(int(base[i]), cand[i], Mk, lc=lc, extend=True,
+                                                       keep_pruned=keep)]
+            got = out[i][out[i] >= 0]
+            assert list(got) == want, (nc, Mk, i)
+            plain = [int(v) for v in G.select_heuristic(int(base[i]), cand[i], Mk, lc=lc, keep_pruned=keep)]
+            changed += plain != want
+    print(f"  extension changed {changed} of {3 * nb} selections", flush=True)
+    assert changed > nb // 2
+
+
+def test_extended_heuristic_rejects_ids_off_the_layer(hnsw):
+    """With extend, a candidate below layer lc (its list there would be read)
+    and an id out of range are refused before any kernel runs."""
+    X = synthdata.base("clustered10", 2000)
+    G = oracle.Graph.build(X, M=6, efC=30, seed=5)
+    idx = hnsw.Index(G.packed(), X)
+    lv = G.packed()["levels"]
+    low, high = int(np.flatnonzero(lv == 0)[0]), np.flatnonzero(lv >= 1)
+    base = torch.tensor([int(high[0])], dtype=torch.int32).cuda()
+    bad = torch.tensor([[int(high[1]), low]], dtype=torch.int32).cuda()
+    with pytest.raises(hnsw.HnswError):
+        hnsw.select_heuristic(idx, base, bad, 4, extend=True, lc=1)
+    out = hnsw.select_heuristic(idx, base, bad, 4, extend=True, lc=0).cpu().numpy()
+    assert (out[0][out[0] >= 0] < len(X)).all()
+    with pytest.raises(hnsw.HnswError):
+        hnsw.select_heuristic(idx, base, torch.tensor([[len(X)]], dtype=torch.int32).cuda(), 4)
+
+
+def test_extend_build_valid_and_recall(hnsw):
+    """extendCandidates in the batched device build, on the clustered data the
+    paper recommends it for (d = 10, 100 clusters): every list valid, and
+    search recall within 0.02 of the oracle's sequential build with the same
+    flag at equal ef."""
+    n = 20000
+    print(f"case GPU batched build with extendCandidates, clustered10 n={n}", flush=True)
+    X = synthdata.base("clustered10", n)
+    Q = synthdata.queries("clustered10", 500)
+    idx = hnsw.Index.build(X, M=8, efC=60, seed=4, extend=True)
+    _check_valid(idx.export(), 8, 8, 16)
+    G = oracle.Graph.build(X, M=8, efC=60, seed=4, extend=True)
+    oidx = hnsw.Index(G.packed(), X)
+    q = torch.from_numpy(Q).cuda()
+    _, gt = oracle.bruteforce(X, Q, 10, nthreads=8)
+    for ef in (16, 64):
+        ids, ds = idx.search(q, 10, ef)
+        oi, _ = oidx.search(q, 10, ef)
+        torch.cuda.synchronize()
+        ids, ds = ids.cpu().numpy(), ds.cpu().numpy()
+        _check_rows(ids, ds, X, Q, oracle.L2)
+        r_dev = parity.recall_at_k(ids, X, Q, gt, oracle.L2).mean()
+        r_orc = parity.recall_at_k(oi.cpu().numpy(), X, Q, gt, oracle.L2).mean()
+        print(f"  ef={ef}: recall device-built {r_dev:.4f}, oracle-built {r_orc:.4f}", flush=True)
+        assert r_dev >= r_orc - 0.02
+
+
+def test_extend_singleton_batches_close_to_oracle_insert(hnsw):
+    """extendCandidates with one element per batch.  The element's own
+    selections read the graph as the sequential INSERT does, so they agree;
+    a merge of a receiving list reads the other receiving lists as they stood
+    before the element's links, where the sequential INSERT sees those merged
+    before it, so a list can differ when its candidates include another
+    receiving element (and the difference can spread to later insertions).
+    Checked: levels and layer rows identical, every list valid, and nearly all
+    lists equal to the oracle's."""
+    n = 1500
+    print(f"case GPU build with extendCandidates, batches of one, n={n}", flush=True)
+    X = synthdata.base("clustered10", n)
+    G = oracle.Graph.build(X, M=6, efC=30, seed=11, extend=True)
+    want = G.packed()
+    idx = hnsw.Index.build(X, M=6, efC=30, seed=11, extend=True, batch_div=n + 1)
+    got = idx.export()
+    assert np.array_equal(got["levels"], want["levels"])
+    assert np.array_equal(got["upper_off"], want["upper_off"]) and got["rows"] == want["rows"]
+    _check_valid(got, 6, 6, 12)
+    lg, lw = _lists(got), _lists(want)
+    same = sum(lg.get(k) == lw[k] for k in lw)
+    print(f"  {same} of {len(lw)} lists equal to the oracle's", flush=True)
+    assert same >= 0.9 * len(lw)
+
+
 def _check_rows(ids, ds, X, Q, metric):
     """Properties of search output on a graph the oracle did not build: ids
     distinct and in range, distances ascending and equal (1e-5 relative) to

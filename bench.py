@@ -436,7 +436,7 @@ def _ef_for_recall(idx, q, X, Q, gt, K, target, efs, steps=5):
             "reached": bool(r >= target)}
 
 
-def paper_experiments(hnsw):
+def paper_experiments(hnsw, which=None):
     """The paper's synthetic-data experiments (Sec. 4.1, Figs. 3, 6, 7, 11 and
     the distance-count scaling of Sec. 5.1), on graphs built by the library on
     the GPU; query time per query of a 10,000-query batch at the smallest ef
@@ -446,13 +446,14 @@ def paper_experiments(hnsw):
             and 0.99;
       fig6: query time vs Mmax0 on the 1M sift_like set (M = 16), at recall
             0.95 and 0.99;
-      fig7: Alg. 3 against Alg. 4 on 1M d = 10 vectors, uniform and from 100
-            isolated clusters, at recall 0.9, 0.95 and 0.99;
+      fig7: Alg. 3 against Alg. 4, and Alg. 4 with extendCandidates, on 1M
+            d = 10 vectors, uniform and from 100 isolated clusters, at recall
+            0.9, 0.95 and 0.99;
       fig11: the ef needed for recall 0.9 / 0.99 (10-NN) vs the set size, d = 4;
       distance evaluations per query against recall (10M, d = 4) and, at
-      recall 0.95, against the set size (d = 8, 100k to 10M)."""
-    import math
-
+      recall 0.95, against the set size (d = 8, 100k to 10M).
+    which: names of the experiments to run (fig3, fig6, fig7, fig11, scaling);
+    all when None."""
     import torch
 
     import synthdata
@@ -470,7 +471,28 @@ def paper_experiments(hnsw):
         torch.cuda.synchronize()
         return gt.cpu().numpy()
 
+    def want(name):
+        return which is None or name in which
+
     # Fig. 3: mL on 10M random d=4
+    if want("fig3"):
+        fig3(hnsw, setup, gt_of, out)
+    if want("fig6"):
+        fig6(hnsw, setup, gt_of, efs, out)
+    if want("fig7"):
+        fig7(hnsw, setup, gt_of, efs, out)
+    if want("fig11"):
+        fig11(hnsw, setup, gt_of, out)
+    if want("scaling"):
+        scaling_d8(hnsw, setup, gt_of, out)
+    return out
+
+
+def fig3(hnsw, setup, gt_of, out):
+    import math
+
+    import torch
+
     X, Q = setup("uniform4", 10_000_000)
     q = torch.from_numpy(Q).cuda()
     rows = []
@@ -491,9 +513,11 @@ def paper_experiments(hnsw):
                 rows.append(r)
             idx.close()
     out["fig3_mL_uniform4_10M"] = {"M": 6, "Mmax0": 12, "efC": 100, "K": 10, "rows": rows}
-    del X
 
-    # Fig. 6: Mmax0 on sift_like 1M
+
+def fig6(hnsw, setup, gt_of, efs, out):
+    import torch
+
     X, Q = setup("sift_like", 1_000_000)
     q = torch.from_numpy(Q).cuda()
     rows = []
@@ -509,25 +533,37 @@ def paper_experiments(hnsw):
             rows.append(r)
         idx.close()
     out["fig6_Mmax0_sift_like_1M"] = {"M": 16, "efC": 200, "K": 10, "rows": rows}
-    del X
 
-    # Fig. 7: neighbour selection on clustered and uniform d=10
+
+def fig7(hnsw, setup, gt_of, efs, out):
+    """Neighbour selection on clustered and uniform d = 10: the M nearest
+    (Alg. 3), the heuristic (Alg. 4), and the heuristic with extendCandidates."""
+    import torch
+
     rows = []
     for wl in ("uniform10", "clustered10"):
         X, Q = setup(wl, 1_000_000)
         q = torch.from_numpy(Q).cuda()
         gt = None
-        for heur in (True, False):
-            idx = hnsw.Index.build(X, M=8, efC=100, seed=6003, heuristic=heur)
+        for sel in ("heuristic", "simple", "heuristic+extend"):
+            t0 = time.time()
+            idx = hnsw.Index.build(X, M=8, efC=100, seed=6003, heuristic=sel != "simple",
+                                   extend=sel == "heuristic+extend")
+            torch.cuda.synchronize()
+            bt = time.time() - t0
             if gt is None:
                 gt = gt_of(idx, q, 10)
             for target in (0.9, 0.95, 0.99):
                 r = _ef_for_recall(idx, q, X, Q, gt, 10, target, efs)
-                r.update(data=wl, selection="heuristic" if heur else "simple", target=target)
+                r.update(data=wl, selection=sel, build_s=round(bt, 2), target=target)
                 log(f"[fig7] {r}")
                 rows.append(r)
             idx.close()
     out["fig7_selection_d10_1M"] = {"M": 8, "Mmax0": 16, "efC": 100, "K": 10, "rows": rows}
+
+
+def fig11(hnsw, setup, gt_of, out):
+    import torch
 
     # Fig. 11: ef needed for a fixed recall vs N, d=4
     rows = []
@@ -555,6 +591,10 @@ def paper_experiments(hnsw):
         idx.close()
     out["fig11_ef_vs_n_uniform4"] = {"M": 6, "Mmax0": 12, "efC": 100, "K": 10, "rows": rows}
 
+
+def scaling_d8(hnsw, setup, gt_of, out):
+    import torch
+
     # distance evaluations at recall 0.95 against the set size, d = 8 (Sec. 5.1)
     rows = []
     for n in (100_000, 1_000_000, 10_000_000):
@@ -568,7 +608,6 @@ def paper_experiments(hnsw):
         rows.append(r)
         idx.close()
     out["dist_evals_vs_n_uniform8"] = {"M": 8, "Mmax0": 16, "efC": 100, "K": 10, "target": 0.95, "rows": rows}
-    return out
 
 
 def main():
@@ -590,6 +629,8 @@ def main():
                     help="skip the 10M x 96 low-precision measurement (graph built on the GPU)")
     ap.add_argument("--paper-experiments", action="store_true",
                     help="run the paper's synthetic-data experiments (Figs. 3, 6, 7, 11) instead; prints their JSON")
+    ap.add_argument("--experiments", default="",
+                    help="with --paper-experiments: comma list of fig3,fig6,fig7,fig11,scaling (default all)")
     ap.add_argument("--copy-probe-bytes", type=int, default=0,
                     help="also run a plain device-to-device copy of this size (counter calibration)")
     a = ap.parse_args()
@@ -605,7 +646,8 @@ def main():
 
     if a.paper_experiments:
         torch.cuda.set_device(0)
-        print(json.dumps({"paper_experiments": paper_experiments(hnsw)}), flush=True)
+        which = set(a.experiments.split(",")) if a.experiments else None
+        print(json.dumps({"paper_experiments": paper_experiments(hnsw, which)}), flush=True)
         return
     path, n, nq, K = WORKLOADS[a.workload]
     gpath = os.path.join(ROOT, path)

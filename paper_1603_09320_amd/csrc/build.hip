@@ -10,7 +10,8 @@
 //   for each layer lc = min(L, l)..0: SEARCH-LAYER with efConstruction
 //   candidates, entered from all of W of the layer above, then
 //   SELECT-NEIGHBORS-HEURISTIC (Alg. 4) for M neighbours, which become the
-//   element's list on lc.
+//   element's list on lc (with extendCandidates, over the candidates and
+//   their neighbours on lc, a list kept in global scratch).
 // Its new links e <- q are then grouped by (lc, e) with a stable radix sort,
 // and one wavefront per receiving element (build_link_kernel) appends them,
 // or, when the list would exceed Mmax (Mmax0 on layer 0), selects the list

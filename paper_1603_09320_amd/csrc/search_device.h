@@ -439,9 +439,12 @@ __device__ __forceinline__ WaveLds carve(uint8_t *base, const SearchArgs &a) {
 // wsize: W <- the ef smallest of W and the new keys, dropping keys whose
 // (distance, id) is already in W.  Returns the insertion position of the
 // smallest admitted key (INT_MAX when none was admitted).
-// Positions come from wave-wide comparisons: for each admitted key (broadcast
-// with readlane) a ballot over each 64-entry chunk of W counts the smaller
-// entries and detects an equal one; no LDS access depends on another.
+// Positions: while W fits one 64-entry chunk, from wave-wide comparisons (for
+// each admitted key, broadcast with readlane, a ballot over W counts the
+// smaller entries and detects an equal one); for a longer W, from a binary
+// search of W by every lane at once (log2(wsize) dependent LDS reads in place
+// of a ballot per chunk and admitted key: on glove_like at ef = 272 the
+// ballots were most of the kernel's scalar instructions).
 // `forgot`: some id of this batch was forgotten by the visited table.  Only
 // then can a new key already be in W (the id was scored before without being
 // recorded) or equal another new key of the batch (an adjacency row that
@@ -527,21 +530,18 @@ __device__ __forceinline__ int merge_into_w(const WaveLds &s, int m, uint32_t ef
             if (lane == t) dup = (same & ((1ull << t) - 1ull)) != 0;
         }
     }
-    for (int cb = 0; cb < ws; cb += 64) {
-        const int i = cb + lane;
-        const uint64_t w = i < ws ? (s.W[i] >> 1) : ~0ull;
-        uint64_t mm = cm;
-        while (mm) {
-            const int t = __ffsll(static_cast<unsigned long long>(mm)) - 1;
-            mm &= mm - 1;
-            const uint64_t at = readlane64(a, t) >> 1;
-            const int below = __popcll(__ballot(w < at));
-            const bool eq = forgot && __ballot(w == at) != 0;
-            if (lane == t) {
-                lb += below;
-                dup = dup || eq;
-            }
+    {
+        // each lane's position in W: the entries whose (distance, id) is below
+        // its key, by a binary search of W (the flag bit ignored; W is sorted,
+        // so it is sorted by key >> 1 too), and whether W holds the key
+        const uint64_t key = a >> 1;
+        int pos = 0;
+        for (int step = 1 << (31 - __clz(ws)); step > 0; step >>= 1) {
+            const int probe = pos + step - 1;
+            if (probe < ws && (s.W[probe] >> 1) < key) pos += step;
         }
+        lb = pos;
+        if (forgot && pos < ws) dup = dup || (s.W[pos] >> 1) == key;
     }
     const bool keep = cand && !dup;
     const uint64_t km = __ballot(keep);

@@ -42,6 +42,8 @@ WORKLOADS = {
     "uniform4": ("graphs/uniform4_1M.bin", 1_000_000, 10_000, 10),
 }
 EF_SWEEP = [10, 16, 24, 32, 40, 48, 56, 64, 80, 96, 112, 128, 160, 192, 256, 320, 384, 512, 640, 800]
+# points of the recall / throughput curve (the workload's ef range, 10..800)
+CURVE_EFS = [10, 16, 24, 32, 48, 64, 96, 128, 192, 256, 384, 512, 800]
 HBM_PEAK_GBS = 8000.0
 METRIC = "QPS at recall@10≥0.95, plain vs learned/low-precision; HBM GB/s"
 
@@ -623,6 +625,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true",
                     help="skip the oracle legs (host timing and the oracle's work counts)")
     ap.add_argument("--no-k1", action="store_true", help="skip the K = 1 measurement")
+    ap.add_argument("--no-curve", action="store_true",
+                    help="skip the recall / throughput curve over ef 10..800 (skipped with --ef too)")
     ap.add_argument("--no-serve", action="store_true", help="skip the serving-loop measurement")
     ap.add_argument("--no-glove", action="store_true", help="skip the learned-rule measurement on glove_like")
     ap.add_argument("--no-deep10m", action="store_true",
@@ -740,6 +744,23 @@ def main():
               "ms_per_step": round(ms1, 4), "kernel_ms": round(kern1, 4), "sweep": curve1}
         log(f"[bench] plain K=1: {k1}")
 
+    # the recall / throughput trade-off over ef 10..800, plain fp32 and the 8-bit
+    # copy (not with --ef, which times one ef only)
+    curves = None
+    if not a.no_curve and not a.ef:
+        curves = {}
+        for form in [f for f in ("plain", "u8") if f in forms]:
+            pts = []
+            for ef in CURVE_EFS:
+                ids, _ = run.search(ef, mode_of[form])
+                torch.cuda.synchronize()
+                r = float(recall(ids.cpu().numpy(), X, Q, gt_d64, graph["metric"]).mean())
+                ms, kern = run.time(ef, mode_of[form], 5, 1)
+                pts.append({"ef": ef, "recall": round(r, 5), "qps": round(nq / (ms / 1000.0), 1),
+                            "kernel_ms": round(kern, 4)})
+            curves[form] = pts
+            log(f"[bench] curve {form}: {pts}")
+
     if a.copy_probe_bytes:
         src = torch.ones(a.copy_probe_bytes // 4, dtype=torch.float32, device=dev)
         dst = torch.empty_like(src)
@@ -820,6 +841,7 @@ def main():
                      "kernel_hash": khash},
         "forms": results,
         "plain_k1": k1,
+        "recall_qps_curve": curves,
         "bruteforce": {"ms": round(bf_ms, 3), "queries": nq,
                        "tflops": round(2.0 * nq * graph["n"] * graph["dim"] / (bf_ms / 1000.0) / 1e12, 2)},
         "cpu_baseline": cpu,

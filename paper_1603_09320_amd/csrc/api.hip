@@ -344,9 +344,10 @@ static hnsw_status search_impl(const hnsw_index *index, const float *queries, ui
     a.wcap = (efe + 63) & ~63u;
     // W needs wcap slots; the low-precision stores sort W after their re-rank
     // (bitonic, a power of two of slots).  A power of two for every store cost
-    // the fp32 search a third of its waves per CU just above ef = 256.
+    // the fp32 search a third of its waves per CU just above ef = 256.  An
+    // exact 8-bit copy has no re-rank and keeps wcap.
     a.wslots = a.wcap;
-    if (mode == HNSW_MODE_BF16 || mode == HNSW_MODE_FP8 || mode == HNSW_MODE_U8) {
+    if (mode == HNSW_MODE_BF16 || mode == HNSW_MODE_FP8 || (mode == HNSW_MODE_U8 && !index->ix.u8_exact)) {
         a.wslots = 64;
         while (a.wslots < a.wcap) a.wslots <<= 1;
     }

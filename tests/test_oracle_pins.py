@@ -220,14 +220,88 @@ def test_heuristic_contains_relative_neighbourhood_graph():
 
 
 def test_heuristic_flags():
-    """Alg. 4 flags: keepPrunedConnections tops R up to M from the discarded
-    queue, nearest first; extendCandidates adds the candidates' neighbours."""
+    """Alg. 4's keepPrunedConnections tops R up to M from the discarded queue,
+    nearest first (extendCandidates: the two tests after this one)."""
     x = np.array([[0.0], [1.0], [2.0], [3.0], [-1.0], [10.0]], dtype=np.float32)
     G = _flat_graph(x)
     # base 0: candidates 1,2,3 on one side -> only 1 kept (2 and 3 are closer to 1)
     assert list(G.select_heuristic(0, [1, 2, 3], M=3)) == [1]
     assert list(G.select_heuristic(0, [1, 2, 3], M=3, keep_pruned=True)) == [1, 2, 3]
     assert list(G.select_heuristic(0, [3, 2, 1, 4], M=2)) == [1, 4]
+
+
+def _linked_graph(X, lists, width=8):
+    """One-layer graph whose layer-0 lists are given (dict id -> ids)."""
+    n = X.shape[0]
+    adj0 = np.full((n, width), 0xFFFFFFFF, np.uint32)
+    for i, lst in lists.items():
+        adj0[i, :len(lst)] = lst
+    packed = dict(metric=oracle.L2, M=4, Mmax=4, Mmax0=width, entry_point=0, max_level=0,
+                  levels=np.zeros(n, np.uint8), adj0=adj0, adjU=np.zeros((0, 4), np.uint32))
+    return oracle.Graph.from_packed(X, packed)
+
+
+def test_heuristic_extend_candidates_worked_example():
+    """Alg. 4 extendCandidates on 1-D points, worked by hand.  Points 0..5 at
+    0, 1, 2, 3, -1, 10; lists 3: {2, 5}, 2: {1, 3}, 4: {0, 1}, 5: {3}.
+    Base 0, candidates {3}: the extension adds 2 and 5; taken in distance
+    order 2 (2), 3 (3), 5 (10), 2 is kept and both others are nearer to 2 than
+    to the base, so R = [2] (plain: [3]); keepPrunedConnections tops up with
+    3 and 5.  Candidates {3, 4}: the extension adds 2, 5 (from 3) and 1 (from
+    4; the base itself is not added); 1 and 4 tie at distance 1 and go in id
+    order, both kept (4 is 2 away from 1), so R = [1, 4] (plain: [4, 3])."""
+    x = np.array([[0.0], [1.0], [2.0], [3.0], [-1.0], [10.0]], dtype=np.float32)
+    G = _linked_graph(x, {3: [2, 5], 2: [1, 3], 4: [0, 1], 5: [3]})
+    assert list(G.select_heuristic(0, [3], M=2)) == [3]
+    assert list(G.select_heuristic(0, [3], M=2, extend=True)) == [2]
+    assert list(G.select_heuristic(0, [3], M=3, extend=True, keep_pruned=True)) == [2, 3, 5]
+    assert list(G.select_heuristic(0, [3, 4], M=2)) == [4, 3]
+    assert list(G.select_heuristic(0, [3, 4], M=2, extend=True)) == [1, 4]
+    assert list(G.select_heuristic(0, [3, 4], M=4, extend=True)) == [1, 4]
+    assert list(G.select_heuristic(0, [3, 4], M=5, extend=True, keep_pruned=True)) == [1, 4, 2, 3, 5]
+
+
+def _extended_selection_model(X, lists, base, cand, M, keep_pruned):
+    """Alg. 4 with extendCandidates written out from its definition: the
+    candidates plus every listed neighbour of a candidate, the base excepted,
+    each element once; visited nearest first ((distance, id) order); an
+    element is kept when it is nearer to the base than to every element kept
+    so far; the discarded ones top R up, nearest first, under keepPruned."""
+    def d(a, b):
+        return np.float32(((X[a].astype(np.float64) - X[b].astype(np.float64)) ** 2).sum())
+    W = list(dict.fromkeys(list(cand) + [e for c in cand for e in lists.get(c, []) if e != base]))
+    W.sort(key=lambda e: (d(e, base), e))
+    R, Wd = [], []
+    for e in W:
+        if len(R) >= M:
+            break
+        if all(d(e, base) < d(e, r) for r in R):
+            R.append(e)
+        else:
+            Wd.append(e)
+    if keep_pruned:
+        R += Wd[:M - len(R)]
+    return R
+
+
+def test_heuristic_extend_candidates_matches_model():
+    """The oracle's extended selection equals the model above on random small
+    graphs with integer coordinates (exact distances, so ties are real ties and
+    both sides order them by id)."""
+    rng = np.random.default_rng(21)
+    for trial in range(300):
+        n, dim = int(rng.integers(6, 40)), int(rng.integers(1, 4))
+        X = rng.integers(0, 6, size=(n, dim)).astype(np.float32)
+        lists = {i: [int(v) for v in rng.choice(np.setdiff1d(np.arange(n), [i]), int(rng.integers(0, 6)),
+                                                replace=False)] for i in range(n)}
+        G = _linked_graph(X, lists)
+        base = int(rng.integers(0, n))
+        cand = [int(v) for v in rng.choice(np.setdiff1d(np.arange(n), [base]), int(rng.integers(1, min(8, n - 1))),
+                                           replace=False)]
+        M = int(rng.integers(1, 8))
+        keep = bool(rng.integers(0, 2))
+        got = [int(v) for v in G.select_heuristic(base, cand, M=M, extend=True, keep_pruned=keep)]
+        assert got == _extended_selection_model(X, lists, base, cand, M, keep), (trial, got)
 
 
 # ------------------------------------------------- P6: k-NN graph special case

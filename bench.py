@@ -236,9 +236,10 @@ class Runner:
         return wall * 1000.0 / steps, float(np.mean([s.elapsed_time(e) for s, e in evs]))
 
 
-# Each server's persistent grid: at ef_max = 512 a wave reserves about 22 KB of
-# LDS (7 waves per CU, 1792 on the chip), so two servers of 768 waves are
-# resident together.
+# Each server's persistent grid must stay resident next to the other's: the
+# main index's kernel (plain, learned, BF16 and FP8 inlined) holds one wave per
+# SIMD by its registers, the uniform4 one's (plain and BF16) two, and at
+# ef_max = 512 a wave reserves 13.3 KB of LDS; 512 + 1024 waves fit together.
 def serve_bench(hnsw, index, Q, mlp, rates=(50_000, 100_000, 200_000, 500_000), n_req=20_000, seed=7):
     """Continuous-batching serving: an open-loop Poisson replay over two live
     servers, the main index (plain, learned when a net is loaded, BF16 and

@@ -237,9 +237,9 @@ class Runner:
 
 
 # Each server's persistent grid must stay resident next to the other's: the
-# main index's kernel (plain, learned, BF16 and FP8 inlined) holds one wave per
-# SIMD by its registers, the uniform4 one's (plain and BF16) two, and at
-# ef_max = 512 a wave reserves 13.3 KB of LDS; 512 + 1024 waves fit together.
+# main index's kernel (plain, learned, BF16 and FP8 inlined) holds two waves
+# per SIMD by its registers, and at ef_max = 512 a wave reserves 13.3 KB of
+# LDS; 512 + 1024 waves fit together.
 def serve_bench(hnsw, index, Q, mlp, rates=(50_000, 100_000, 200_000, 500_000), n_req=20_000, seed=7):
     """Continuous-batching serving: an open-loop Poisson replay over two live
     servers, the main index (plain, learned when a net is loaded, BF16 and
@@ -267,8 +267,8 @@ def serve_bench(hnsw, index, Q, mlp, rates=(50_000, 100_000, 200_000, 500_000), 
     rng = np.random.default_rng(seed)
     slots = 4096
     for rate in rates:
-        # the main index's kernel holds one wave per SIMD (it inlines the FP8
-        # search), the other's two: 512 + 1024 waves are resident together
+        # 512 waves for the main index (its kernel inlines every kind), 1024
+        # for the uniform4 one: both grids are resident together
         servers = [hnsw.Server(index, mlp=mlp, slots=slots, waves=512, ef_max=512, k_max=100, budget_s=120.0)]
         if idx4 is not None:
             servers.append(hnsw.Server(idx4, mlp=None, slots=slots, waves=1024, ef_max=512, k_max=100,

@@ -66,11 +66,11 @@ __device__ __forceinline__ uint64_t load_sys64(const uint64_t *p) {
 // lanes leave it at different times, which defers the completion flag of a
 // served request until the others exit.
 // LOWP: the low-precision copies this server's kernel can traverse (bit 0
-// BF16, bit 1 FP8).  Each kind's search is inlined into the request loop, and
-// the registers follow: 102 for plain and learned alone (four waves per
-// SIMD), 182 with BF16 (two), 256 with FP8 (one), so a server instantiates
-// only the kinds its index holds.
-template <int G, int F, int METRIC, int LOWP>
+// BF16, bit 1 FP8).  Each kind's search is inlined into the request loop with
+// the lane-group shape the batch kernels use for that store (G, F for fp32;
+// GB, FB for BF16; G8, F8 for FP8), and a server instantiates only the kinds
+// its index holds: the registers are those of the widest kind inlined.
+template <int G, int F, int GB, int FB, int G8, int F8, int METRIC, int LOWP>
 __global__ __launch_bounds__(64) void serve_kernel(DevIndex ix, SearchArgs a, ServeArgs sv) {
     extern __shared__ __align__(16) uint8_t smem[];
     const WaveLds s = carve<true>(smem, a);
@@ -116,9 +116,9 @@ __global__ __launch_bounds__(64) void serve_kernel(DevIndex ix, SearchArgs a, Se
         job.counters = sv.counters + static_cast<size_t>(slot) * 4;
         job.trace = nullptr;
         if ((LOWP & 1) && mode == HNSW_MODE_BF16 && ix.vbf16)
-            search_one<G, F, METRIC, kBF16, false, true>(ix, a, job, s);
+            search_one<GB, FB, METRIC, kBF16, false, true>(ix, a, job, s);
         else if ((LOWP & 2) && mode == HNSW_MODE_FP8 && ix.vfp8)
-            search_one<G, F, METRIC, kFP8, false, true>(ix, a, job, s);
+            search_one<G8, F8, METRIC, kFP8, false, true>(ix, a, job, s);
         else if (mode == HNSW_MODE_LEARNED && a.mlp.w1)
             search_one<G, F, METRIC, kF32, true, true>(ix, a, job, s);
         else
@@ -129,25 +129,27 @@ __global__ __launch_bounds__(64) void serve_kernel(DevIndex ix, SearchArgs a, Se
     }
 }
 
-template <int G, int F, int LOWP>
+template <int G, int F, int GB, int FB, int G8, int F8, int LOWP>
 hipError_t launch_serve_gfl(const DevIndex &ix, const SearchArgs &a, const ServeArgs &sv, uint32_t waves,
                             hipStream_t st) {
     const size_t lds = search_lds_bytes(a, true);
     if (ix.metric == HNSW_IP)
-        hipLaunchKernelGGL((serve_kernel<G, F, HNSW_IP, LOWP>), dim3(waves), dim3(64), lds, st, ix, a, sv);
+        hipLaunchKernelGGL((serve_kernel<G, F, GB, FB, G8, F8, HNSW_IP, LOWP>), dim3(waves), dim3(64), lds, st, ix,
+                           a, sv);
     else
-        hipLaunchKernelGGL((serve_kernel<G, F, HNSW_L2SQ, LOWP>), dim3(waves), dim3(64), lds, st, ix, a, sv);
+        hipLaunchKernelGGL((serve_kernel<G, F, GB, FB, G8, F8, HNSW_L2SQ, LOWP>), dim3(waves), dim3(64), lds, st,
+                           ix, a, sv);
     return hipGetLastError();
 }
 
-template <int G, int F>
+template <int G, int F, int GB, int FB, int G8, int F8>
 hipError_t launch_serve_gf(const DevIndex &ix, const SearchArgs &a, const ServeArgs &sv, uint32_t waves,
                            hipStream_t st) {
     switch ((ix.vbf16 ? 1 : 0) | (ix.vfp8 ? 2 : 0)) {
-        case 0: return launch_serve_gfl<G, F, 0>(ix, a, sv, waves, st);
-        case 1: return launch_serve_gfl<G, F, 1>(ix, a, sv, waves, st);
-        case 2: return launch_serve_gfl<G, F, 2>(ix, a, sv, waves, st);
-        default: return launch_serve_gfl<G, F, 3>(ix, a, sv, waves, st);
+        case 0: return launch_serve_gfl<G, F, GB, FB, G8, F8, 0>(ix, a, sv, waves, st);
+        case 1: return launch_serve_gfl<G, F, GB, FB, G8, F8, 1>(ix, a, sv, waves, st);
+        case 2: return launch_serve_gfl<G, F, GB, FB, G8, F8, 2>(ix, a, sv, waves, st);
+        default: return launch_serve_gfl<G, F, GB, FB, G8, F8, 3>(ix, a, sv, waves, st);
     }
 }
 
@@ -155,15 +157,17 @@ hipError_t launch_serve_gf(const DevIndex &ix, const SearchArgs &a, const ServeA
 
 hipError_t launch_serve(const DevIndex &ix, const SearchArgs &a, const ServeArgs &sv, uint32_t waves,
                         hipStream_t st) {
-    // one tile shape must serve every mode: the fp32 shape of the dimension
+    // The fp32 shape of the dimension selects the kernel; within each fp32
+    // shape's range of dimensions the BF16 and FP8 shapes below hold every
+    // coordinate (8 and 16 values per piece), as the batch kernels' shapes do.
     const TileShape t = tile_for(kF32, ix.dim);
     switch (t.G * 16 + t.F) {
-        case 1 * 16 + 1: return launch_serve_gf<1, 1>(ix, a, sv, waves, st);
-        case 2 * 16 + 2: return launch_serve_gf<2, 2>(ix, a, sv, waves, st);
-        case 4 * 16 + 2: return launch_serve_gf<4, 2>(ix, a, sv, waves, st);
-        case 8 * 16 + 2: return launch_serve_gf<8, 2>(ix, a, sv, waves, st);
-        case 16 * 16 + 2: return launch_serve_gf<16, 2>(ix, a, sv, waves, st);
-        default: return launch_serve_gf<16, 4>(ix, a, sv, waves, st);
+        case 1 * 16 + 1: return launch_serve_gf<1, 1, 1, 1, 1, 1>(ix, a, sv, waves, st);     // d <= 4
+        case 2 * 16 + 2: return launch_serve_gf<2, 2, 2, 1, 1, 1>(ix, a, sv, waves, st);     // d <= 16
+        case 4 * 16 + 2: return launch_serve_gf<4, 2, 4, 1, 2, 1>(ix, a, sv, waves, st);     // d <= 32
+        case 8 * 16 + 2: return launch_serve_gf<8, 2, 8, 1, 4, 1>(ix, a, sv, waves, st);     // d <= 64
+        case 16 * 16 + 2: return launch_serve_gf<16, 2, 16, 1, 8, 1>(ix, a, sv, waves, st);  // d <= 128
+        default: return launch_serve_gf<16, 4, 16, 2, 16, 1>(ix, a, sv, waves, st);          // d <= 256
     }
 }
 

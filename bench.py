@@ -240,15 +240,18 @@ class Runner:
 # main index's kernel (plain, learned, BF16 and FP8 inlined) holds two waves
 # per SIMD by its registers, and at ef_max = 512 a wave reserves 13.3 KB of
 # LDS; 512 + 1024 waves fit together.
-def serve_bench(hnsw, index, Q, mlp, rates=(50_000, 100_000, 200_000, 500_000), n_req=20_000, seed=7):
+def serve_bench(hnsw, index, Q, mlp, rates=(50_000, 100_000, 200_000, 500_000), duration_s=2.5, warmup_s=0.5,
+                seed=7):
     """Continuous-batching serving: an open-loop Poisson replay over two live
     servers, the main index (plain, learned when a net is loaded, BF16 and
     FP8 requests) and a 1M x 4 uniform index (built by the oracle, file
     graphs/uniform4_1M.bin; plain and BF16); per request K in {1, 10, 100}, ef
-    uniform in [K, 512].  Returns, per arrival rate, p50/p99 latency (arrival
-    to completion), completed requests per second, and the occupancy of the
-    request slots (requests in flight between submission and completion:
-    mean, p99 and peak, against the 4,096 slots of each server)."""
+    uniform in [K, 512].  Each rate runs duration_s of arrivals; the
+    statistics cover the requests that arrive after warmup_s (the steady
+    state): p50/p99 latency (arrival to completion), completed requests per
+    second, and the occupancy of the request slots (requests in flight between
+    submission and completion: mean, p99 and peak, against the 4,096 slots of
+    each server)."""
     import synthdata
 
     upath = os.path.join(ROOT, WORKLOADS["uniform4"][0])
@@ -273,12 +276,13 @@ def serve_bench(hnsw, index, Q, mlp, rates=(50_000, 100_000, 200_000, 500_000), 
         if idx4 is not None:
             servers.append(hnsw.Server(idx4, mlp=None, slots=slots, waves=1024, ef_max=512, k_max=100,
                                        budget_s=120.0))
+        n_req = int(rate * duration_s)
         try:
             arrival = np.cumsum(rng.exponential(1.0 / rate, n_req))
             server_of = rng.integers(0, len(servers), n_req).astype(np.uint32)
             qidx = rng.integers(0, len(Q), n_req).astype(np.uint32)
             k = rng.choice([1, 10, 100], n_req).astype(np.uint32)
-            ef = np.array([rng.integers(kk, 513) for kk in k], dtype=np.uint32)
+            ef = rng.integers(k.astype(np.int64), 513).astype(np.uint32)
             modes = [0, 1, 2, 3] if mlp is not None else [0, 1, 2]
             mode = rng.choice(modes, n_req).astype(np.int32)
             mode[(mode == 3) & ((k > 64) | (server_of == 1))] = 0
@@ -289,14 +293,17 @@ def serve_bench(hnsw, index, Q, mlp, rates=(50_000, 100_000, 200_000, 500_000), 
         finally:
             for sv in servers:
                 sv.stop()
-        lat = (r["t_done"] - arrival) * 1e3
-        span = float(r["t_done"].max() - arrival[0])
-        # requests in flight at each submission and completion instant
+        steady = arrival >= warmup_s
+        lat = (r["t_done"][steady] - arrival[steady]) * 1e3
+        ns = int(steady.sum())
+        span = float(r["t_done"][steady].max() - arrival[steady][0])
+        # requests in flight at each submission and completion instant (of the steady window)
         ev = np.concatenate([np.stack([r["t_submit"], np.ones(n_req)], 1), np.stack([r["t_done"], -np.ones(n_req)], 1)])
         ev = ev[np.lexsort((ev[:, 1], ev[:, 0]))]
-        inflight = np.cumsum(ev[:, 1])
-        row = {"offered_rps": rate, "requests": n_req, "p50_ms": round(float(np.percentile(lat, 50)), 3),
-               "p99_ms": round(float(np.percentile(lat, 99)), 3), "completed_rps": round(n_req / span, 1),
+        inflight = np.cumsum(ev[:, 1])[ev[:, 0] >= warmup_s]
+        row = {"offered_rps": rate, "requests": n_req, "steady_requests": ns, "steady_s": round(duration_s - warmup_s, 2),
+               "p50_ms": round(float(np.percentile(lat, 50)), 3),
+               "p99_ms": round(float(np.percentile(lat, 99)), 3), "completed_rps": round(ns / span, 1),
                "in_flight_mean": round(float(np.mean(inflight)), 1),
                "in_flight_p99": round(float(np.percentile(inflight, 99)), 1),
                "in_flight_max": int(inflight.max()), "slots": slots * len(servers)}
@@ -310,13 +317,42 @@ def serve_bench(hnsw, index, Q, mlp, rates=(50_000, 100_000, 200_000, 500_000), 
             "rates": out}
 
 
+def read_probe_bench(hnsw, gib=4, steps=10, warmup=3):
+    """The attainable HBM read bandwidth: the library's streaming-read probe
+    (16-byte loads, grid-stride) over `gib` GiB, timed with events (median of
+    `steps`), at the best of several grid sizes."""
+    import torch
+
+    buf = torch.ones(gib << 28, dtype=torch.float32, device="cuda")
+    nbytes = buf.numel() * 4
+    stream = torch.cuda.current_stream()
+    best = None
+    for blocks in (2048, 8192, 16384, 32768, 65536):
+        for _ in range(warmup):
+            hnsw.read_probe(buf, blocks)
+        ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(steps)]
+        for a, b in ev:
+            a.record(stream)
+            hnsw.read_probe(buf, blocks)
+            b.record(stream)
+        torch.cuda.synchronize()
+        ms = float(np.median([a.elapsed_time(b) for a, b in ev]))
+        gbs = nbytes / (ms / 1e3) / 1e9
+        log(f"[probe] {blocks} blocks: {ms:.3f} ms, {gbs:.1f} GB/s")
+        if best is None or gbs > best["GBs"]:
+            best = {"GBs": round(gbs, 1), "blocks": blocks, "bytes": nbytes, "ms": round(ms, 4)}
+    del buf
+    return best
+
+
 def learned_glove_bench(hnsw, steps=10, warmup=2, target=0.95, batches=(10_000, 100_000)):
     """The learned stop rule on glove_like 1.2M x 100 (inner product) with the
     net trained and calibrated for it: plain and learned are each timed at the
     smallest ef of a grid of step 16 that reaches recall@10 >= 0.95.  Two
     batch sizes: the 10,000 test queries in one call, and 100,000 queries of
     the same law in one call (a batch long enough that its last, longest
-    searches are a small part of it)."""
+    searches are a small part of it).  recall_histogram[j]: the queries that
+    found j of their K nearest."""
     import torch
 
     import synthdata
@@ -343,14 +379,18 @@ def learned_glove_bench(hnsw, steps=10, warmup=2, target=0.95, batches=(10_000, 
         res = {"queries": nq}
         for form, mode in (("plain", 0), ("learned", 3)):
             ef, rec, _ = run.sweep(mode, efs, target)
-            _, _, cnt = run.search(ef, mode, counters=True)
+            ids, _, cnt = run.search(ef, mode, counters=True)
             torch.cuda.synchronize()
             c = cnt.cpu().numpy().astype(np.float64)
+            # per-query recall@K: how many queries found 0, 1, ..., K of their K nearest
+            per_q = recall(ids.cpu().numpy(), X, Q, gt.cpu().numpy(), g["metric"])
+            hist = np.bincount(np.rint(per_q * K).astype(np.int64), minlength=K + 1)
             ms, kern_ms = run.time(ef, mode, steps, warmup)
             res[form] = {"ef": ef, "recall": round(rec, 5), "qps": round(nq / (ms / 1000.0), 1),
                          "ms_per_batch": round(ms, 4), "kernel_ms": round(kern_ms, 4),
                          "layer0_expansions_per_query": round(float(c[:, 3].mean()), 2),
-                         "distance_evals_per_query": round(float(c[:, 0].mean()), 1)}
+                         "distance_evals_per_query": round(float(c[:, 0].mean()), 1),
+                         "recall_histogram": [int(v) for v in hist]}
             log(f"[glove] {nq} queries, {form}: {res[form]}")
         res["learned_vs_plain_qps"] = round(res["learned"]["qps"] / res["plain"]["qps"], 4)
         out[f"batch_{nq}"] = res
@@ -810,6 +850,8 @@ def main():
             r["algorithmic_GBs"] = r["gpu_count_GBs"]
     khash = kernel_source_hash()
     achieved = head["algorithmic_GBs"]
+    # the attainable read bandwidth (not with --ef, which times one ef only)
+    probe = None if a.ef else read_probe_bench(hnsw)
     traffic = load_traffic(khash, a.workload, head["ef"])
     out = {
         "metric": METRIC,
@@ -839,7 +881,9 @@ def main():
                                 else "search call: search_kernel (one launch, event-timed)"),
                      "kernel_ms": head["kernel_ms"],
                      "algorithmic_bytes_per_launch": head["bytes_per_step"], "counts": counts,
-                     "kernel_hash": khash},
+                     "kernel_hash": khash,
+                     "attainable_read": probe,
+                     "frac_of_attainable_read": round(achieved / probe["GBs"], 4) if probe else None},
         "forms": results,
         "plain_k1": k1,
         "recall_qps_curve": curves,

@@ -270,6 +270,17 @@ hnsw_status hnsw_bruteforce_knn(const hnsw_index *index, const float *queries, u
                                 int32_t *ids_out, double *dists_out, void *stream);
 
 /*
+ * Measurement aid, not part of the search path: streams `bytes` of device
+ * memory at `buf` with 16-byte loads, `blocks` workgroups of 256 threads in a
+ * grid-stride loop, and writes the XOR of every 32-bit word each block read to
+ * out[block] (device, `blocks` words), so that no load is dropped.  Its time
+ * gives the attainable read bandwidth against which the search's algorithmic
+ * bytes are also reported.  buf 16-byte aligned, bytes a multiple of 16,
+ * 1 <= blocks <= 65,536.  Asynchronous on `stream`.
+ */
+hnsw_status hnsw_read_probe(const void *buf, uint64_t bytes, uint32_t *out, uint32_t blocks, void *stream);
+
+/*
  * Add a low-precision copy of the vector store for HNSW_MODE_BF16 /
  * HNSW_MODE_FP8 / HNSW_MODE_U8 searches (quantised on the device from the
  * fp32 rows; the call synchronises `stream`).  BF16: round to nearest even.

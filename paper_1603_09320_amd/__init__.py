@@ -65,6 +65,7 @@ SIGNATURES = {
     "hnsw_search_batch_ex": (C.c_int, [_vp, _vp, _u32, _u32, _u32, _i32, _vp, _vp, _vp, _vp, _vp]),
     "hnsw_search_batch_noalloc": (C.c_int, [_vp, _vp, _u32, _u32, _u32, _i32, _vp, _vp, _vp, _vp, _vp]),
     "hnsw_bruteforce_knn": (C.c_int, [_vp, _vp, _u32, _u32, _vp, _vp, _vp]),
+    "hnsw_read_probe": (C.c_int, [_vp, _u64, _vp, _u32, _vp]),
     "hnsw_index_add_lowp": (C.c_int, [_vp, _i32, _vp]),
     "hnsw_index_read_lowp": (C.c_int, [_vp, _i32, _vp, _vp]),
     "hnsw_search_learned_trace": (C.c_int, [_vp, _vp, _u32, _u32, _u32, _vp, _vp, _vp, _vp, _vp, _vp]),
@@ -409,6 +410,17 @@ def replay(servers, queries, arrival_s, server_of, qidx, k, ef, mode, out_stride
     out = dict(t_submit=ts, t_done=td)
     if keep_results:
         out.update(ids=ids, dists=ds)
+    return out
+
+
+def read_probe(buf, blocks: int = 2048, stream=None):
+    """``hnsw_read_probe`` over a CUDA tensor (16-byte aligned, size a multiple of 16 bytes);
+    returns the per-block XOR words, int32 [blocks] on the device."""
+    import torch
+
+    out = torch.empty(blocks, dtype=torch.int32, device=buf.device)
+    _check("hnsw_read_probe", lib().hnsw_read_probe(_dptr(buf), buf.numel() * buf.element_size(), _dptr(out), blocks,
+                                                    _stream_ptr(stream)))
     return out
 
 

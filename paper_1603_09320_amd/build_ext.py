@@ -11,7 +11,7 @@ CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libhnsw_gpu.so")
 OBJ = os.path.join(HERE, "_build")
 SOURCES = ["api.hip", "search.hip", "search_wide.hip", "bruteforce.hip", "quantize.hip", "mlp.hip", "serve.hip",
-           "build.hip"]
+           "build.hip", "probe.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [
     "--offload-arch=gfx950",

@@ -341,3 +341,19 @@ def test_parity_sift_like_full_size_sampled(hnsw):
         assert (np.diff(ds, axis=1) >= 0).all()
         d64 = oracle.pair_dist(X, Q, ids)
         assert np.array_equal(d64.astype(np.float32), ds)
+
+
+def test_read_probe_reads_every_word(hnsw):
+    """The bandwidth probe folds every 32-bit word it reads: the XOR of its
+    per-block words equals the XOR of the buffer, for grids smaller and larger
+    than the buffer's 16-byte words (tail loop and unrolled loop)."""
+    rng = np.random.default_rng(5)
+    for words16 in (1, 37, 4096, 100_003):
+        h = rng.integers(0, 2**32, size=words16 * 4, dtype=np.uint64).astype(np.uint32)
+        buf = torch.from_numpy(h.view(np.int32)).cuda()
+        want = int(np.bitwise_xor.reduce(h))
+        for blocks in (1, 3, 64, 1024):
+            out = hnsw.read_probe(buf, blocks).cpu().numpy().view(np.uint32)
+            assert int(np.bitwise_xor.reduce(out)) == want, (words16, blocks)
+    with pytest.raises(hnsw.HnswError):
+        hnsw.read_probe(torch.zeros(3, dtype=torch.int32).cuda())  # 12 bytes: not a multiple of 16

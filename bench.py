@@ -883,7 +883,12 @@ def main():
                      "algorithmic_bytes_per_launch": head["bytes_per_step"], "counts": counts,
                      "kernel_hash": khash,
                      "attainable_read": probe,
-                     "frac_of_attainable_read": round(achieved / probe["GBs"], 4) if probe else None},
+                     # algorithmic bytes include hits in L2 and the Infinity Cache, so this can exceed 1
+                     "frac_of_attainable_read": round(achieved / probe["GBs"], 4) if probe else None,
+                     # the counted L2-to-fabric bytes over the same time, against the same probe
+                     "traffic_GBs": round(traffic / (head["kernel_ms"] / 1e3) / 1e9, 1) if traffic else None,
+                     "traffic_frac_of_attainable_read": (round(traffic / (head["kernel_ms"] / 1e3) / 1e9 / probe["GBs"], 4)
+                                                         if traffic and probe else None)},
         "forms": results,
         "plain_k1": k1,
         "recall_qps_curve": curves,

@@ -659,7 +659,7 @@ def main():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="sift_like", choices=sorted(WORKLOADS))
-    ap.add_argument("--ef", type=int, default=0, help="time this ef (plain form only) instead of sweeping")
+    ap.add_argument("--ef", type=int, default=0, help="time this ef for every form instead of sweeping")
     ap.add_argument("--forms", default="plain,bf16,fp8,u8,learned",
                     help="comma list of plain,bf16,fp8,u8,learned (learned needs a trained net file)")
     ap.add_argument("--target-recall", type=float, default=0.95)
@@ -740,8 +740,8 @@ def main():
             index.add_lowp(mode)
         if mode == 4:
             rerank_of[4] = not index.read_lowp(4)[1]  # an exact 8-bit copy needs no re-rank
-        if form == "plain" and a.ef:
-            ids, _ = run.search(a.ef, 0)
+        if a.ef:
+            ids, _ = run.search(a.ef, mode)
             torch.cuda.synchronize()
             ef, rec = a.ef, float(recall(ids.cpu().numpy(), X, Q, gt_d64, graph["metric"]).mean())
             curve = [{"ef": ef, "recall": round(rec, 5)}]

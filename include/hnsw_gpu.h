@@ -297,9 +297,10 @@ hnsw_status hnsw_index_add_lowp(hnsw_index *index, int kind, void *stream);
 
 /*
  * Layout and contents of a low-precision copy: layout[0] = bytes per row,
- * layout[1] = 16-byte pieces holding values, layout[2] = byte offset of the
- * FP8 row scale (0 for BF16; for U8, 1 when the copy is exact, else 0).
- * host_out (optional) receives the n rows, [n][layout[0]] bytes (synchronous
+ * layout[1] = 16-byte pieces holding values, layout[2] = for FP8 the byte
+ * offset in host_out of the row scales (n * layout[0]); 0 for BF16; for U8,
+ * 1 when the copy is exact, else 0.  host_out (optional) receives the n rows,
+ * [n][layout[0]] bytes, and for FP8 then the n fp32 row scales (synchronous
  * copy).
  */
 hnsw_status hnsw_index_read_lowp(const hnsw_index *index, int kind, void *host_out, uint64_t layout[3]);

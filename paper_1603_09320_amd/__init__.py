@@ -220,14 +220,16 @@ class Index:
         lay = np.zeros(3, dtype=np.uint64)
         _check("hnsw_index_read_lowp", lib().hnsw_index_read_lowp(self._h, kind, None, _np(lay)))
         row = int(lay[0])
-        raw = np.empty((self.n, row), dtype=np.uint8)
-        _check("hnsw_index_read_lowp", lib().hnsw_index_read_lowp(self._h, kind, _np(raw), _np(lay)))
+        extra = 4 * self.n if kind == MODE_FP8 else 0  # FP8: the row scales follow the rows
+        buf = np.empty(self.n * row + extra, dtype=np.uint8)
+        _check("hnsw_index_read_lowp", lib().hnsw_index_read_lowp(self._h, kind, _np(buf), _np(lay)))
+        raw = buf[:self.n * row].reshape(self.n, row)
         if kind == MODE_BF16:
             return raw.view(np.uint16)[:, :self.dim].copy(), np.ones(self.n, np.float32)
         if kind == MODE_U8:
             return raw[:, :self.dim].copy(), bool(lay[2])
         off = int(lay[2])
-        return raw[:, :self.dim].copy(), raw[:, off:off + 4].copy().view(np.float32)[:, 0]
+        return raw[:, :self.dim].copy(), buf[off:off + extra].copy().view(np.float32)
 
     def close(self):
         if getattr(self, "_h", None):

@@ -405,10 +405,13 @@ hnsw_status hnsw_index_add_lowp(hnsw_index *index, int kind, void *stream) {
         nx.u8_stride16 = (nx.u8_pieces + 3) & ~3u;
         bytes = (static_cast<size_t>(ix.n) + 1) * nx.u8_stride16 * 16;
     } else {
+        // rows padded to 64 bytes; the scale takes 4 bytes of a row's padding
+        // when there are any, else the n + 1 scales follow the rows
         nx.fp8_pieces = (ix.dim + 15) / 16;
-        nx.fp8_scale_off = nx.fp8_pieces * 16;
-        nx.fp8_stride16 = ((nx.fp8_scale_off + 4 + 63) / 64) * 4;
-        bytes = (static_cast<size_t>(ix.n) + 1) * nx.fp8_stride16 * 16;
+        nx.fp8_stride16 = (nx.fp8_pieces + 3) & ~3u;
+        const bool in_row = nx.fp8_stride16 > nx.fp8_pieces;
+        nx.fp8_scale_stride = in_row ? nx.fp8_stride16 * 16 : 4;
+        bytes = (static_cast<size_t>(ix.n) + 1) * (nx.fp8_stride16 * 16 + (in_row ? 0 : 4));
     }
     if (index->bytes + bytes > mem_cap()) return HNSW_ERR_OUT_OF_MEMORY;
     void *p = nullptr;
@@ -421,7 +424,13 @@ hnsw_status hnsw_index_add_lowp(hnsw_index *index, int kind, void *stream) {
     bool ok = hipMemsetAsync(p, 0, bytes, st) == hipSuccess;
     if (kind == HNSW_MODE_BF16) ok = ok && hnsw::launch_quantize_bf16(nx, static_cast<uint16_t *>(p), st) == hipSuccess;
     else if (kind == HNSW_MODE_U8) ok = ok && hnsw::launch_quantize_u8(nx, static_cast<uint8_t *>(p), flag, st) == hipSuccess;
-    else ok = ok && hnsw::launch_quantize_fp8(nx, static_cast<uint8_t *>(p), st) == hipSuccess;
+    else {
+        uint8_t *scale = static_cast<uint8_t *>(p) + (nx.fp8_scale_stride == 4
+                                                          ? (static_cast<size_t>(ix.n) + 1) * nx.fp8_stride16 * 16
+                                                          : static_cast<size_t>(nx.fp8_pieces) * 16);
+        nx.fp8_scale = scale;
+        ok = ok && hnsw::launch_quantize_fp8(nx, static_cast<uint8_t *>(p), scale, st) == hipSuccess;
+    }
     uint32_t inexact = 0;
     if (kind == HNSW_MODE_U8) {
         ok = ok && hipMemcpyAsync(&inexact, flag, 4, hipMemcpyDeviceToHost, st) == hipSuccess;
@@ -445,7 +454,8 @@ hnsw_status hnsw_index_add_lowp(hnsw_index *index, int kind, void *stream) {
         ix.vfp8 = static_cast<uint8_t *>(p);
         ix.fp8_stride16 = nx.fp8_stride16;
         ix.fp8_pieces = nx.fp8_pieces;
-        ix.fp8_scale_off = nx.fp8_scale_off;
+        ix.fp8_scale = nx.fp8_scale;
+        ix.fp8_scale_stride = nx.fp8_scale_stride;
     }
     index->allocations.push_back(p);
     index->bytes += bytes;
@@ -465,9 +475,13 @@ hnsw_status hnsw_index_read_lowp(const hnsw_index *index, int kind, void *host_o
                                                 : ix.fp8_stride16 * 16ull;
     layout[0] = row;
     layout[1] = kind == HNSW_MODE_BF16 ? ix.bf16_stride16 : (kind == HNSW_MODE_U8 ? ix.u8_pieces : ix.fp8_pieces);
-    layout[2] = kind == HNSW_MODE_FP8 ? ix.fp8_scale_off : (kind == HNSW_MODE_U8 ? ix.u8_exact : 0);
+    layout[2] = kind == HNSW_MODE_FP8 ? row * ix.n : (kind == HNSW_MODE_U8 ? ix.u8_exact : 0);
     if (!host_out) return HNSW_OK;
-    if (hipMemcpy(host_out, src, row * ix.n, hipMemcpyDeviceToHost) != hipSuccess) {
+    bool ok = hipMemcpy(host_out, src, row * ix.n, hipMemcpyDeviceToHost) == hipSuccess;
+    if (kind == HNSW_MODE_FP8)
+        ok = ok && hipMemcpy2D(static_cast<uint8_t *>(host_out) + row * ix.n, 4, ix.fp8_scale, ix.fp8_scale_stride,
+                               4, ix.n, hipMemcpyDeviceToHost) == hipSuccess;
+    if (!ok) {
         (void)hipGetLastError();
         return HNSW_ERR_DEVICE;
     }

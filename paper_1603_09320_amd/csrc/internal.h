@@ -24,7 +24,8 @@ struct DevIndex {
     uint32_t bf16_stride16;  // 16-byte pieces per BF16 row
     uint32_t fp8_stride16;   // 16-byte pieces per FP8 row (values, scale, padding)
     uint32_t fp8_pieces;     // pieces of an FP8 row that hold values
-    uint32_t fp8_scale_off;  // byte offset of the row's fp32 scale
+    const uint8_t *fp8_scale;   // fp32 scale of FP8 row i at fp8_scale + i * fp8_scale_stride (row n: 0)
+    uint32_t fp8_scale_stride;  // row bytes (scale in the row's padding) or 4 (an array after the rows)
     uint32_t u8_stride16;    // 16-byte pieces per 8-bit row (values, padding)
     uint32_t u8_pieces;      // pieces of an 8-bit row that hold values
     uint32_t u8_exact;       // every coordinate is an integer in [0, 255]: the copy equals the fp32 store
@@ -86,7 +87,7 @@ hipError_t launch_adam(float *P, const float *G, float *M, float *V, uint32_t np
 
 // Quantisation of the fp32 store into the low-precision copies.
 hipError_t launch_quantize_bf16(const DevIndex &ix, uint16_t *out, hipStream_t stream);
-hipError_t launch_quantize_fp8(const DevIndex &ix, uint8_t *out, hipStream_t stream);
+hipError_t launch_quantize_fp8(const DevIndex &ix, uint8_t *out, uint8_t *scale, hipStream_t stream);
 // 8-bit integer copy: code = x rounded to the nearest integer (ties to even),
 // clamped to [0, 255]; *inexact (device) is set when some code differs from x.
 hipError_t launch_quantize_u8(const DevIndex &ix, uint8_t *out, uint32_t *inexact, hipStream_t stream);

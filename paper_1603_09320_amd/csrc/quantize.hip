@@ -46,7 +46,7 @@ __global__ void quantize_bf16_kernel(DevIndex ix, uint16_t *out) {
     for (uint32_t j = 0; j < ix.bf16_stride16 * 8; ++j) o[j] = j < ix.dim ? to_bf16(x[j]) : 0;
 }
 
-__global__ void quantize_fp8_kernel(DevIndex ix, uint8_t *out) {
+__global__ void quantize_fp8_kernel(DevIndex ix, uint8_t *out, uint8_t *scale) {
     const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= ix.n) return;
     const float *x = ix.vec + static_cast<size_t>(i) * ix.stride4 * 4;
@@ -55,7 +55,7 @@ __global__ void quantize_fp8_kernel(DevIndex ix, uint8_t *out) {
     for (uint32_t j = 0; j < ix.dim; ++j) mx = fmaxf(mx, fabsf(x[j]));
     const float s = mx > 0.0f ? mx / 448.0f : 1.0f;
     for (uint32_t j = 0; j < ix.fp8_pieces * 16; ++j) o[j] = j < ix.dim ? to_e4m3(x[j] / s) : 0;
-    *reinterpret_cast<float *>(o + ix.fp8_scale_off) = s;
+    *reinterpret_cast<float *>(scale + static_cast<size_t>(i) * ix.fp8_scale_stride) = s;
 }
 
 __global__ void quantize_u8_kernel(DevIndex ix, uint8_t *out, uint32_t *inexact) {
@@ -88,8 +88,8 @@ hipError_t launch_quantize_bf16(const DevIndex &ix, uint16_t *out, hipStream_t s
     return hipGetLastError();
 }
 
-hipError_t launch_quantize_fp8(const DevIndex &ix, uint8_t *out, hipStream_t stream) {
-    hipLaunchKernelGGL(quantize_fp8_kernel, dim3((ix.n + 255) / 256), dim3(256), 0, stream, ix, out);
+hipError_t launch_quantize_fp8(const DevIndex &ix, uint8_t *out, uint8_t *scale, hipStream_t stream) {
+    hipLaunchKernelGGL(quantize_fp8_kernel, dim3((ix.n + 255) / 256), dim3(256), 0, stream, ix, out, scale);
     return hipGetLastError();
 }
 

@@ -201,7 +201,9 @@ __device__ __forceinline__ double group_sum(double v) {
 
 // Vector stores the traversal can read.  A row is a sequence of 16-byte
 // pieces: 4 fp32, 8 bf16, 16 fp8-E4M3 or 16 unsigned 8-bit integer values;
-// the FP8 row carries its fp32 scale at byte offset lp_scale_off.  kU8E is
+// an FP8 row's fp32 scale sits in the row's padding when the codes leave 4
+// bytes before the next 64-byte boundary, else in an array after the rows (a
+// d = 128 row stays 128 bytes, two 64-byte requests, not three).  kU8E is
 // the 8-bit store when it equals the fp32 one (integer data in [0, 255]): its
 // distances are the fp32 ones, so its kernels carry no re-rank (and, without
 // the re-rank's registers, hold six waves per SIMD).
@@ -276,8 +278,9 @@ __device__ __forceinline__ void load_query(const float *qrow, uint32_t dim, Quer
 struct RowSource {
     const uint4 *base;   // piece 0 of row 0
     uint32_t stride;     // pieces per row
-    uint32_t pieces;     // pieces holding values (the rest of the row is padding/scale)
-    uint32_t scale_off;  // FP8: byte offset of the scale within the row
+    uint32_t pieces;     // pieces holding values (the rest of the row is padding)
+    const uint8_t *scale;   // FP8: scale of row i at scale + i * scale_stride, else null
+    uint32_t scale_stride;
     __amdgpu_buffer_rsrc_t rsrc;  // raw buffer over the store (buffered kernels: the store spans <= 2 GiB)
 };
 
@@ -289,12 +292,13 @@ constexpr int kBufferDword3 = 0x00020000;
 constexpr uint64_t kBufferedMaxBytes = 1ull << 31;
 
 __device__ __forceinline__ RowSource make_source(const void *base, uint32_t stride, uint32_t pieces,
-                                                 uint32_t scale_off, uint32_t n) {
+                                                 const uint8_t *scale, uint32_t scale_stride, uint32_t n) {
     RowSource r;
     r.base = reinterpret_cast<const uint4 *>(base);
     r.stride = stride;
     r.pieces = pieces;
-    r.scale_off = scale_off;
+    r.scale = scale;
+    r.scale_stride = scale_stride;
     const uint64_t bytes = (static_cast<uint64_t>(n) + 1) * stride * 16;
     r.rsrc = __builtin_amdgcn_make_buffer_rsrc(const_cast<void *>(base), 0,
                                                static_cast<int>(bytes <= kBufferedMaxBytes ? bytes : 0), kBufferDword3);
@@ -302,10 +306,14 @@ __device__ __forceinline__ RowSource make_source(const void *base, uint32_t stri
 }
 
 __device__ __forceinline__ RowSource rows_of(const DevIndex &ix, const SearchArgs &a, int kind) {
-    if (kind == kF32) return make_source(ix.vec, ix.stride4, ix.stride4, 0, ix.n);
-    if (kind == kBF16) return make_source(ix.vbf16, ix.bf16_stride16, ix.bf16_stride16, 0, ix.n);
-    if (kind == kU8 || kind == kU8E) return make_source(ix.vu8, ix.u8_stride16, ix.u8_pieces, 0, ix.n);
-    return make_source(ix.vfp8, ix.fp8_stride16, ix.fp8_pieces, ix.fp8_scale_off, ix.n);
+    if (kind == kF32) return make_source(ix.vec, ix.stride4, ix.stride4, nullptr, 0, ix.n);
+    if (kind == kBF16) return make_source(ix.vbf16, ix.bf16_stride16, ix.bf16_stride16, nullptr, 0, ix.n);
+    if (kind == kU8 || kind == kU8E) return make_source(ix.vu8, ix.u8_stride16, ix.u8_pieces, nullptr, 0, ix.n);
+    return make_source(ix.vfp8, ix.fp8_stride16, ix.fp8_pieces, ix.fp8_scale, ix.fp8_scale_stride, ix.n);
+}
+
+__device__ __forceinline__ float row_scale(const RowSource &src, uint32_t id) {
+    return *reinterpret_cast<const float *>(src.scale + static_cast<size_t>(id) * src.scale_stride);
 }
 
 // Scores ids[0..m) against the query; keys[slot] receives the key of ids[slot].
@@ -357,8 +365,7 @@ __device__ __forceinline__ void score_ids(const DevIndex &ix, const RowSource &s
                     const auto w = __builtin_amdgcn_raw_buffer_load_b128(src.rsrc, roff + coff[f], 0, 0);
                     v[b][f] = make_uint4(w[0], w[1], w[2], w[3]);
                 }
-                if (KIND == kFP8)
-                    sc[b] = __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(src.rsrc, roff + src.scale_off, 0, 0));
+                if (KIND == kFP8) sc[b] = row_scale(src, idv[b]);
             }
         } else {
 #pragma unroll
@@ -370,9 +377,7 @@ __device__ __forceinline__ void score_ids(const DevIndex &ix, const RowSource &s
                     const uint32_t c = static_cast<uint32_t>(sub + f * G);
                     v[b][f] = src.base[c < src.pieces ? row + c : zero_row];
                 }
-                if (KIND == kFP8)
-                    sc[b] = *reinterpret_cast<const float *>(reinterpret_cast<const uint8_t *>(src.base + row) +
-                                                             src.scale_off);
+                if (KIND == kFP8) sc[b] = row_scale(src, idv[b]);
             }
         }
 #pragma unroll

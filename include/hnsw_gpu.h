@@ -234,9 +234,9 @@ hnsw_status hnsw_search_batch_ex(const hnsw_index *index, const float *queries, 
 /*
  * hnsw_search_batch_ex for callers that cannot allocate (code under HIP graph
  * capture, tight serving loops, harnesses that forbid allocation): the same
- * kernels, results and counters, but the scheduled form's workspace (20 bytes
+ * kernels, results and counters, but the scheduled form's workspace (24 bytes
  * per query) is a static device array of the library, sized for
- * HNSW_NOALLOC_MAX_QUERIES queries (5 MiB), which every device the library
+ * HNSW_NOALLOC_MAX_QUERIES queries (6 MiB), which every device the library
  * runs on holds until the process ends; no device or host memory is
  * allocated and no timing event is created (the form is the one
  * hnsw_search_batch_ex has already measured for this index, mode, ef and

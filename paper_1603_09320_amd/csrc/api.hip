@@ -259,6 +259,7 @@ hnsw_status hnsw_index_upload(const hnsw_graph_desc *g, void *stream, hnsw_index
     ix.Mmax0 = g->Mmax0;
     ix.entry = g->entry_point;
     ix.max_level = g->max_level;
+    ix.cell_level = hnsw::cell_level_of(g->levels, g->n, g->max_level);
     ix.metric = g->metric;
     ix.uid = hnsw::next_index_uid();
     ok = ok && hnsw::launch_row_norms(ix, xnorm, st) == hipSuccess;

@@ -901,6 +901,7 @@ hnsw_status hnsw_index_build(const float *vectors, uint32_t n, uint32_t dim, int
     }
     ix.entry = entry;
     ix.max_level = top;
+    ix.cell_level = cell_level_of(lv.data(), n, top);
     ix.uid = next_index_uid();
     ok = ok && launch_row_norms(ix, xnorm, st) == hipSuccess;
     ok = ok && hipStreamSynchronize(st) == hipSuccess;

@@ -31,6 +31,7 @@ struct DevIndex {
     uint32_t u8_exact;       // every coordinate is an integer in [0, 255]: the copy equals the fp32 store
     uint32_t n, dim, dv4, stride4;
     uint32_t Mmax, Mmax0, entry, max_level, metric;
+    uint32_t cell_level;  // layer whose greedy result groups a batch's queries on the XCDs (cell_level_of)
     uint32_t uid;  // identifies the index among those uploaded by this process (host bookkeeping only)
 };
 
@@ -66,6 +67,7 @@ struct SearchArgs {
     uint64_t *sched_start;   // [nq] key of each query's layer-0 entry
     uint32_t *sched_up;      // [nq][2] distance evaluations and expansions above layer 0
     uint32_t *sched_order;   // [nq] query of each layer-0 wave
+    uint32_t *sched_cell;    // [nq] node each query's descent reached on layer ix.cell_level
     int sched;               // 0: one kernel; 1: scheduled when the batch exceeds the resident waves; 2: always
     bool no_alloc;           // the caller cannot allocate: workspace from the static scratch array, no timing events
 };
@@ -108,6 +110,11 @@ bool tuned_form(const DevIndex &ix, const SearchArgs &a, hipStream_t stream, hip
 void forget_index(uint32_t uid);
 // Next index identifier (never 0).
 uint32_t next_index_uid();
+// The highest layer >= 1 that holds at least kCellMin nodes (1 if none does,
+// 0 for a single-layer graph): its nodes split the space into cells that are
+// few enough to group a batch's queries and many enough to spread over the XCDs.
+constexpr uint32_t kCellMin = 256;
+uint32_t cell_level_of(const uint8_t *levels, uint32_t n, uint32_t max_level);
 
 // Visited-table slots for a batch search: what the kernel's LDS share at its
 // target occupancy leaves, at least 1024 (the learned kernels 64 fewer).

@@ -96,13 +96,13 @@ bool stores_buffered(const DevIndex &ix) {
 namespace {
 
 // Workspace of the scheduled launches, one per (device, stream): kSchedBytes
-// per query (layer-0 entry key, the upper layers' counters, the order).  It
+// per query (layer-0 entry key, the upper layers' counters, the order, the cell).  It
 // grows to the largest batch seen on that stream and is kept until the
 // process ends.  Launches on one stream run in order, so a buffer is reused
 // only after the previous batch's kernels have read it; the mutex is held
 // while a batch's kernels are enqueued, so that batches submitted to one
 // stream from several threads do not interleave their launches.
-constexpr size_t kSchedBytes = 20;
+constexpr size_t kSchedBytes = 24;
 struct SchedBuf {
     int device;
     hipStream_t stream;
@@ -178,6 +178,18 @@ uint32_t next_index_uid() {
     uint32_t u = ++g_uid;
     if (u == 0) u = ++g_uid;
     return u;
+}
+
+uint32_t cell_level_of(const uint8_t *levels, uint32_t n, uint32_t max_level) {
+    if (max_level == 0) return 0;
+    std::vector<uint64_t> at(max_level + 2, 0);  // at[l]: nodes of level exactly l
+    for (uint32_t i = 0; i < n; ++i) ++at[levels[i] <= max_level ? levels[i] : max_level];
+    uint64_t above = 0;  // nodes of level >= l
+    for (uint32_t l = max_level; l >= 1; --l) {
+        above += at[l];
+        if (above >= kCellMin) return l;
+    }
+    return 1;
 }
 
 void forget_index(uint32_t uid) {
@@ -315,6 +327,7 @@ hipError_t launch_search(const DevIndex &ix, const SearchArgs &a0, hipStream_t s
     a.sched_start = nullptr;
     a.sched_up = nullptr;
     a.sched_order = nullptr;
+    a.sched_cell = nullptr;
     std::unique_lock<std::mutex> lk(g_sched_mu, std::defer_lock);
     if (a.sched == 2 || (a.sched == 1 && a.nq > 256)) {
         lk.lock();
@@ -331,6 +344,7 @@ hipError_t launch_search(const DevIndex &ix, const SearchArgs &a0, hipStream_t s
             a.sched_start = reinterpret_cast<uint64_t *>(p);
             a.sched_up = reinterpret_cast<uint32_t *>(p + n * 8);
             a.sched_order = reinterpret_cast<uint32_t *>(p + n * 16);
+            a.sched_cell = reinterpret_cast<uint32_t *>(p + n * 20);
         } else {
             a.sched = 0;
         }

@@ -806,6 +806,7 @@ __device__ __forceinline__ void sort_w(uint64_t *W, uint32_t n, uint32_t cap) {
 struct Descent {
     uint64_t cur;
     uint32_t n_dist, n_exp;
+    uint32_t cell;  // the node the walk reached on layer ix.cell_level (the entry point if that is 0)
 };
 
 // The first part of K-NN-SEARCH (Alg. 5): the entry point's distance, then a
@@ -815,7 +816,7 @@ template <int G, int F, int METRIC, int KIND, bool BUF>
 __device__ Descent descend(const DevIndex &ix, const RowSource &src, const QueryRegs<G, F, KIND> &Q,
                            const WaveLds &s) {
     const int lane = lane_id();
-    Descent d{0ull, 0u, 0u};
+    Descent d{0ull, 0u, 0u, ix.entry};
     if (lane == 0) s.ids[0] = ix.entry;
     wave_sync();
     score_ids<G, F, METRIC, KIND, BUF>(ix, src, Q, s.ids, 1, s.keys);
@@ -844,6 +845,7 @@ __device__ Descent descend(const DevIndex &ix, const RowSource &src, const Query
             if (best == cur) break;
             cur = best;
         }
+        if (lc == static_cast<int>(ix.cell_level)) d.cell = key_id(cur);
     }
     d.cur = cur;
     return d;

@@ -56,9 +56,12 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(6))) void se
 // expansions decides the end.  The scheduled form runs every query's descent
 // first (descent_kernel), then starts the layer-0 searches of the quarter of
 // queries whose descent ended farthest from them (their layer-0 searches tend
-// to be the longest) before the others (order_kernel, layer0_kernel).  Each
-// query's arithmetic is that of the one-kernel path; only the order in which
-// queries occupy the chip changes.
+// to be the longest) before the others (order_kernel, layer0_kernel).  It also
+// places queries whose descents passed through the same node of layer
+// ix.cell_level, which gather many of the same rows, on the same XCD at about
+// the same time, so that those rows come from that XCD's L2 rather than from
+// HBM.  Each query's arithmetic is that of the one-kernel path; only the order
+// in which queries occupy the chip changes.
 
 template <int G, int F, int METRIC, int KIND, bool BUF>
 __global__ __launch_bounds__(64) void descent_kernel(DevIndex ix, SearchArgs a) {
@@ -77,39 +80,40 @@ __global__ __launch_bounds__(64) void descent_kernel(DevIndex ix, SearchArgs a) 
         a.sched_start[qi] = d.cur;
         a.sched_up[2 * static_cast<size_t>(qi)] = d.n_dist;
         a.sched_up[2 * static_cast<size_t>(qi) + 1] = d.n_exp;
+        a.sched_cell[qi] = d.cell;
     }
 }
 
-// One workgroup of 1024 threads (16 waves).  The threshold is the distance
-// ranked at a quarter of a sample of at most 512 descents (every nq/ns-th
-// query, bitonic-sorted in LDS, largest first).  Queries at or above it go
-// first, in batch order, then the others, in batch order: a stable partition,
-// computed over rounds of 16 tiles of 1024 consecutive queries (thread t reads
-// query tile*1024 + t of each tile, so every load is coalesced and all 16 are
-// in flight together); a ballot per (tile, wave) counts the queries that go
-// first, an exclusive scan of those 256 counts gives each wave its base, and a
-// lane adds the flagged lanes below it.  A batch of one round keeps its flags
-// from the counting pass.
+// One workgroup of 1024 threads (16 waves).  The long queries are those whose
+// descent ended at or beyond the distance ranked at a quarter of a sample of
+// at most 512 descents (every nq/ns-th query, bitonic-sorted in LDS, largest
+// first).  A counting sort over 2 x kCellBins bins (the long queries' bins
+// first, then the others'; within each part, a hash of the query's cell)
+// ranks the batch.  Workgroups go to the kXcds XCDs round robin (block b runs
+// on XCD b % kXcds), so the long part and the rest are each cut into kXcds
+// consecutive runs of nearly equal size, and XCD x takes the x-th run of each,
+// its long run first: block kXcds * j + x gets the j-th query of XCD x's
+// sequence.  Each XCD thus receives a share of the long queries at the start
+// and queries from few cells at a time.  Queries that share a bin land in the
+// order of their atomics, which changes when the chip runs them, never what
+// they return.  Loads go in rounds of kOrderTiles tiles of 1024 consecutive
+// queries (thread t reads query tile * 1024 + t of each tile, coalesced, all
+// in flight together); a batch of one round keeps its bins in registers
+// between the counting and the placing pass.
 constexpr uint32_t kOrderThreads = 1024, kOrderSample = 512, kOrderTiles = 16;
+constexpr uint32_t kCellBinsLog2 = 10, kCellBins = 1u << kCellBinsLog2, kXcds = 8;
+static_assert(kCellBins == kOrderThreads, "the scan takes two bins per thread");
 
-__device__ __forceinline__ uint32_t wave_sum_u32(uint32_t v) {
-    v += dpp_u32<0xB1>(v);   // quad_perm [1,0,3,2]
-    v += dpp_u32<0x4E>(v);   // quad_perm [2,3,0,1]
-    v += dpp_u32<0x141>(v);  // row_half_mirror
-    v += dpp_u32<0x140>(v);  // row_mirror
-    return __builtin_amdgcn_readlane(v, 0) + __builtin_amdgcn_readlane(v, 16) + __builtin_amdgcn_readlane(v, 32) +
-           __builtin_amdgcn_readlane(v, 48);
-}
-
-__global__ __launch_bounds__(1024) void order_kernel(const uint64_t *start, uint32_t nq, uint32_t *order) {
+__global__ __launch_bounds__(1024) void order_kernel(const uint64_t *start, const uint32_t *cell, uint32_t nq,
+                                                     uint32_t *order) {
     __shared__ uint32_t samp[kOrderSample];
-    __shared__ uint32_t cnt[kOrderTiles * 16];
-    __shared__ uint32_t total_s, round_s;
+    __shared__ uint32_t bins[2 * kCellBins];
+    __shared__ uint32_t wsum[kOrderThreads / 64];
     const uint32_t t = threadIdx.x, lane = t & 63u, wv = t >> 6;
     const uint32_t *dist_bits = reinterpret_cast<const uint32_t *>(start) + 1;  // high word of each key
     const uint32_t ns = nq < kOrderSample ? nq : kOrderSample;
     if (t < kOrderSample) samp[t] = t < ns ? dist_bits[2 * (static_cast<uint64_t>(t) * nq / ns)] : 0u;
-    if (t == 0) total_s = 0u;
+    for (uint32_t i = t; i < 2 * kCellBins; i += kOrderThreads) bins[i] = 0u;
     __syncthreads();
     for (uint32_t k = 2; k <= kOrderSample; k <<= 1)
         for (uint32_t j = k >> 1; j > 0; j >>= 1) {
@@ -125,68 +129,76 @@ __global__ __launch_bounds__(1024) void order_kernel(const uint64_t *start, uint
             __syncthreads();
         }
     const uint32_t thr = samp[ns / 4];
-    // Bit i of the result: query r0 + i*1024 + t exists and goes first.  The
-    // loads read a clamped index unconditionally, so all 16 are in flight
-    // before the first comparison.
-    auto flags = [&](uint32_t r0) {
-        uint32_t hi[kOrderTiles];
-#pragma unroll
-        for (uint32_t i = 0; i < kOrderTiles; ++i) hi[i] = dist_bits[2 * min(r0 + i * kOrderThreads + t, nq - 1u)];
-        uint32_t fb = 0;
-#pragma unroll
-        for (uint32_t i = 0; i < kOrderTiles; ++i)
-            fb |= static_cast<uint32_t>(r0 + i * kOrderThreads + t < nq && hi[i] >= thr) << i;
-        return fb;
-    };
-    constexpr uint32_t kRound = kOrderTiles * kOrderThreads;
-    // the number of queries that go first (the others start after them)
-    const uint32_t fb0 = flags(0);
-    uint32_t mine = __popc(fb0);
-    for (uint32_t r0 = kRound; r0 < nq; r0 += kRound) mine += __popc(flags(r0));
-    mine = wave_sum_u32(mine);
-    if (lane == 0) atomicAdd(&total_s, mine);
-    __syncthreads();
-    const uint32_t total = total_s;
-    uint32_t fbase = 0;  // queries that go first among those before this round
-    for (uint32_t r0 = 0; r0 < nq; r0 += kRound) {
-        const uint32_t fb = r0 == 0 ? fb0 : flags(r0);
+    // bin of query r0 + i * 1024 + t (clamped loads, all in flight first)
+    auto bins_of = [&](uint32_t r0, uint32_t (&b)[kOrderTiles]) {
+        uint32_t hi[kOrderTiles], c[kOrderTiles];
 #pragma unroll
         for (uint32_t i = 0; i < kOrderTiles; ++i) {
-            const uint64_t bm = __ballot((fb >> i) & 1u);
-            if (lane == 0) cnt[i * 16 + wv] = static_cast<uint32_t>(__popcll(bm));
+            const uint32_t q = min(r0 + i * kOrderThreads + t, nq - 1u);
+            hi[i] = dist_bits[2 * static_cast<size_t>(q)];
+            c[i] = cell[q];
         }
-        __syncthreads();
-        if (wv == 0) {
-            // exclusive scan of cnt[0..256) in (tile, wave) order: 4 per lane
-            uint32_t v[4], run = 0;
 #pragma unroll
-            for (int e = 0; e < 4; ++e) {
-                v[e] = run;
-                run += cnt[4 * lane + e];
-            }
-            uint32_t incl = run;
+        for (uint32_t i = 0; i < kOrderTiles; ++i)
+            b[i] = (hi[i] >= thr ? 0u : kCellBins) + ((c[i] * 0x9E3779B1u) >> (32 - kCellBinsLog2));
+    };
+    constexpr uint32_t kRound = kOrderTiles * kOrderThreads;
+    uint32_t b[kOrderTiles];
+    for (uint32_t r0 = 0; r0 < nq; r0 += kRound) {
+        bins_of(r0, b);
 #pragma unroll
-            for (int o = 1; o < 64; o <<= 1) {
-                const uint32_t y = __shfl_up(incl, o, 64);
-                if (lane >= static_cast<uint32_t>(o)) incl += y;
-            }
-            const uint32_t excl = incl - run;
+        for (uint32_t i = 0; i < kOrderTiles; ++i)
+            if (r0 + i * kOrderThreads + t < nq) atomicAdd(&bins[b[i]], 1u);
+    }
+    __syncthreads();
+    // exclusive scan of the 2048 bin counts, two per thread
+    const uint32_t c0 = bins[2 * t], c1 = bins[2 * t + 1];
+    uint32_t incl = c0 + c1;
 #pragma unroll
-            for (int e = 0; e < 4; ++e) cnt[4 * lane + e] = excl + v[e];
-            if (lane == 63) round_s = incl;
-        }
-        __syncthreads();
+    for (int o = 1; o < 64; o <<= 1) {
+        const uint32_t y = __shfl_up(incl, o, 64);
+        if (lane >= static_cast<uint32_t>(o)) incl += y;
+    }
+    if (lane == 63) wsum[wv] = incl;
+    __syncthreads();
+    uint32_t base = incl - (c0 + c1);
+    for (uint32_t w = 0; w < wv; ++w) base += wsum[w];
+    bins[2 * t] = base;
+    bins[2 * t + 1] = base + c0;
+    __syncthreads();
+    const uint32_t nl = bins[kCellBins];  // queries in the long part
+    __syncthreads();                      // read before the placing atomics move it
+    // XCD x's sequence: la + (x < lb) long queries, then ca + (x < cb) in all
+    const uint32_t la = nl / kXcds, lb = nl % kXcds, ca = nq / kXcds, cb = nq % kXcds;
+    for (uint32_t r0 = 0; r0 < nq; r0 += kRound) {
+        if (nq > kRound) bins_of(r0, b);  // else b still holds the only round's bins
 #pragma unroll
         for (uint32_t i = 0; i < kOrderTiles; ++i) {
             const uint32_t q = r0 + i * kOrderThreads + t;
-            const bool f = (fb >> i) & 1u;
-            const uint64_t bm = __ballot(f);
-            const uint32_t below = static_cast<uint32_t>(__popcll(bm & ((1ull << lane) - 1ull)));
-            const uint32_t fr = fbase + cnt[i * 16 + wv] + below;  // queries going first before q
-            if (q < nq) order[f ? fr : total + q - fr] = q;
+            if (q >= nq) continue;
+            const uint32_t r = atomicAdd(&bins[b[i]], 1u);  // rank in the sorted batch
+            uint32_t x, j;
+            if (r < nl) {
+                // runs of la + 1 for the first lb XCDs, then runs of la
+                const uint32_t big = lb * (la + 1);
+                if (r < big) {
+                    x = r / (la + 1);
+                    j = r % (la + 1);
+                } else {
+                    x = lb + (r - big) / la;  // la > 0 here: r < nl = lb when la == 0
+                    j = (r - big) % la;
+                }
+            } else {
+                uint32_t rest = r - nl;
+                x = 0;
+                while (x + 1 < kXcds && rest >= ca + (x < cb) - (la + (x < lb))) {
+                    rest -= ca + (x < cb) - (la + (x < lb));
+                    ++x;
+                }
+                j = la + (x < lb) + rest;
+            }
+            order[kXcds * j + x] = q;
         }
-        fbase += round_s;
-        __syncthreads();  // cnt and round_s are rewritten by the next round
     }
 }
 
@@ -232,7 +244,8 @@ hipError_t launch_form(const DevIndex &ix, const SearchArgs &a, hipStream_t stre
         return hipGetLastError();
     }
     hipLaunchKernelGGL((descent_kernel<G, F, METRIC, KIND, BUF>), dim3(a.nq), dim3(64), 0, stream, ix, a);
-    hipLaunchKernelGGL(order_kernel, dim3(1), dim3(kOrderThreads), 0, stream, a.sched_start, a.nq, a.sched_order);
+    hipLaunchKernelGGL(order_kernel, dim3(1), dim3(kOrderThreads), 0, stream, a.sched_start, a.sched_cell, a.nq,
+                       a.sched_order);
     if (learned)
         hipLaunchKernelGGL((layer0_kernel_learned<G, F, METRIC, BUF>), dim3(a.nq), dim3(64), lds, stream, ix, a);
     else

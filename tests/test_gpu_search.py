@@ -343,6 +343,29 @@ def test_parity_sift_like_full_size_sampled(hnsw):
         assert np.array_equal(d64.astype(np.float32), ds)
 
 
+
+def test_scheduled_order_full_size_two_rounds(hnsw, monkeypatch):
+    """The scheduled form on the 1M x 128 graph with 20,000 queries: the order
+    kernel's two 16,384-query rounds, queries grouped by the layer-3 node their
+    descent reached and dealt to the XCDs; outputs and counters equal the
+    one-kernel form's bit for bit."""
+    _log("case sift_like 1M x 128, 20,000 queries, scheduled against one kernel")
+    p = hnsw.graphfile.read(FULL)
+    X = synthdata.base("sift_like", p["n"])
+    Q = synthdata.queries("sift_like", 20000)
+    idx = hnsw.Index(p, X)
+    q = torch.from_numpy(Q).cuda()
+    out = {}
+    for form in ("2", "0"):
+        monkeypatch.setenv("HNSW_SCHEDULE", form)
+        ids, ds, cnt = idx.search(q, 10, 56, counters=True)
+        torch.cuda.synchronize()
+        out[form] = (ids.cpu().numpy(), ds.cpu().numpy(), cnt.cpu().numpy())
+    for a, b in zip(out["2"], out["0"]):
+        assert np.array_equal(a, b)
+    assert ((out["2"][0] >= 0) & (out["2"][0] < p["n"])).all()
+    idx.close()
+
 def test_read_probe_reads_every_word(hnsw):
     """The bandwidth probe folds every 32-bit word it reads: the XOR of its
     per-block words equals the XOR of the buffer, for grids smaller and larger

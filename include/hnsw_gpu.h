@@ -187,13 +187,14 @@ hnsw_status hnsw_select_heuristic(const hnsw_index *index, const uint32_t *base,
  *   ef        size of the dynamic list W (Alg. 2); raised to k when smaller;
  *             above HNSW_EF_MAX returns HNSW_ERR_UNSUPPORTED.
  *   ids_out   device i32 [n][k];  dists_out  device fp32 [n][k].
- * A batch of more than 256 queries uses a device workspace of 20 bytes per
+ * A batch of more than 256 queries uses a device workspace of 24 bytes per
  * query (at least 1 MiB), one per (device, stream), allocated on first use,
  * grown to the largest batch seen on that stream and kept until the process
  * ends.  A batch larger than the waves the GPU holds at once can run as three
  * launches on `stream` (every descent, an ordering step, then layer 0 with the
- * queries whose descent ended farthest started first); results and counters
- * are those of the one-launch form.  Which form is faster depends on the data
+ * queries whose descent ended farthest started first, and queries whose
+ * descents passed through the same upper-layer node run together on one XCD);
+ * results and counters are those of the one-launch form.  Which form is faster depends on the data
  * (per-query cost spread), so for each (index, mode, ef, batch-size octave)
  * the library times two calls of each form, reading events back without
  * blocking, and then keeps the faster; until then it uses the three launches.
